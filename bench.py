@@ -1,0 +1,186 @@
+"""Throughput of the LIF + delayed delivery step on one MI355X.
+
+Workload: the 112,500-neuron balanced network with alpha-current LIF neurons,
+in-degree 9,000 E + 2,250 I (1.27e9 synapses), delays uniform on 5..30 steps,
+FP32, dt = 0.1 ms.  One benchmark step simulates 1 s (10,000 time steps) in
+one persistent launch; inputs (graph, state) are resident in HBM before the
+timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SIM_STEPS_PER_BENCH_STEP = 10000      # 1 s of biological time at dt = 0.1 ms
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
+    """The CPU oracle on a bounded sample of the same workload: every synapse
+    into `n_targets` sampled neurons, those neurons' updates, driven for
+    `n_steps` by a replayed raster of all sources at the measured rate."""
+    import oracle
+    import netspec
+    N = spec.n_neurons
+    sel = np.arange(0, N, N // n_targets)[:n_targets]
+    t0 = time.perf_counter()
+    o = oracle.OracleNet(spec, seed, sel=sel)
+    t_build = time.perf_counter() - t0
+    p = rate_hz * spec.dt * 1e-3
+    steps, ids = netspec.sparse_raster(N, n_steps, p, seed=seed + 100)
+    t0 = time.perf_counter()
+    o.run_frozen(steps, ids, n_steps, record_x=False, record_v=False)
+    t_run = time.perf_counter() - t0
+    ev = o.events
+    return {
+        "value": ev / t_run,
+        "unit": "synaptic events/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{len(sel)} of {N} targets with all {o.E} of their synapses, "
+                   f"{n_steps} steps of a replayed {rate_hz:.2f} Hz raster of all sources; "
+                   f"{ev:.3e} events in {t_run:.2f} s (graph build {t_build:.1f} s excluded)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sim-steps", type=int, default=SIM_STEPS_PER_BENCH_STEP)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--tile-size", type=int, default=0)
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-targets", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=4000)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import netspec
+    import paper_2406_03762_amd as cx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    spec = netspec.config2()
+    log("[bench] building config2 network")
+    t0 = time.perf_counter()
+    net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    E = net.E
+    B_rec = net.query("EDGE_BYTES")
+    n_tiles = net.query("TILES")
+    log(f"[bench] built: N={net.N} E={E} tiles={n_tiles} T={net.query('TILE_SIZE')} "
+        f"R={net.query('RING_SLOTS')} BS={net.query('BLOCK_SIZE')} rec={B_rec}B "
+        f"in {t_build:.1f}s")
+
+    for w in range(args.warmup):
+        net.step(args.sim_steps)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+
+    stream = torch.cuda.current_stream()
+    ev0 = net.query("EVENTS")
+    sp0 = net.query("SPIKES")
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        net.step(args.sim_steps)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev1 = net.query("EVENTS")
+    sp1 = net.query("SPIKES")
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    events = ev1 - ev0
+    spikes = sp1 - sp0
+    sim_s = args.steps * args.sim_steps * spec.dt * 1e-3
+    rate_hz = spikes / (net.N * sim_s)
+    ev_per_s = events / wall
+    avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
+    bytes_per_launch = events / args.steps * B_rec
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+    offset_bytes = spikes / args.steps * n_tiles * 8
+    log(f"[bench] timed {args.steps} x {args.sim_steps} steps: wall {wall:.3f}s, "
+        f"kernel avg {avg_kernel_s * 1e3:.2f} ms, rate {rate_hz:.2f} Hz, {ev_per_s:.3e} events/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(spec, rate_hz, args.seed, args.cpu_targets, args.cpu_steps)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} events/s")
+
+    out = {
+        "metric": "synaptic events/s (1 GPU)",
+        "value": ev_per_s,
+        "unit": "synaptic events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic (network and Poisson drive generated on device from Philox seeds)",
+        "config": {
+            "workload": "balanced random net, alpha-current LIF, 112,500 neurons (90,000 E / 22,500 I), "
+                        "in-degree 9,000 E + 2,250 I, 1.27e9 synapses, weights Normal(J, (0.1J)^2) "
+                        "as PSP peaks, delays uniform 0.5-3.0 ms, dt 0.1 ms, FP32; "
+                        f"one step = {args.sim_steps} time steps ({args.sim_steps * spec.dt:.0f} ms)",
+            "neurons": net.N,
+            "synapses": E,
+            "tiles": n_tiles,
+            "tile_size": net.query("TILE_SIZE"),
+            "block_size": net.query("BLOCK_SIZE"),
+            "record_bytes": B_rec,
+        },
+        "rtf": wall / sim_s,
+        "firing_rate_hz": rate_hz,
+        "events_per_launch": events / args.steps,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "step_kernel",
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "offset_bytes_per_launch": offset_bytes,
+            "avg_launch_ms": avg_kernel_s * 1e3,
+        },
+        "cpu_baseline": cpu,
+        "graph_build_s": t_build,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
+if __name__ == "__main__":
+    main()

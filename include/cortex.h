@@ -1,0 +1,225 @@
+/*
+ * cortex.h - C ABI of the MI355X (gfx950) LIF + delayed spike delivery
+ * library.
+ *
+ * The library simulates spiking networks of leaky integrate-and-fire neurons
+ * (Sec. I-A, Eq. 1-2 of Lyu et al., "CORTEX: Large-Scale Brain Simulator
+ * Utilizing Indegree Sub-Graph Decomposition on Fugaku Supercomputer") with
+ * current-based delta, exponential or alpha synapses (the current form of
+ * Eq. 3).  One time step follows the procedure of Sec. II-B: the synapses of
+ * neurons that spiked d steps ago act on their targets, then every neuron
+ * updates and emits new spikes.  Work is organised by the indegree sub-graph
+ * decomposition of Sec. II-A (Eq. 5, 9-14) and the thread ownership of
+ * Sec. III-B: the neurons are cut into tiles of consecutive targets, each tile
+ * owns all synapses into its targets, and exactly one GPU workgroup writes a
+ * tile's input buffers, so delivery needs no global atomics.
+ *
+ * Conventions for every entry point:
+ *  - return value: CORTEX_OK (0) or a negative cortex_status; the message of
+ *    the last failure on the calling thread is cortex_last_error();
+ *  - "device" pointers are GPU memory of the device current at
+ *    cortex_build_network; "host" pointers are CPU memory;
+ *  - pointers passed in stay owned by the caller; the network owns the device
+ *    memory it obtained from cortex_device.alloc and returns it through
+ *    cortex_device.free in cortex_destroy;
+ *  - work is enqueued on cortex_device.stream; calls documented as
+ *    "synchronising" wait for that stream;
+ *  - neurons are numbered globally: instance after instance, population after
+ *    population; spike times are step indices n (time (n+1)*dt);
+ *  - canonical synapse order is (target, projection, slot) ascending, where a
+ *    projection's slot is its draw index for that target.
+ */
+#ifndef CORTEX_H
+#define CORTEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CORTEX_ABI_VERSION 1
+
+typedef enum {
+    CORTEX_OK = 0,
+    CORTEX_EINVAL = -1,       /* invalid argument or specification */
+    CORTEX_ENOMEM = -2,       /* allocation failed */
+    CORTEX_EDEVICE = -3,      /* HIP runtime error */
+    CORTEX_ESTATE = -4,       /* call not valid in the network's state */
+    CORTEX_EUNSUPPORTED = -5, /* valid request this build cannot serve */
+    CORTEX_ETIMEOUT = -6,     /* a device-side wait exceeded its spin limit */
+    CORTEX_ETRUNC = -7        /* output truncated (buffer or log capacity) */
+} cortex_status;
+
+enum { CORTEX_MODEL_DELTA = 0, CORTEX_MODEL_EXP = 1, CORTEX_MODEL_ALPHA = 2 };
+enum { CORTEX_RULE_FIXED_INDEGREE = 0, CORTEX_RULE_PAIRWISE = 1 };
+enum { CORTEX_DELAY_CONST = 0, CORTEX_DELAY_UNIFORM_INT = 1, CORTEX_DELAY_NORMAL = 2 };
+enum { CORTEX_UNIT_NATIVE = 0, CORTEX_UNIT_PSP_MV = 1 };
+enum { CORTEX_FP32 = 0, CORTEX_FP64_VERIFY = 1 };
+enum { CORTEX_W_FP32 = 0, CORTEX_W_BF16 = 1 };
+
+/* A population: `size` consecutive neurons of instance `instance`.
+   Populations must be listed grouped by instance, instances ascending. */
+typedef struct {
+    int32_t instance;
+    int64_t size;
+} cortex_pop;
+
+/* All synapses from population src_pop onto population tgt_pop (indices into
+   the population list, same instance).
+   rule FIXED_INDEGREE: each target draws k sources uniformly with replacement
+   (no self-connection unless `autapses`); rule PAIRWISE: each (source,
+   target) pair connects with probability p.
+   Weight ~ Normal(w_mean, w_sd^2) clipped at 0 to keep the sign of w_mean
+   (constant if w_sd == 0), in the spec's weight unit.
+   Delay CONST: d0 ms; UNIFORM_INT: integer steps uniform on [d0, d1];
+   NORMAL: Normal(d0, d1^2) ms.  ms values round to the nearest step, at
+   least 1. */
+typedef struct {
+    int32_t src_pop, tgt_pop;
+    int32_t rule;
+    int64_t k;
+    double p;
+    double w_mean, w_sd;
+    int32_t delay_kind;
+    double d0, d1;
+    int32_t autapses;
+} cortex_proj;
+
+/* Network specification.  Units ms, mV, pF, pA.  Weights are mV jumps
+   (delta) or pA current amplitudes (exp: jump of the current; alpha: peak of
+   the current); with weight_unit PSP_MV they (and w_ext) are the PSP peak in
+   mV and the library converts them.  Each neuron receives a Poisson count
+   with mean poisson_lambda per step, each event of weight w_ext.  Initial
+   V ~ Uniform[v0_lo, v0_hi). */
+typedef struct {
+    uint32_t abi_version;     /* CORTEX_ABI_VERSION */
+    uint32_t struct_size;     /* sizeof(cortex_spec) */
+    int32_t model;            /* CORTEX_MODEL_* */
+    int32_t precision;        /* CORTEX_FP32 or CORTEX_FP64_VERIFY */
+    int32_t weight_dtype;     /* CORTEX_W_* (FP32 mode only) */
+    int32_t weight_unit;      /* CORTEX_UNIT_* */
+    double dt, tau_m, C_m, E_L, V_th, V_reset, t_ref, I_e, tau_syn;
+    double poisson_lambda, w_ext, v0_lo, v0_hi;
+    int32_t n_instances;
+    int32_t n_pops;
+    const cortex_pop* pops;   /* host, n_pops */
+    int32_t n_projs;
+    const cortex_proj* projs; /* host, n_projs */
+    int32_t tile_size;        /* targets per tile; 0 = automatic */
+    int32_t block_size;       /* threads per workgroup: 0 (auto), 256, 512, 1024 */
+    int64_t record_steps;     /* steps of spike log kept (0 = none) */
+    int32_t ckpt_every;       /* adjoint checkpoint interval in steps; 0 = no adjoint */
+    int64_t adjoint_steps;    /* longest forward window the adjoint covers */
+    int32_t spin_limit_log2;  /* device wait limit, 2^k polls (0 = default 22) */
+} cortex_spec;
+
+/* Device memory and stream supplied by the caller.  alloc returns device
+   memory of at least `bytes` bytes aligned to 256 (NULL on failure); free
+   releases it.  With alloc == NULL the library uses hipMalloc/hipFree.
+   stream is a hipStream_t (NULL = the null stream). */
+typedef struct {
+    void* stream;
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} cortex_device;
+
+typedef struct cortex_net cortex_net;
+
+/* Build a network from `spec` with Philox key (seed, instance): generates
+   every synapse on the device, lays the graph out in indegree tiles and sets
+   the initial state (step 0).  Synchronising.  *out receives the handle.
+   Errors: EINVAL (bad spec), ENOMEM, EDEVICE, EUNSUPPORTED (e.g. input rings
+   larger than the workgroup-local memory). */
+int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_device* dev,
+                         cortex_net** out);
+
+/* Advance the simulation by n_steps (closed loop: spikes from threshold
+   crossings).  Asynchronous on the network's stream.  FP32 networks run one
+   persistent launch; the spike log keeps steps inside the record window.
+   Errors: EINVAL (n_steps < 0), ESTATE (network failed earlier), EDEVICE,
+   ETIMEOUT (reported by the next synchronising call). */
+int cortex_step(cortex_net* net, int64_t n_steps);
+
+/* Spikes with step in [step0, step1) from the log, sorted by (step, id),
+   into host arrays of `capacity` entries; *count = number of spikes in the
+   range.  Returns ETRUNC if capacity < *count (the first `capacity` are
+   written) or if the range leaves the record window.  Synchronising. */
+int cortex_get_spikes(cortex_net* net, int64_t step0, int64_t step1, uint32_t* steps,
+                      uint32_t* ids, int64_t capacity, int64_t* count);
+
+/* Restart the spike log window at the current step. */
+int cortex_clear_spikes(cortex_net* net);
+
+/* Open loop with spikes frozen to a raster (host arrays, sorted by (step,
+   id), absolute steps): advance n_steps; a neuron spikes and resets exactly at
+   its raster entries, thresholds are not evaluated, and delivery uses the
+   raster.  Optional device traces [n_steps][N] (float in FP32 mode, double in
+   FP64 mode): x = synaptic input consumed at each step, v = membrane
+   potential after the step.  Synchronising. */
+int cortex_run_frozen(cortex_net* net, const uint32_t* r_steps, const uint32_t* r_ids,
+                      int64_t n_spikes, int64_t n_steps, void* x_trace, void* v_trace);
+
+/* Gradient of L = sum_b 1/(N_b T) sum_{i in b, n < T} (V_i(n) - V*_i(n))^2
+   over the T steps simulated since the build (or the last cortex_reset),
+   with every neuron's spikes frozen to the ones it emitted, with respect to
+   all stored synaptic weights (native units).  Requires spec.ckpt_every > 0
+   and T <= spec.adjoint_steps.  vstar: device float [T][N]; grad_w: device
+   float [E] in canonical synapse order (overwritten); *loss (host) gets L.
+   Synchronising.  Errors: ESTATE (adjoint not enabled / window too long). */
+int cortex_backward(cortex_net* net, const float* vstar, float* grad_w, double* loss);
+
+/* Back to the build-time state (step 0, empty input rings, empty log). */
+int cortex_reset(cortex_net* net);
+
+/* Neuron state into host arrays of N entries (V in mV; r = refractory steps
+   left; y1/y2 synaptic state as in the oracle: exp y1 = current; alpha y1 =
+   auxiliary, y2 = current); NULL skips an array.  Synchronising. */
+int cortex_get_state(cortex_net* net, double* V, int32_t* r, double* y1, double* y2);
+
+/* All synapses into host arrays of E entries, in the library's storage
+   order (grouped by source, then tile).  Global ids; delay in steps; weight
+   as stored, widened to double.  Synchronising. */
+int cortex_export_graph(cortex_net* net, int64_t* src, int64_t* tgt, double* w, int32_t* d);
+
+/* Canonical index of every stored synapse (host int64[E], storage order),
+   so export order can be mapped to canonical order. Synchronising. */
+int cortex_export_canonical(cortex_net* net, int64_t* canon);
+
+/* Tile table into host arrays of n_tiles entries: first global target,
+   number of targets, instance.  Synchronising. */
+int cortex_export_tiles(cortex_net* net, int64_t* start, int32_t* size, int32_t* instance);
+
+enum {
+    CORTEX_Q_NEURONS = 0,
+    CORTEX_Q_SYNAPSES = 1,
+    CORTEX_Q_MIN_DELAY = 2,
+    CORTEX_Q_MAX_DELAY = 3,
+    CORTEX_Q_TILES = 4,
+    CORTEX_Q_TILE_SIZE = 5,
+    CORTEX_Q_RING_SLOTS = 6,
+    CORTEX_Q_STEP = 7,            /* current step */
+    CORTEX_Q_EVENTS = 8,          /* synaptic events delivered since build/reset */
+    CORTEX_Q_SPIKES = 9,          /* spikes emitted since build/reset */
+    CORTEX_Q_DEVICE_BYTES = 10,   /* device memory held */
+    CORTEX_Q_EDGE_BYTES = 11,     /* bytes of one stored synapse record */
+    CORTEX_Q_BLOCK_SIZE = 12,
+    CORTEX_Q_LDS_BYTES = 13,      /* workgroup-local memory per workgroup */
+    CORTEX_Q_OFFSET_BYTES = 14    /* bytes of the per-(source, tile) offset table */
+};
+/* Scalar facts about the network into *value.  EVENTS and SPIKES
+   synchronise. */
+int cortex_query(cortex_net* net, int what, int64_t* value);
+
+/* Release the network and its device memory.  NULL is ignored. */
+void cortex_destroy(cortex_net* net);
+
+/* Message of the last failure on the calling thread (never NULL). */
+const char* cortex_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -286,6 +286,22 @@ def synthetic_raster(n_neurons: int, n_steps: int, p_spike: float, seed: int,
     return np.concatenate(steps_l), np.concatenate(ids_l)
 
 
+def sparse_raster(n_neurons: int, n_steps: int, p_spike: float, seed: int,
+                  step0: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """Like synthetic_raster for large, sparse rasters: per step a binomial
+    number of distinct neurons drawn uniformly."""
+    rng = np.random.default_rng(seed)
+    counts = rng.binomial(n_neurons, p_spike, size=n_steps)
+    steps_l, ids_l = [], []
+    for s, c in enumerate(counts):
+        if c:
+            ids_l.append(np.sort(rng.choice(n_neurons, size=int(c), replace=False)).astype(np.uint32))
+            steps_l.append(np.full(int(c), s + step0, np.uint32))
+    if not steps_l:
+        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    return np.concatenate(steps_l), np.concatenate(ids_l)
+
+
 def refractory_raster(n_neurons: int, n_steps: int, p_spike: float, seed: int,
                       n_ref: int) -> Tuple[np.ndarray, np.ndarray]:
     """Bernoulli raster thinned so no neuron spikes again within ``n_ref``

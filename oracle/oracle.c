@@ -706,6 +706,9 @@ static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t
         while (q < nspk && st[q] == step) q++;
         int64_t qs = q0;
         for (int64_t i = 0; i < n->N; ++i) {
+            /* with a target selection only the selected neurons are simulated;
+               the others merely emit the raster's spikes */
+            if (n->sel && n->col_of[i] < 0) continue;
             double x = n->ring[i * n->D + slot];
             n->ring[i * n->D + slot] = 0.0;
             int kc = poisson_count(n, i, step);

@@ -1,0 +1,352 @@
+"""Python binding of libcortex (MI355X LIF + delayed spike delivery).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libcortex.so.  PyTorch supplies device memory (its caching
+allocator, through the allocator callbacks of ``cortex_device``) and the
+stream (the current torch stream).  The functions keep the C names;
+``Network`` wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcortex.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cortex.h")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
+Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
+         STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
+         OFFSET_BYTES=14)
+
+
+class CortexError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cortex status {status}: {msg}")
+        self.status = status
+
+
+class cortex_pop(C.Structure):
+    _fields_ = [("instance", C.c_int32), ("size", C.c_int64)]
+
+
+class cortex_proj(C.Structure):
+    _fields_ = [("src_pop", C.c_int32), ("tgt_pop", C.c_int32), ("rule", C.c_int32),
+                ("k", C.c_int64), ("p", C.c_double), ("w_mean", C.c_double), ("w_sd", C.c_double),
+                ("delay_kind", C.c_int32), ("d0", C.c_double), ("d1", C.c_double),
+                ("autapses", C.c_int32)]
+
+
+class cortex_spec(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("struct_size", C.c_uint32), ("model", C.c_int32),
+                ("precision", C.c_int32), ("weight_dtype", C.c_int32), ("weight_unit", C.c_int32),
+                ("dt", C.c_double), ("tau_m", C.c_double), ("C_m", C.c_double), ("E_L", C.c_double),
+                ("V_th", C.c_double), ("V_reset", C.c_double), ("t_ref", C.c_double),
+                ("I_e", C.c_double), ("tau_syn", C.c_double), ("poisson_lambda", C.c_double),
+                ("w_ext", C.c_double), ("v0_lo", C.c_double), ("v0_hi", C.c_double),
+                ("n_instances", C.c_int32), ("n_pops", C.c_int32), ("pops", C.POINTER(cortex_pop)),
+                ("n_projs", C.c_int32), ("projs", C.POINTER(cortex_proj)),
+                ("tile_size", C.c_int32), ("block_size", C.c_int32), ("record_steps", C.c_int64),
+                ("ckpt_every", C.c_int32), ("adjoint_steps", C.c_int64),
+                ("spin_limit_log2", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class cortex_device(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libcortex.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcortex.so not built ({LIB_PATH}); run "
+                               "python -m paper_2406_03762_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i64 = C.c_int64
+        L.cortex_last_error.restype = C.c_char_p
+        L.cortex_build_network.argtypes = [C.POINTER(cortex_spec), C.c_uint64, C.POINTER(cortex_device),
+                                           C.POINTER(P)]
+        L.cortex_step.argtypes = [P, i64]
+        L.cortex_get_spikes.argtypes = [P, i64, i64, P, P, i64, C.POINTER(i64)]
+        L.cortex_clear_spikes.argtypes = [P]
+        L.cortex_run_frozen.argtypes = [P, P, P, i64, i64, P, P]
+        L.cortex_backward.argtypes = [P, P, P, C.POINTER(C.c_double)]
+        L.cortex_reset.argtypes = [P]
+        L.cortex_get_state.argtypes = [P, P, P, P, P]
+        L.cortex_export_graph.argtypes = [P, P, P, P, P]
+        L.cortex_export_canonical.argtypes = [P, P]
+        L.cortex_export_tiles.argtypes = [P, P, P, P]
+        L.cortex_query.argtypes = [P, C.c_int, C.POINTER(i64)]
+        L.cortex_destroy.argtypes = [P]
+        L.cortex_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise CortexError(rc, lib().cortex_last_error().decode())
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+_MODEL = {"delta": 0, "exp": 1, "alpha": 2}
+_RULE = {"fixed_indegree": 0, "pairwise": 1}
+_DELAY = {"const": 0, "uniform_int": 1, "normal": 2}
+_UNIT = {"native": 0, "psp_mV": 1}
+
+
+def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 0,
+              ckpt_every: int = 0, adjoint_steps: int = 0, spin_limit_log2: int = 0):
+    """Marshal a network description (netspec.NetSpec) into cortex_spec.
+
+    Returns (spec, keepalive)."""
+    pops, projs = [], []
+    for b, inst in enumerate(net.instances):
+        base = len(pops)
+        for p in inst.pops:
+            pops.append(cortex_pop(b, p.size))
+        for pr in inst.projs:
+            projs.append(cortex_proj(base + pr.src, base + pr.tgt, _RULE[pr.rule], pr.k, pr.p,
+                                     pr.w_mean, pr.w_sd, _DELAY[pr.delay], pr.d0, pr.d1,
+                                     int(pr.autapses)))
+    pa = (cortex_pop * max(1, len(pops)))(*pops)
+    qa = (cortex_proj * max(1, len(projs)))(*projs)
+    s = cortex_spec()
+    s.abi_version = ABI_VERSION
+    s.struct_size = C.sizeof(cortex_spec)
+    s.model = _MODEL[net.model]
+    s.precision = 1 if net.precision == "fp64" else 0
+    s.weight_dtype = 1 if net.weight_dtype == "bf16" else 0
+    s.weight_unit = _UNIT[net.weight_unit]
+    for f in ("dt", "tau_m", "C_m", "E_L", "V_th", "V_reset", "t_ref", "I_e", "tau_syn",
+              "poisson_lambda", "w_ext", "v0_lo", "v0_hi"):
+        setattr(s, f, getattr(net, f))
+    s.n_instances = len(net.instances)
+    s.n_pops = len(pops)
+    s.pops = pa
+    s.n_projs = len(projs)
+    s.projs = qa
+    s.tile_size = tile_size
+    s.block_size = block_size
+    s.record_steps = record_steps
+    s.ckpt_every = ckpt_every
+    s.adjoint_steps = adjoint_steps
+    s.spin_limit_log2 = spin_limit_log2
+    return s, (pa, qa)
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator for cortex_device."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+def cortex_build_network(net, seed: int, device=None, stream=None, **plan):
+    """Build on the current torch device/stream; returns (handle, keepalive)."""
+    import torch
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    torch.cuda.set_device(device)
+    alloc = _TorchAllocator(device)
+    st = torch.cuda.current_stream(device) if stream is None else stream
+    dev = cortex_device(C.c_void_p(st.cuda_stream), alloc.alloc_fn, alloc.free_fn, None)
+    spec, keep = make_spec(net, **plan)
+    h = C.c_void_p()
+    _check(lib().cortex_build_network(C.byref(spec), seed, C.byref(dev), C.byref(h)))
+    return h, (alloc, keep, dev, st)
+
+
+def cortex_step(h, n_steps: int) -> None:
+    _check(lib().cortex_step(h, n_steps))
+
+
+def cortex_query(h, what: str) -> int:
+    v = C.c_int64()
+    _check(lib().cortex_query(h, Q[what], C.byref(v)))
+    return v.value
+
+
+def cortex_get_spikes(h, step0: int, step1: int):
+    cnt = C.c_int64()
+    rc = lib().cortex_get_spikes(h, step0, step1, None, None, 0, C.byref(cnt))
+    if rc not in (OK, ETRUNC):
+        _check(rc)
+    n = cnt.value
+    st = np.zeros(max(1, n), np.uint32)
+    ids = np.zeros(max(1, n), np.uint32)
+    _check(lib().cortex_get_spikes(h, step0, step1, st.ctypes.data, ids.ctypes.data, n, C.byref(cnt)))
+    return st[:n], ids[:n]
+
+
+def cortex_run_frozen(h, steps, ids, n_steps: int, x_trace=None, v_trace=None) -> None:
+    st = np.ascontiguousarray(steps, np.uint32)
+    ii = np.ascontiguousarray(ids, np.uint32)
+    _check(lib().cortex_run_frozen(h, st.ctypes.data if len(st) else None,
+                                   ii.ctypes.data if len(ii) else None, len(st), n_steps,
+                                   _ptr(x_trace), _ptr(v_trace)))
+
+
+def cortex_backward(h, vstar, grad_w) -> float:
+    loss = C.c_double()
+    _check(lib().cortex_backward(h, _ptr(vstar), _ptr(grad_w), C.byref(loss)))
+    return loss.value
+
+
+def cortex_reset(h) -> None:
+    _check(lib().cortex_reset(h))
+
+
+def cortex_clear_spikes(h) -> None:
+    _check(lib().cortex_clear_spikes(h))
+
+
+def cortex_get_state(h, N: int):
+    V = np.zeros(N)
+    r = np.zeros(N, np.int32)
+    y1 = np.zeros(N)
+    y2 = np.zeros(N)
+    _check(lib().cortex_get_state(h, V.ctypes.data, r.ctypes.data, y1.ctypes.data, y2.ctypes.data))
+    return V, r, y1, y2
+
+
+def cortex_export_graph(h, E: int):
+    src = np.zeros(E, np.int64)
+    tgt = np.zeros(E, np.int64)
+    w = np.zeros(E, np.float64)
+    d = np.zeros(E, np.int32)
+    _check(lib().cortex_export_graph(h, src.ctypes.data, tgt.ctypes.data, w.ctypes.data, d.ctypes.data))
+    return src, tgt, w, d
+
+
+def cortex_export_canonical(h, E: int):
+    c = np.zeros(E, np.int64)
+    _check(lib().cortex_export_canonical(h, c.ctypes.data))
+    return c
+
+
+def cortex_export_tiles(h, n_tiles: int):
+    s = np.zeros(n_tiles, np.int64)
+    z = np.zeros(n_tiles, np.int32)
+    b = np.zeros(n_tiles, np.int32)
+    _check(lib().cortex_export_tiles(h, s.ctypes.data, z.ctypes.data, b.ctypes.data))
+    return s, z, b
+
+
+def cortex_destroy(h) -> None:
+    lib().cortex_destroy(h)
+
+
+class Network:
+    """A network living on one GPU (convenience wrapper over the C calls)."""
+
+    def __init__(self, net, seed: int, **plan):
+        import torch
+        self.spec = net
+        self._h, self._keep = cortex_build_network(net, seed, **plan)
+        self.N = cortex_query(self._h, "NEURONS")
+        self.E = cortex_query(self._h, "SYNAPSES")
+        self.fp64 = net.precision == "fp64"
+        self.torch = torch
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            cortex_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, what: str) -> int:
+        return cortex_query(self._h, what)
+
+    def step(self, n_steps: int) -> None:
+        cortex_step(self._h, n_steps)
+
+    def spikes(self, step0: int = 0, step1: Optional[int] = None):
+        if step1 is None:
+            step1 = self.query("STEP")
+        return cortex_get_spikes(self._h, step0, step1)
+
+    def run_frozen(self, steps, ids, n_steps: int, traces: bool = True):
+        """Frozen-raster run; returns (x, v) device tensors [n_steps, N] or None."""
+        if not traces:
+            cortex_run_frozen(self._h, steps, ids, n_steps)
+            return None, None
+        dt = self.torch.float64 if self.fp64 else self.torch.float32
+        x = self.torch.empty((n_steps, self.N), dtype=dt, device="cuda")
+        v = self.torch.empty((n_steps, self.N), dtype=dt, device="cuda")
+        cortex_run_frozen(self._h, steps, ids, n_steps, x, v)
+        return x, v
+
+    def backward(self, vstar, grad=None):
+        if grad is None:
+            grad = self.torch.empty(self.E, dtype=self.torch.float32, device="cuda")
+        loss = cortex_backward(self._h, vstar, grad)
+        return grad, loss
+
+    def reset(self) -> None:
+        cortex_reset(self._h)
+
+    def clear_spikes(self) -> None:
+        cortex_clear_spikes(self._h)
+
+    def state(self):
+        return cortex_get_state(self._h, self.N)
+
+    def graph(self):
+        return cortex_export_graph(self._h, self.E)
+
+    def canonical(self):
+        return cortex_export_canonical(self._h, self.E)
+
+    def tiles(self):
+        return cortex_export_tiles(self._h, self.query("TILES"))
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/cortex.h."""
+    import re
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cortex_[a-z_]+)\s*\(", txt)))

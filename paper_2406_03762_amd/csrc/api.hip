@@ -1,0 +1,903 @@
+// Host side of libcortex: specification checks, model constants, planning of
+// the indegree tiles, device memory, and the extern "C" entry points.
+//
+// This file is compiled with -ffp-contract=off: the FP64 model constants
+// follow the documented recipe operation by operation.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cortex {
+
+namespace {
+thread_local std::string g_error = "";
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+// ----------------------------------------------------------------------------
+// Model constants.  The membrane equation tau dU/dt = -U + R I (Eq. 1, with
+// U = u - u_rest and R = tau/C) is linear between spikes, so one step of
+// length dt is the exact linear map exp(A dt) of the (U, synaptic state)
+// system:
+//   P22 = e^{-dt/tm}                        U <- P22 U
+//   P20 = (tm/C)(1 - e^{-dt/tm})            constant current I_e
+//   exp kernel, a = 1/ts - 1/tm:
+//   P11 = e^{-dt/ts}                        I <- P11 I
+//   P21 = P22 (1 - e^{-a dt}) / (C a)       U gains P21 I
+//   alpha kernel (y1 auxiliary, y2 current):
+//   P21s = dt P11, P22s = P11               y2 <- P21s y1 + P22s y2
+//   P31 = P22 (1 - e^{-a dt}(1 + a dt)) / (C a^2)   U gains P31 y1 + P32 y2
+//   P32 = P21;  an input w adds (e/ts) w to y1 (current peaks at w).
+// The expressions below are the shared recipe (same operations as the CPU
+// reference), so FP64 networks reproduce its rounding exactly.
+Consts model_constants(const cortex_spec& s) {
+    Consts k{};
+    const double dt = s.dt, tm = s.tau_m, ts = s.tau_syn, C = s.C_m;
+    k.P22 = std::exp(-dt / tm);
+    k.P20 = -(tm / C) * std::expm1(-dt / tm);
+    k.jump = 1.0;
+    k.conv = 1.0;
+    if (s.model != CORTEX_MODEL_DELTA) {
+        const double a = 1.0 / ts - 1.0 / tm;
+        k.P11 = std::exp(-dt / ts);
+        k.P21 = (a == 0.0) ? k.P22 * dt / C : k.P22 * (-std::expm1(-a * dt)) / (C * a);
+        if (s.model == CORTEX_MODEL_ALPHA) {
+            k.P21s = dt * k.P11;
+            k.P22s = k.P11;
+            k.P32 = k.P21;
+            k.P31 = (a == 0.0) ? k.P22 * dt * dt / (2.0 * C)
+                               : k.P22 * (1.0 - std::exp(-a * dt) * (1.0 + a * dt)) / (C * a * a);
+            k.jump = 2.71828182845904523536 / ts;
+        }
+        if (s.weight_unit == CORTEX_UNIT_PSP_MV) {
+            // PSP of a unit input: v(t) = (1/C) int_0^t e^{-(t-s)/tm} I(s) ds with
+            // I(s) = e^{-s/ts} (exp) or (s/ts) e^{1-s/ts} (alpha); its maximum is
+            // where v'(t) = I(t)/C - v(t)/tm = 0.  Newton on v' from a bracket.
+            auto v = [&](double t) {
+                if (s.model == CORTEX_MODEL_EXP)
+                    return (a == 0.0) ? std::exp(-t / tm) * t / C
+                                      : std::exp(-t / tm) * (-std::expm1(-a * t)) / (C * a);
+                const double g = (a == 0.0) ? t * t / 2.0
+                                            : (1.0 - std::exp(-a * t) * (1.0 + a * t)) / (a * a);
+                return (2.71828182845904523536 / (C * ts)) * std::exp(-t / tm) * g;
+            };
+            auto cur = [&](double t) {
+                return s.model == CORTEX_MODEL_EXP ? std::exp(-t / ts)
+                                                   : (t / ts) * std::exp(1.0 - t / ts);
+            };
+            auto dv = [&](double t) { return cur(t) / C - v(t) / tm; };
+            double lo = 1e-9 * std::min(ts, tm), hi = 50.0 * std::max(ts, tm);
+            for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                (dv(mid) > 0.0 ? lo : hi) = mid;
+            }
+            double t = 0.5 * (lo + hi);
+            for (int it = 0; it < 5; ++it) {   // polish with secant steps on v'
+                const double h = 1e-7 * t;
+                const double d1 = dv(t), d2 = (dv(t + h) - dv(t - h)) / (2.0 * h);
+                if (d2 == 0.0) break;
+                const double tn = t - d1 / d2;
+                if (!(tn > 0.0)) break;
+                t = tn;
+            }
+            k.conv = 1.0 / v(t);
+        }
+    }
+    k.n_ref = (int)std::floor(s.t_ref / dt + 0.5);
+    if (k.n_ref < 0) k.n_ref = 0;
+    return k;
+}
+
+// Poisson counts by inversion: count = #{m : u >= thr[m]} for a uniform
+// 32-bit u, with thr[m] = floor(F(m) 2^32) while that is below 2^32 - 1
+// (the omitted tail is below 2^-32); F accumulated as p_m = p_{m-1} l / m.
+int poisson_thresholds(double lambda, uint32_t* thr, int cap) {
+    if (lambda == 0.0) return 0;
+    double p = std::exp(-lambda);
+    double F = p;
+    int m = 0;
+    for (; m < cap; ) {
+        const double t = F * 4294967296.0;
+        if (t >= 4294967295.0) break;
+        thr[m] = (uint32_t)t;
+        ++m;
+        p = p * lambda / (double)m;
+        F = F + p;
+    }
+    return m < cap ? m : -1;
+}
+
+// ----------------------------------------------------------------------------
+// Device memory through the caller's allocator.
+void* dev_alloc(cortex_net* n, size_t bytes, bool scratch) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (n->dev.alloc) {
+        p = n->dev.alloc(bytes, n->dev.user);
+        require(p != nullptr, CORTEX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    } else {
+        const hipError_t e = hipMalloc(&p, bytes);
+        require(e == hipSuccess && p, CORTEX_ENOMEM,
+                "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    (scratch ? n->scratch : n->bufs).push_back(DevBuf{p, bytes});
+    n->dev_bytes += scratch ? 0 : bytes;
+    return p;
+}
+
+static void release(cortex_net* n, std::vector<DevBuf>& v) {
+    for (auto& b : v) {
+        if (!b.p) continue;
+        if (n->dev.alloc) {
+            if (n->dev.free) n->dev.free(b.p, n->dev.user);
+        } else {
+            (void)hipFree(b.p);
+        }
+    }
+    v.clear();
+}
+
+void free_scratch(cortex_net* n) {
+    (void)hipStreamSynchronize(n->stream);
+    release(n, n->scratch);
+}
+
+void dev_zero(cortex_net* n, void* p, size_t bytes) {
+    if (bytes) CX_HIP(hipMemsetAsync(p, 0, bytes, n->stream));
+}
+
+template <class T>
+static void upload(cortex_net* n, T* dst, const std::vector<T>& src) {
+    if (!src.empty())
+        CX_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, n->stream));
+}
+
+template <class T>
+static std::vector<T> download(cortex_net* n, const T* src, size_t count) {
+    std::vector<T> v(count);
+    if (count) CX_HIP(hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, n->stream));
+    CX_HIP(hipStreamSynchronize(n->stream));
+    return v;
+}
+
+// ----------------------------------------------------------------------------
+static int32_t steps_of_ms(double ms, double dt) {
+    const double x = ms / dt + 0.5;
+    const double f = std::floor(x);
+    if (f < 1.0) return 1;
+    if (f > 1e9) return 1000000000;
+    return (int32_t)f;
+}
+
+static void validate(const cortex_spec* s) {
+    require(s != nullptr, CORTEX_EINVAL, "spec is NULL");
+    require(s->abi_version == CORTEX_ABI_VERSION, CORTEX_EINVAL, "spec ABI version mismatch");
+    require(s->struct_size == sizeof(cortex_spec), CORTEX_EINVAL, "spec struct size mismatch");
+    require(s->model >= 0 && s->model <= 2, CORTEX_EINVAL, "unknown neuron model");
+    require(s->precision == CORTEX_FP32 || s->precision == CORTEX_FP64_VERIFY, CORTEX_EINVAL, "unknown precision");
+    require(s->weight_dtype == CORTEX_W_FP32 || s->weight_dtype == CORTEX_W_BF16, CORTEX_EINVAL, "unknown weight dtype");
+    require(s->weight_unit == CORTEX_UNIT_NATIVE || s->weight_unit == CORTEX_UNIT_PSP_MV, CORTEX_EINVAL, "unknown weight unit");
+    require(s->dt > 0 && s->tau_m > 0 && s->C_m > 0, CORTEX_EINVAL, "dt, tau_m and C_m must be positive");
+    require(s->model == CORTEX_MODEL_DELTA || s->tau_syn > 0, CORTEX_EINVAL, "tau_syn must be positive");
+    require(s->V_reset < s->V_th, CORTEX_EINVAL, "V_reset must lie below V_th");
+    require(s->t_ref >= 0, CORTEX_EINVAL, "t_ref must be >= 0");
+    require(s->poisson_lambda >= 0 && s->poisson_lambda <= 50, CORTEX_EINVAL, "poisson_lambda must be in [0, 50]");
+    require(s->n_instances >= 1 && s->n_pops >= 1 && s->pops, CORTEX_EINVAL, "need instances and populations");
+    require(s->block_size == 0 || s->block_size == 256 || s->block_size == 512 || s->block_size == 1024,
+            CORTEX_EINVAL, "block_size must be 0, 256, 512 or 1024");
+    require(s->tile_size >= 0 && s->record_steps >= 0 && s->ckpt_every >= 0 && s->adjoint_steps >= 0 &&
+                s->spin_limit_log2 >= 0 && s->spin_limit_log2 <= 40,
+            CORTEX_EINVAL, "negative planning field");
+    require(s->n_projs >= 0 && (s->n_projs == 0 || s->projs), CORTEX_EINVAL, "projection list is NULL");
+    int prev = 0;
+    std::vector<int> seen(s->n_instances, 0);
+    int64_t N = 0;
+    for (int p = 0; p < s->n_pops; ++p) {
+        const cortex_pop& P = s->pops[p];
+        require(P.instance >= 0 && P.instance < s->n_instances && P.instance >= prev, CORTEX_EINVAL,
+                "populations must be grouped by instance in ascending order");
+        require(P.size >= 1, CORTEX_EINVAL, "population size must be >= 1");
+        prev = P.instance;
+        seen[P.instance] = 1;
+        N += P.size;
+    }
+    for (int b = 0; b < s->n_instances; ++b) require(seen[b], CORTEX_EINVAL, "instance without population");
+    require(N < ((int64_t)1 << 31), CORTEX_EUNSUPPORTED, "at most 2^31 - 1 neurons");
+    for (int q = 0; q < s->n_projs; ++q) {
+        const cortex_proj& R = s->projs[q];
+        require(R.src_pop >= 0 && R.src_pop < s->n_pops && R.tgt_pop >= 0 && R.tgt_pop < s->n_pops,
+                CORTEX_EINVAL, "projection population index out of range");
+        require(s->pops[R.src_pop].instance == s->pops[R.tgt_pop].instance, CORTEX_EINVAL,
+                "projection crosses instances");
+        require(R.rule == CORTEX_RULE_FIXED_INDEGREE || R.rule == CORTEX_RULE_PAIRWISE, CORTEX_EINVAL, "unknown rule");
+        require(R.rule != CORTEX_RULE_FIXED_INDEGREE || (R.k >= 0 && R.k < (1 << 30)), CORTEX_EINVAL, "bad in-degree");
+        require(R.rule != CORTEX_RULE_PAIRWISE || (R.p >= 0 && R.p <= 1), CORTEX_EINVAL, "p outside [0, 1]");
+        require(R.delay_kind >= 0 && R.delay_kind <= 2, CORTEX_EINVAL, "unknown delay kind");
+        require(R.delay_kind != CORTEX_DELAY_UNIFORM_INT || (R.d0 >= 1 && R.d1 >= R.d0 && R.d1 < 65535),
+                CORTEX_EINVAL, "uniform delay needs 1 <= lo <= hi steps");
+        require(R.w_sd >= 0 && std::isfinite(R.w_mean), CORTEX_EINVAL, "bad weight distribution");
+        const bool same = R.src_pop == R.tgt_pop && !R.autapses;
+        require(!(same && R.rule == CORTEX_RULE_FIXED_INDEGREE && R.k > 0 && s->pops[R.src_pop].size < 2),
+                CORTEX_EINVAL, "no source left without autapses");
+    }
+}
+
+// Generation blocks in canonical order and instance tables.
+static void make_blocks(cortex_net* n) {
+    const cortex_spec& s = n->spec;
+    std::vector<int64_t> pop_g0(n->pops.size() + 1, 0);
+    for (size_t p = 0; p < n->pops.size(); ++p) pop_g0[p + 1] = pop_g0[p] + n->pops[p].size;
+    n->N = pop_g0.back();
+    n->n_inst = s.n_instances;
+    n->inst_n0.assign(n->n_inst, 0);
+    n->inst_N.assign(n->n_inst, 0);
+    for (int b = n->n_inst - 1, p = (int)n->pops.size() - 1; b >= 0; --b) {
+        while (p >= 0 && n->pops[p].instance == b) {
+            n->inst_n0[b] = pop_g0[p];
+            n->inst_N[b] += n->pops[p].size;
+            --p;
+        }
+    }
+    std::vector<int32_t> proj_local(n->projs.size(), 0);
+    std::vector<int> count(n->n_inst, 0);
+    for (size_t q = 0; q < n->projs.size(); ++q) {
+        const int b = n->pops[n->projs[q].tgt_pop].instance;
+        proj_local[q] = count[b]++;
+    }
+    n->blocks.clear();
+    for (size_t p = 0; p < n->pops.size(); ++p) {
+        const int b = n->pops[p].instance;
+        for (size_t q = 0; q < n->projs.size(); ++q) {
+            const cortex_proj& R = n->projs[q];
+            if (R.tgt_pop != (int32_t)p) continue;
+            GenBlock B{};
+            B.tgt0 = pop_g0[p];
+            B.n_tgt = n->pops[p].size;
+            B.inst_n0 = n->inst_n0[b];
+            B.src0_local = pop_g0[R.src_pop] - n->inst_n0[b];
+            B.n_src = n->pops[R.src_pop].size;
+            B.k = R.rule == CORTEX_RULE_FIXED_INDEGREE ? R.k : 0;
+            B.all_pairs = R.rule == CORTEX_RULE_PAIRWISE && R.p >= 1.0;
+            B.thr_p = (R.rule == CORTEX_RULE_PAIRWISE && R.p < 1.0) ? (uint64_t)std::ldexp(R.p, 64) : ~0ull;
+            B.w_mean = R.w_mean;
+            B.w_sd = R.w_sd;
+            B.d0 = R.d0;
+            B.d1 = R.d1;
+            B.rule = R.rule;
+            B.delay_kind = R.delay_kind;
+            B.same_pop_no_autapse = (R.src_pop == R.tgt_pop && !R.autapses) ? 1 : 0;
+            B.proj_local = proj_local[q];
+            B.instance = b;
+            const bool empty = (R.rule == CORTEX_RULE_FIXED_INDEGREE && R.k == 0) ||
+                               (R.rule == CORTEX_RULE_PAIRWISE && R.p <= 0.0);
+            if (!empty) n->blocks.push_back(B);
+        }
+    }
+}
+
+// Delay range known from the specification (normal delays need a device pass).
+static bool host_delay_range(const cortex_net* n, int* dmin, int* dmax) {
+    int lo = 1 << 30, hi = 0;
+    for (const auto& B : n->blocks) {
+        if (B.delay_kind == CORTEX_DELAY_NORMAL) return false;
+        int a, b;
+        if (B.delay_kind == CORTEX_DELAY_CONST) {
+            a = b = steps_of_ms(B.d0, n->spec.dt);
+        } else {
+            a = (int)B.d0;
+            b = (int)B.d1;
+        }
+        lo = std::min(lo, a);
+        hi = std::max(hi, b);
+    }
+    if (hi == 0) lo = hi = 1;
+    *dmin = lo;
+    *dmax = hi;
+    return true;
+}
+
+static int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Tile size: the fewest, largest tiles whose input rings fit the
+// workgroup-local memory, with every tile's workgroup resident at once.
+static void plan_tiles(cortex_net* n) {
+    hipDeviceProp_t prop;
+    CX_HIP(hipGetDeviceProperties(&prop, n->device));
+    const int n_cu = prop.multiProcessorCount;
+    const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+    const int thr_cu = prop.maxThreadsPerMultiProcessor ? prop.maxThreadsPerMultiProcessor : 2048;
+    const int64_t maxN = *std::max_element(n->inst_N.begin(), n->inst_N.end());
+    auto tiles_for = [&](int64_t T) {
+        int64_t t = 0;
+        for (int64_t Nb : n->inst_N) t += (Nb + T - 1) / T;
+        return t;
+    };
+    auto ntb_max_for = [&](int64_t T) { return (int)((maxN + T - 1) / T); };
+    int T = n->spec.tile_size;
+    int BS = n->spec.block_size;
+    require(BS == 0 || BS == 256 || BS == 512 || BS == 1024, CORTEX_EINVAL, "block_size must be 0, 256, 512 or 1024");
+    if (T <= 0) {
+        bool found = false;
+        for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
+            const int64_t cap = (int64_t)n_cu * per_cu;
+            int64_t lo = 1, hi = std::max<int64_t>(1, maxN);
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                if (tiles_for(mid) <= cap) hi = mid; else lo = mid + 1;
+            }
+            const int t = (int)lo;
+            const int bs = BS ? BS : (t > 1024 ? 1024 : (t > 256 ? 512 : 256));
+            const size_t lds = step_lds_bytes(n->R, t, bs, ntb_max_for(t));
+            if (t <= 4 * bs && lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
+                T = t;
+                BS = bs;
+                found = true;
+            }
+        }
+        require(found, CORTEX_EUNSUPPORTED,
+                "network too large for workgroup-local input rings on this device");
+    }
+    if (BS == 0) BS = T > 1024 ? 1024 : (T > 256 ? 512 : 256);
+    require(T <= 4 * BS, CORTEX_EINVAL, "tile_size larger than 4 x block_size");
+    n->T = T;
+    n->BS = BS;
+    n->NPT = (T + BS - 1) / BS;
+    if (n->NPT == 3) n->NPT = 4;
+    n->n_tiles = 0;
+    n->inst_tile0.assign(n->n_inst, 0);
+    n->inst_ntiles.assign(n->n_inst, 0);
+    n->inst_offbase.assign(n->n_inst, 0);
+    n->tile_start.clear();
+    n->tile_size.clear();
+    n->tile_inst.clear();
+    uint64_t off = 0;
+    for (int b = 0; b < n->n_inst; ++b) {
+        const int nt = (int)((n->inst_N[b] + T - 1) / T);
+        n->inst_tile0[b] = n->n_tiles;
+        n->inst_ntiles[b] = nt;
+        n->inst_offbase[b] = off;
+        off += (uint64_t)n->inst_N[b] * (nt + 1);
+        for (int t = 0; t < nt; ++t) {
+            n->tile_start.push_back(n->inst_n0[b] + (int64_t)t * T);
+            n->tile_size.push_back((int32_t)std::min<int64_t>(T, n->inst_N[b] - (int64_t)t * T));
+            n->tile_inst.push_back(b);
+        }
+        n->n_tiles += nt;
+    }
+    n->lds_bytes = step_lds_bytes(n->R, T, BS, ntb_max_for(T));
+    require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
+    n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
+}
+
+static void upload_tables_fp32(cortex_net* n) {
+    n->d_tile_start = dev_alloc_t<int64_t>(n, n->n_tiles);
+    n->d_tile_size = dev_alloc_t<int32_t>(n, n->n_tiles);
+    n->d_tile_inst = dev_alloc_t<int32_t>(n, n->n_tiles);
+    n->d_inst_tile0 = dev_alloc_t<int32_t>(n, n->n_inst);
+    n->d_inst_ntiles = dev_alloc_t<int32_t>(n, n->n_inst);
+    n->d_inst_offbase = dev_alloc_t<uint64_t>(n, n->n_inst);
+    upload(n, n->d_tile_start, n->tile_start);
+    upload(n, n->d_tile_size, n->tile_size);
+    upload(n, n->d_tile_inst, n->tile_inst);
+    upload(n, n->d_inst_tile0, n->inst_tile0);
+    upload(n, n->d_inst_ntiles, n->inst_ntiles);
+    upload(n, n->d_inst_offbase, n->inst_offbase);
+}
+
+static void alloc_state_fp32(cortex_net* n) {
+    const int64_t N = n->N;
+    n->d_U = dev_alloc_t<float>(n, N);
+    n->d_U0 = dev_alloc_t<float>(n, N);
+    n->d_y1 = dev_alloc_t<float>(n, N);
+    n->d_y2 = dev_alloc_t<float>(n, N);
+    n->d_r = dev_alloc_t<int32_t>(n, N);
+    n->d_ring = dev_alloc_t<float>(n, (size_t)n->n_tiles * n->R * n->T);
+    n->d_spk_ids = dev_alloc_t<uint32_t>(n, (size_t)n->H * N);
+    n->d_spk_rec = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles);
+    n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
+    n->d_log_cnt = dev_alloc_t<uint32_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles);
+    std::vector<uint64_t> base(n->n_tiles + 1, 0);
+    const int64_t per = (n->log_steps + n->k.n_ref) / (n->k.n_ref + 1);
+    for (int t = 0; t < n->n_tiles; ++t) base[t + 1] = base[t] + (uint64_t)n->tile_size[t] * per;
+    n->d_log_base = dev_alloc_t<uint64_t>(n, n->n_tiles + 1);
+    upload(n, n->d_log_base, base);
+    n->d_log_ids = dev_alloc_t<uint32_t>(n, std::max<uint64_t>(1, base.back()));
+    n->d_log_pos = dev_alloc_t<uint64_t>(n, n->n_tiles);
+    n->d_events = dev_alloc_t<uint64_t>(n, n->n_tiles);
+    n->d_spikes = dev_alloc_t<uint64_t>(n, n->n_tiles);
+    n->d_err = dev_alloc_t<int32_t>(n, 4);
+}
+
+static void zero_dynamic_fp32(cortex_net* n) {
+    const int64_t N = n->N;
+    CX_HIP(hipMemcpyAsync(n->d_U, n->d_U0, N * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    dev_zero(n, n->d_y1, N * sizeof(float));
+    dev_zero(n, n->d_y2, N * sizeof(float));
+    dev_zero(n, n->d_r, N * sizeof(int32_t));
+    dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * sizeof(float));
+    dev_zero(n, n->d_spk_rec, (size_t)n->H * n->n_tiles * sizeof(uint64_t));
+    dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
+    dev_zero(n, n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles * sizeof(uint32_t));
+    dev_zero(n, n->d_events, n->n_tiles * sizeof(uint64_t));
+    dev_zero(n, n->d_spikes, n->n_tiles * sizeof(uint64_t));
+    dev_zero(n, n->d_err, 4 * sizeof(int32_t));
+}
+
+static void alloc_state_fp64(cortex_net* n) {
+    const int64_t N = n->N;
+    n->W64 = (N + 63) / 64;
+    n->H = pow2_at_least(n->dmax + 1);
+    n->d_Ud = dev_alloc_t<double>(n, N);
+    n->d_Ud0 = dev_alloc_t<double>(n, N);
+    n->d_y1d = dev_alloc_t<double>(n, N);
+    n->d_y2d = dev_alloc_t<double>(n, N);
+    n->d_r = dev_alloc_t<int32_t>(n, N);
+    n->d_hist = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->W64);
+    n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
+    n->d_raster = dev_alloc_t<uint64_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64);
+    n->d_events = dev_alloc_t<uint64_t>(n, 1);
+    n->d_err = dev_alloc_t<int32_t>(n, 4);
+}
+
+static void zero_dynamic_fp64(cortex_net* n) {
+    const int64_t N = n->N;
+    CX_HIP(hipMemcpyAsync(n->d_Ud, n->d_Ud0, N * sizeof(double), hipMemcpyDeviceToDevice, n->stream));
+    dev_zero(n, n->d_y1d, N * sizeof(double));
+    dev_zero(n, n->d_y2d, N * sizeof(double));
+    dev_zero(n, n->d_r, N * sizeof(int32_t));
+    dev_zero(n, n->d_hist, (size_t)n->H * n->W64 * sizeof(uint64_t));
+    dev_zero(n, n->d_raster, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64 * sizeof(uint64_t));
+    dev_zero(n, n->d_events, sizeof(uint64_t));
+    dev_zero(n, n->d_err, 4 * sizeof(int32_t));
+}
+
+// Device error flag raised by a kernel (a wait that exceeded its limit).
+static void check_device_flag(cortex_net* n) {
+    CX_HIP(hipStreamSynchronize(n->stream));
+    int32_t e = 0;
+    CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
+    if (e != 0) {
+        n->failed = true;
+        throw Error{CORTEX_ETIMEOUT, "a device-side wait exceeded its spin limit; network state is invalid"};
+    }
+}
+
+static void build(cortex_net* n) {
+    const cortex_spec& s = n->spec;
+    n->k = model_constants(s);
+    n->n_thr = poisson_thresholds(s.poisson_lambda, n->thr, 64);
+    require(n->n_thr >= 0, CORTEX_EINVAL, "Poisson table too long");
+    n->w_ext_native = (s.weight_unit == CORTEX_UNIT_PSP_MV && n->k.conv != 1.0) ? s.w_ext * n->k.conv : s.w_ext;
+    make_blocks(n);
+    n->d_inst_n0 = dev_alloc_t<int64_t>(n, n->n_inst);
+    upload(n, n->d_inst_n0, n->inst_n0);
+    n->ckpt = s.ckpt_every;
+    if (s.precision == CORTEX_FP64_VERIFY) {
+        build_graph_fp64(n);
+        alloc_state_fp64(n);
+        zero_dynamic_fp64(n);
+        init_state(n);
+        zero_dynamic_fp64(n);   // copies U0 into U after init
+    } else {
+        int dmin = 1, dmax = 1;
+        if (!host_delay_range(n, &dmin, &dmax)) delay_range(n, &dmin, &dmax);
+        n->dmin = dmin;
+        n->dmax = dmax;
+        n->R = dmax - dmin + 1;
+        n->H = pow2_at_least(std::max(8, 2 * dmin + 2));
+        plan_tiles(n);
+        upload_tables_fp32(n);
+        build_graph_fp32(n);
+        alloc_state_fp32(n);
+        init_state(n);
+        zero_dynamic_fp32(n);
+        const int per_cu = step_max_blocks_per_cu(n);
+        hipDeviceProp_t prop;
+        CX_HIP(hipGetDeviceProperties(&prop, n->device));
+        require((int64_t)per_cu * prop.multiProcessorCount >= n->n_tiles, CORTEX_EUNSUPPORTED,
+                "not every tile's workgroup can be resident at once (" + std::to_string(n->n_tiles) +
+                    " tiles, " + std::to_string(per_cu) + " per CU)");
+    }
+    n->step = 0;
+    n->log_step0 = 0;
+    free_scratch(n);
+    CX_HIP(hipStreamSynchronize(n->stream));
+}
+
+// Per-(step, tile) lists of a frozen raster for the FP32 kernel.
+static void frozen_lists(cortex_net* n, const uint32_t* st, const uint32_t* id, int64_t ns,
+                         int64_t n_steps, std::vector<uint32_t>& ids, std::vector<uint64_t>& ptr) {
+    ptr.assign((size_t)n_steps * n->n_tiles + 1, 0);
+    ids.clear();
+    int64_t q = 0;
+    for (int64_t s = 0; s < n_steps; ++s) {
+        const int64_t step = n->step + s;
+        while (q < ns && (int64_t)st[q] < step) ++q;
+        int tile_cursor = 0;
+        for (int t = 0; t < n->n_tiles; ++t) {
+            ptr[(size_t)s * n->n_tiles + t] = ids.size();
+            const int64_t t0 = n->tile_start[t], t1 = t0 + n->tile_size[t];
+            while (q < ns && (int64_t)st[q] == step && (int64_t)id[q] < t1) {
+                require((int64_t)id[q] >= t0, CORTEX_EINVAL, "raster not sorted by (step, id)");
+                ids.push_back(id[q]);
+                ++q;
+            }
+            tile_cursor = t;
+        }
+        (void)tile_cursor;
+    }
+    ptr[(size_t)n_steps * n->n_tiles] = ids.size();
+}
+
+}  // namespace cortex
+
+using namespace cortex;
+
+#define CX_API_BEGIN try {
+#define CX_API_END                                           \
+    }                                                        \
+    catch (const ::cortex::Error& e) {                       \
+        set_error(e.msg);                                    \
+        return e.status;                                     \
+    }                                                        \
+    catch (const std::bad_alloc&) {                          \
+        set_error("host allocation failed");                 \
+        return CORTEX_ENOMEM;                                \
+    }                                                        \
+    catch (...) {                                            \
+        set_error("unexpected internal error");              \
+        return CORTEX_EDEVICE;                               \
+    }
+
+static void require_net(cortex_net* n) {
+    require(n != nullptr, CORTEX_EINVAL, "network handle is NULL");
+    require(!n->failed, CORTEX_ESTATE, "network failed earlier; destroy it");
+}
+
+extern "C" {
+
+const char* cortex_last_error(void) { return g_error.c_str(); }
+
+int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_device* dev, cortex_net** out) {
+    cortex_net* n = nullptr;
+    try {
+        require(out != nullptr, CORTEX_EINVAL, "out is NULL");
+        *out = nullptr;
+        validate(spec);
+        n = new cortex_net();
+        n->spec = *spec;
+        n->pops.assign(spec->pops, spec->pops + spec->n_pops);
+        n->projs.assign(spec->projs, spec->projs + spec->n_projs);
+        n->spec.pops = nullptr;
+        n->spec.projs = nullptr;
+        if (dev) n->dev = *dev;
+        n->stream = static_cast<hipStream_t>(n->dev.stream);
+        CX_HIP(hipGetDevice(&n->device));
+        n->seed = seed;
+        build(n);
+        *out = n;
+        return CORTEX_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        if (n) cortex_destroy(n);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        if (n) cortex_destroy(n);
+        return CORTEX_ENOMEM;
+    }
+}
+
+int cortex_step(cortex_net* n, int64_t n_steps) {
+    CX_API_BEGIN
+    require_net(n);
+    require(n_steps >= 0, CORTEX_EINVAL, "n_steps must be >= 0");
+    if (n->spec.precision == CORTEX_FP64_VERIFY) launch_step_fp64(n, n_steps, nullptr, nullptr, nullptr);
+    else launch_step_fp32(n, n_steps, nullptr, nullptr, nullptr, nullptr);
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_get_spikes(cortex_net* n, int64_t step0, int64_t step1, uint32_t* steps, uint32_t* ids,
+                      int64_t capacity, int64_t* count) {
+    CX_API_BEGIN
+    require_net(n);
+    require(count != nullptr && capacity >= 0 && (capacity == 0 || (steps && ids)), CORTEX_EINVAL,
+            "bad output buffers");
+    check_device_flag(n);
+    const int64_t w0 = n->log_step0, w1 = std::min(n->log_step0 + n->log_steps, n->step);
+    bool trunc = step0 < w0 || step1 > w1;
+    const int64_t s0 = std::max(step0, w0), s1 = std::min(step1, w1);
+    std::vector<std::pair<uint32_t, uint32_t>> out;
+    if (s1 > s0) {
+        if (n->spec.precision == CORTEX_FP64_VERIFY) {
+            auto bits = download(n, n->d_raster + (size_t)(s0 - w0) * n->W64, (size_t)(s1 - s0) * n->W64);
+            for (int64_t s = s0; s < s1; ++s)
+                for (int64_t w = 0; w < n->W64; ++w) {
+                    uint64_t x = bits[(size_t)(s - s0) * n->W64 + w];
+                    while (x) {
+                        const int b = __builtin_ctzll(x);
+                        out.emplace_back((uint32_t)s, (uint32_t)(w * 64 + b));
+                        x &= x - 1;
+                    }
+                }
+        } else {
+            auto cnt = download(n, n->d_log_cnt, (size_t)(s1 - w0) * n->n_tiles);
+            auto pos = download(n, n->d_log_pos, n->n_tiles);
+            std::vector<uint64_t> base(n->n_tiles + 1);
+            CX_HIP(hipMemcpy(base.data(), n->d_log_base, base.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+            for (int t = 0; t < n->n_tiles; ++t) {
+                auto tid = download(n, n->d_log_ids + base[t], (size_t)pos[t]);
+                uint64_t p = 0;
+                for (int64_t s = w0; s < s1; ++s) {
+                    const uint32_t c = cnt[(size_t)(s - w0) * n->n_tiles + t];
+                    if (c == 0xFFFFFFFFu) { trunc = true; break; }
+                    if (s >= s0)
+                        for (uint32_t k = 0; k < c; ++k) out.emplace_back((uint32_t)s, tid[p + k]);
+                    p += c;
+                }
+            }
+            std::sort(out.begin(), out.end());
+        }
+    }
+    *count = (int64_t)out.size();
+    const int64_t m = std::min<int64_t>(capacity, (int64_t)out.size());
+    for (int64_t i = 0; i < m; ++i) {
+        steps[i] = out[i].first;
+        ids[i] = out[i].second;
+    }
+    if (m < (int64_t)out.size()) trunc = true;
+    if (trunc) {
+        set_error("spike range truncated (capacity or record window)");
+        return CORTEX_ETRUNC;
+    }
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_clear_spikes(cortex_net* n) {
+    CX_API_BEGIN
+    require_net(n);
+    n->log_step0 = n->step;
+    if (n->spec.precision != CORTEX_FP64_VERIFY) dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
+    CX_HIP(hipStreamSynchronize(n->stream));
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_run_frozen(cortex_net* n, const uint32_t* r_steps, const uint32_t* r_ids, int64_t n_spikes,
+                      int64_t n_steps, void* x_trace, void* v_trace) {
+    CX_API_BEGIN
+    require_net(n);
+    require(n_steps >= 0 && n_spikes >= 0 && (n_spikes == 0 || (r_steps && r_ids)), CORTEX_EINVAL,
+            "bad raster");
+    require((x_trace == nullptr) == (v_trace == nullptr), CORTEX_EINVAL, "pass both traces or neither");
+    for (int64_t q = 0; q < n_spikes; ++q) {
+        require(r_ids[q] < n->N, CORTEX_EINVAL, "raster id out of range");
+        require(q == 0 || r_steps[q] > r_steps[q - 1] || (r_steps[q] == r_steps[q - 1] && r_ids[q] > r_ids[q - 1]),
+                CORTEX_EINVAL, "raster must be sorted by (step, id) without duplicates");
+    }
+    if (n_steps == 0) return CORTEX_OK;
+    if (n->spec.precision == CORTEX_FP64_VERIFY) {
+        std::vector<uint64_t> bits((size_t)n_steps * n->W64, 0);
+        for (int64_t q = 0; q < n_spikes; ++q) {
+            const int64_t s = (int64_t)r_steps[q] - n->step;
+            if (s < 0 || s >= n_steps) continue;
+            bits[(size_t)s * n->W64 + (r_ids[q] >> 6)] |= 1ull << (r_ids[q] & 63);
+        }
+        uint64_t* d_bits = dev_alloc_t<uint64_t>(n, bits.size(), true);
+        upload(n, d_bits, bits);
+        launch_step_fp64(n, n_steps, d_bits, static_cast<double*>(x_trace), static_cast<double*>(v_trace));
+    } else {
+        std::vector<uint32_t> ids;
+        std::vector<uint64_t> ptr;
+        frozen_lists(n, r_steps, r_ids, n_spikes, n_steps, ids, ptr);
+        uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
+        uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
+        upload(n, d_ids, ids);
+        upload(n, d_ptr, ptr);
+        launch_step_fp32(n, n_steps, d_ids, d_ptr, static_cast<float*>(x_trace), static_cast<float*>(v_trace));
+    }
+    check_device_flag(n);
+    free_scratch(n);
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss) {
+    CX_API_BEGIN
+    require_net(n);
+    (void)vstar; (void)grad_w; (void)loss;
+    throw Error{CORTEX_EUNSUPPORTED, "adjoint not built in this library version"};
+    CX_API_END
+}
+
+int cortex_reset(cortex_net* n) {
+    CX_API_BEGIN
+    require_net(n);
+    if (n->spec.precision == CORTEX_FP64_VERIFY) zero_dynamic_fp64(n);
+    else zero_dynamic_fp32(n);
+    n->step = 0;
+    n->log_step0 = 0;
+    CX_HIP(hipStreamSynchronize(n->stream));
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_get_state(cortex_net* n, double* V, int32_t* r, double* y1, double* y2) {
+    CX_API_BEGIN
+    require_net(n);
+    check_device_flag(n);
+    const bool fp64 = n->spec.precision == CORTEX_FP64_VERIFY;
+    const double EL = n->spec.E_L;
+    if (fp64) {
+        if (V) { auto u = download(n, n->d_Ud, n->N); for (int64_t i = 0; i < n->N; ++i) V[i] = u[i] + EL; }
+        if (y1) { auto u = download(n, n->d_y1d, n->N); std::copy(u.begin(), u.end(), y1); }
+        if (y2) { auto u = download(n, n->d_y2d, n->N); std::copy(u.begin(), u.end(), y2); }
+    } else {
+        if (V) { auto u = download(n, n->d_U, n->N); for (int64_t i = 0; i < n->N; ++i) V[i] = (double)u[i] + EL; }
+        if (y1) { auto u = download(n, n->d_y1, n->N); for (int64_t i = 0; i < n->N; ++i) y1[i] = u[i]; }
+        if (y2) { auto u = download(n, n->d_y2, n->N); for (int64_t i = 0; i < n->N; ++i) y2[i] = u[i]; }
+    }
+    if (r) { auto u = download(n, n->d_r, n->N); std::copy(u.begin(), u.end(), r); }
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, int32_t* d) {
+    CX_API_BEGIN
+    require_net(n);
+    if (n->spec.precision == CORTEX_FP64_VERIFY) {
+        auto ptr = download(n, n->d_in_ptr, n->N + 1);
+        auto s = download(n, n->d_in_src, n->E);
+        auto ww = download(n, n->d_in_w, n->E);
+        auto dd = download(n, n->d_in_d, n->E);
+        for (int64_t i = 0; i < n->N; ++i)
+            for (uint64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+                if (src) src[e] = s[e];
+                if (tgt) tgt[e] = i;
+                if (w) w[e] = ww[e];
+                if (d) d[e] = dd[e];
+            }
+        return CORTEX_OK;
+    }
+    auto rs = download(n, n->d_row_start, n->N + 1);
+    uint64_t off_len = 0;
+    for (int b = 0; b < n->n_inst; ++b) off_len += (uint64_t)n->inst_N[b] * (n->inst_ntiles[b] + 1);
+    auto off = download(n, n->d_off_rel, off_len);
+    std::vector<uint32_t> meta(n->E);
+    if (n->meta_bytes == 2) {
+        auto m = download(n, static_cast<const uint16_t*>(n->d_meta), n->E);
+        std::copy(m.begin(), m.end(), meta.begin());
+    } else {
+        meta = download(n, static_cast<const uint32_t*>(n->d_meta), n->E);
+    }
+    std::vector<double> wv(n->E);
+    if (n->w_bytes == 2) {
+        auto m = download(n, static_cast<const uint16_t*>(n->d_w), n->E);
+        for (int64_t e = 0; e < n->E; ++e) {
+            uint32_t u = (uint32_t)m[e] << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            wv[e] = f;
+        }
+    } else {
+        auto m = download(n, static_cast<const float*>(n->d_w), n->E);
+        for (int64_t e = 0; e < n->E; ++e) wv[e] = m[e];
+    }
+    const uint32_t tmask = (1u << n->tbits) - 1u;
+    for (int b = 0; b < n->n_inst; ++b) {
+        const int nt = n->inst_ntiles[b];
+        for (int64_t jl = 0; jl < n->inst_N[b]; ++jl) {
+            const int64_t j = n->inst_n0[b] + jl;
+            const uint64_t ob = n->inst_offbase[b] + (uint64_t)jl * (nt + 1);
+            for (int t = 0; t < nt; ++t) {
+                for (uint64_t e = rs[j] + off[ob + t]; e < rs[j] + off[ob + t + 1]; ++e) {
+                    if (src) src[e] = j;
+                    if (tgt) tgt[e] = n->inst_n0[b] + (int64_t)t * n->T + (meta[e] & tmask);
+                    if (w) w[e] = wv[e];
+                    if (d) d[e] = n->dmin + (int32_t)(meta[e] >> n->tbits);
+                }
+            }
+        }
+    }
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_export_canonical(cortex_net* n, int64_t* canon) {
+    CX_API_BEGIN
+    require_net(n);
+    require(canon != nullptr, CORTEX_EINVAL, "canon is NULL");
+    const uint32_t* src = n->spec.precision == CORTEX_FP64_VERIFY ? n->d_in_canon : n->d_canon;
+    require(src != nullptr, CORTEX_ESTATE, "canonical indices need ckpt_every > 0 in FP32 mode");
+    auto c = download(n, src, n->E);
+    for (int64_t e = 0; e < n->E; ++e) canon[e] = c[e];
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_export_tiles(cortex_net* n, int64_t* start, int32_t* size, int32_t* instance) {
+    CX_API_BEGIN
+    require_net(n);
+    require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_ESTATE, "FP64 networks have no tiles");
+    for (int t = 0; t < n->n_tiles; ++t) {
+        if (start) start[t] = n->tile_start[t];
+        if (size) size[t] = n->tile_size[t];
+        if (instance) instance[t] = n->tile_inst[t];
+    }
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_query(cortex_net* n, int what, int64_t* value) {
+    CX_API_BEGIN
+    require(n != nullptr && value != nullptr, CORTEX_EINVAL, "NULL argument");
+    const bool fp64 = n->spec.precision == CORTEX_FP64_VERIFY;
+    switch (what) {
+        case CORTEX_Q_NEURONS: *value = n->N; break;
+        case CORTEX_Q_SYNAPSES: *value = n->E; break;
+        case CORTEX_Q_MIN_DELAY: *value = n->dmin; break;
+        case CORTEX_Q_MAX_DELAY: *value = n->dmax; break;
+        case CORTEX_Q_TILES: *value = n->n_tiles; break;
+        case CORTEX_Q_TILE_SIZE: *value = n->T; break;
+        case CORTEX_Q_RING_SLOTS: *value = n->R; break;
+        case CORTEX_Q_STEP: *value = n->step; break;
+        case CORTEX_Q_DEVICE_BYTES: *value = (int64_t)n->dev_bytes; break;
+        case CORTEX_Q_EDGE_BYTES: *value = fp64 ? 14 : n->meta_bytes + n->w_bytes; break;
+        case CORTEX_Q_BLOCK_SIZE: *value = n->BS; break;
+        case CORTEX_Q_LDS_BYTES: *value = (int64_t)n->lds_bytes; break;
+        case CORTEX_Q_OFFSET_BYTES: {
+            uint64_t off_len = 0;
+            for (int b = 0; b < n->n_inst && !fp64; ++b) off_len += (uint64_t)n->inst_N[b] * (n->inst_ntiles[b] + 1);
+            *value = (int64_t)off_len * 4;
+            break;
+        }
+        case CORTEX_Q_EVENTS:
+        case CORTEX_Q_SPIKES: {
+            require(!n->failed, CORTEX_ESTATE, "network failed earlier");
+            check_device_flag(n);
+            if (fp64) {
+                if (what == CORTEX_Q_EVENTS) {
+                    auto v = download(n, n->d_events, 1);
+                    *value = (int64_t)v[0];
+                } else {
+                    auto bits = download(n, n->d_raster, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64);
+                    int64_t c = 0;
+                    const int64_t used = std::min(n->step - n->log_step0, n->log_steps);
+                    for (size_t i = 0; i < (size_t)std::max<int64_t>(0, used) * n->W64; ++i) c += __builtin_popcountll(bits[i]);
+                    *value = c;
+                }
+            } else {
+                auto v = download(n, what == CORTEX_Q_EVENTS ? n->d_events : n->d_spikes, n->n_tiles);
+                int64_t s = 0;
+                for (auto x : v) s += (int64_t)x;
+                *value = s;
+            }
+            break;
+        }
+        default: throw Error{CORTEX_EINVAL, "unknown query"};
+    }
+    return CORTEX_OK;
+    CX_API_END
+}
+
+void cortex_destroy(cortex_net* n) {
+    if (!n) return;
+    if (n->stream || true) (void)hipStreamSynchronize(n->stream);
+    release(n, n->scratch);
+    release(n, n->bufs);
+    delete n;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Device helpers: counter-based random numbers and workgroup scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cortex {
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Every random quantity
+// of a network is a pure function of (counter, key): key = (seed, instance),
+// counter = (c0, c1, c2, stream tag).  Ten rounds; each multiplies words 0
+// and 2 by the two Philox constants, mixes the high halves with words 1 and
+// 3 and the round key, and advances the key by the Weyl constants.
+struct Philox4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                          uint64_t k0, uint64_t k1) {
+    constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ull;
+    constexpr uint64_t kMulB = 0xCA5A826395121157ull;
+    constexpr uint64_t kWeylA = 0x9E3779B97F4A7C15ull;
+    constexpr uint64_t kWeylB = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a_hi = __umul64hi(kMulA, c0), a_lo = kMulA * c0;
+        const uint64_t b_hi = __umul64hi(kMulB, c2), b_lo = kMulB * c2;
+        c0 = b_hi ^ c1 ^ k0;
+        c1 = b_lo;
+        c2 = a_hi ^ c3 ^ k1;
+        c3 = a_lo;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    Philox4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Stream tags of the counter's last word.
+enum : uint64_t { kTagEdge = 1, kTagPoisson = 2, kTagV0 = 3, kTagPair = 5 };
+
+// Integer uniform on [0, n): high word of u * n.
+__device__ __forceinline__ uint64_t uniform_below(uint64_t u, uint64_t n) { return __umul64hi(u, n); }
+// Double in [0, 1) from the top 53 bits; (0, 1] variant for logarithms.
+__device__ __forceinline__ double unit_closed0(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
+__device__ __forceinline__ double unit_open0(uint64_t u) { return (double)((u >> 11) + 1) * 0x1.0p-53; }
+
+// Wave (64 lanes) inclusive scan of 32-bit values.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of data[0..n) in LDS, in place, by the whole workgroup.
+// `wsum` is LDS scratch of at least (blockDim.x / 64 + 1) words.  Returns
+// the total.  Must be called by every thread of the workgroup.
+__device__ inline uint32_t block_excl_scan(uint32_t* data, int n, uint32_t* wsum) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int per = (n + bs - 1) / bs;
+    const int beg = min(n, tid * per), end = min(n, beg + per);
+    uint32_t local = 0;
+    for (int i = beg; i < end; ++i) local += data[i];
+    uint32_t inc = wave_incl_scan(local);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        const int nw = (bs + 63) >> 6;
+        for (int w = 0; w < nw; ++w) { uint32_t t = wsum[w]; wsum[w] = acc; acc += t; }
+        wsum[nw] = acc;
+    }
+    __syncthreads();
+    uint32_t run = wsum[wave] + inc - local;
+    for (int i = beg; i < end; ++i) { uint32_t t = data[i]; data[i] = run; run += t; }
+    const uint32_t total = wsum[(bs + 63) >> 6];
+    __syncthreads();
+    return total;
+}
+
+// Index of the last entry of the ascending prefix array pfx[0..n) that is
+// <= x (pfx[0] == 0 <= x).
+__device__ __forceinline__ int seg_of(const uint32_t* pfx, int n, uint32_t x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pfx[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace cortex

@@ -1,0 +1,184 @@
+// Internal declarations shared by the translation units of libcortex.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cortex.h"
+
+namespace cortex {
+
+// Error reporting -----------------------------------------------------------
+void set_error(const std::string& msg);
+
+struct Error {
+    int status;
+    std::string msg;
+};
+
+#define CX_HIP(expr)                                                                \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            throw ::cortex::Error{CORTEX_EDEVICE, std::string(#expr) + ": " +       \
+                                                      hipGetErrorString(e_)};       \
+    } while (0)
+
+inline void require(bool ok, int status, const std::string& msg) {
+    if (!ok) throw Error{status, msg};
+}
+
+// Model constants (host, FP64) ----------------------------------------------
+struct Consts {
+    double P22, P20, P11, P21, P31, P32, P21s, P22s, jump, conv;
+    int n_ref;
+};
+Consts model_constants(const cortex_spec& s);
+int poisson_thresholds(double lambda, uint32_t* thr, int cap);
+
+// Generation tables ----------------------------------------------------------
+// One "block" is a (target population, projection) pair: every target of the
+// population draws the projection's synapses.  Blocks are listed in
+// canonical order inside a population: projections ascending.
+struct GenBlock {
+    int64_t tgt0;        // first global target of the population
+    int64_t n_tgt;       // population size
+    int64_t inst_n0;     // first global neuron of the instance
+    int64_t src0_local;  // first source (instance-local id)
+    int64_t n_src;
+    int64_t k;           // fixed in-degree
+    uint64_t thr_p;      // pairwise threshold p*2^64
+    double w_mean, w_sd;
+    double d0, d1;
+    int32_t rule, delay_kind;
+    int32_t same_pop_no_autapse;
+    int32_t proj_local;  // projection index within the instance
+    int32_t instance;
+    int32_t all_pairs;   // pairwise with p >= 1
+    int64_t tgt0_in_pop; // offset of tgt0 inside its population (0)
+    int32_t slot_base;   // canonical offset of this projection within a target (fixed-k only)
+    int32_t pad;
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace cortex
+
+// Network object ----------------------------------------------------------------
+struct cortex_net {
+    cortex_spec spec{};
+    std::vector<cortex_pop> pops;
+    std::vector<cortex_proj> projs;
+    cortex_device dev{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t seed = 0;
+    bool failed = false;
+    cortex::Consts k{};
+    uint32_t thr[64] = {};
+    int n_thr = 0;
+    double w_ext_native = 0;
+
+    // sizes
+    int64_t N = 0, E = 0;
+    int n_inst = 0;
+    std::vector<int64_t> inst_n0, inst_N;
+    std::vector<int32_t> inst_tile0, inst_ntiles;
+    std::vector<uint64_t> inst_offbase;     // start of the instance's off_rel block
+    int n_tiles = 0, T = 0, BS = 512, NPT = 1;
+    std::vector<int64_t> tile_start;
+    std::vector<int32_t> tile_size, tile_inst;
+    int dmin = 1, dmax = 1, R = 1, H = 64;
+    int tbits = 0, meta_bytes = 2, w_bytes = 4;
+    size_t lds_bytes = 0;
+    int xcd_map = 0;
+    int64_t step = 0;
+    std::vector<cortex::GenBlock> blocks;
+
+    // record window
+    int64_t log_step0 = 0, log_steps = 0;
+
+    // device memory
+    std::vector<cortex::DevBuf> bufs;
+    std::vector<cortex::DevBuf> scratch;
+    size_t dev_bytes = 0;
+    // tables
+    int64_t* d_tile_start = nullptr;
+    int32_t* d_tile_size = nullptr;
+    int32_t* d_tile_inst = nullptr;
+    int32_t* d_inst_tile0 = nullptr;
+    int32_t* d_inst_ntiles = nullptr;
+    int64_t* d_inst_n0 = nullptr;
+    uint64_t* d_inst_offbase = nullptr;
+    // production graph
+    uint64_t* d_row_start = nullptr;   // [N+1]
+    uint32_t* d_off_rel = nullptr;     // [sum_b N_b (nt_b + 1)]
+    void* d_meta = nullptr;            // u16/u32 [E]
+    void* d_w = nullptr;               // f32/bf16 [E]
+    uint32_t* d_canon = nullptr;       // [E] instance-local canonical index (adjoint)
+    uint64_t* d_inst_e0 = nullptr;     // canonical edge base per instance
+    // FP32 state
+    float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
+    int32_t* d_r = nullptr;
+    float* d_ring = nullptr;           // [n_tiles][R][T]
+    uint32_t* d_spk_ids = nullptr;     // [H][N]
+    uint64_t* d_spk_rec = nullptr;     // [H][n_tiles]
+    uint32_t* d_log_cnt = nullptr;     // [log_steps][n_tiles]
+    uint32_t* d_log_ids = nullptr;
+    uint64_t* d_log_base = nullptr;    // [n_tiles + 1]
+    uint64_t* d_log_pos = nullptr;     // [n_tiles]
+    uint64_t* d_events = nullptr;      // [n_tiles]
+    uint64_t* d_spikes = nullptr;      // [n_tiles]
+    int32_t* d_err = nullptr;          // [4]
+    // initial state copy (reset / adjoint)
+    float *d_U0 = nullptr;
+    // FP64 verify graph and state
+    uint64_t* d_in_ptr = nullptr;      // [N+1]
+    uint32_t* d_in_src = nullptr;
+    double* d_in_w = nullptr;
+    uint16_t* d_in_d = nullptr;
+    uint32_t* d_in_canon = nullptr;
+    double *d_Ud = nullptr, *d_y1d = nullptr, *d_y2d = nullptr;
+    double* d_Ud0 = nullptr;
+    uint64_t* d_raster = nullptr;      // [log_steps][W] spike bits of the record window
+    uint64_t* d_hist = nullptr;        // [H][W] spike bits of the last H steps
+    int64_t raster_steps = 0;
+    int64_t W64 = 0;
+    double events_fp64 = 0;
+
+    // adjoint
+    int ckpt = 0;
+    int64_t adj_steps = 0;
+    float* d_ckpt = nullptr;           // checkpoints of (U, y1, y2, r) per ckpt
+    float* d_ckpt_ring = nullptr;      // rings per checkpoint
+};
+
+namespace cortex {
+void* dev_alloc(cortex_net* n, size_t bytes, bool scratch = false);
+void free_scratch(cortex_net* n);
+void dev_zero(cortex_net* n, void* p, size_t bytes);
+template <class T>
+T* dev_alloc_t(cortex_net* n, size_t count, bool scratch = false) {
+    return static_cast<T*>(dev_alloc(n, count * sizeof(T) + (count == 0 ? 16 : 0), scratch));
+}
+
+// Kernel launchers (graph.hip) -----------------------------------------------
+void delay_range(cortex_net* n, int* dmin, int* dmax);
+void build_graph_fp32(cortex_net* n);
+void build_graph_fp64(cortex_net* n);
+void init_state(cortex_net* n);
+// step.hip
+void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
+                      const uint64_t* frz_ptr, float* x_trace, float* v_trace);
+size_t step_lds_bytes(int R, int T, int BS, int ntiles_max);
+int step_max_blocks_per_cu(cortex_net* n);
+// verify.hip
+void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits,
+                      double* x_trace, double* v_trace);
+}  // namespace cortex

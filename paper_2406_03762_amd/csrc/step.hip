@@ -1,0 +1,420 @@
+// Persistent FP32 step kernel: LIF update, spike publication and delivery
+// into workgroup-local input rings.
+//
+// Mapping of the paper's scheme onto the GPU:
+//  - a tile of T consecutive targets and all synapses into them (the
+//    indegree sub-graph of Eq. 5 for that vertex set, one per part of the
+//    partition of Eq. 9-10) belongs to exactly one workgroup for the whole
+//    run, as each post-neuron and its in-edges belong to one thread in
+//    Sec. III-B; the tile's pending input lives in that workgroup's LDS, so
+//    every write of the delivery is local and no global atomic is needed
+//    (the shared part of two indegree sub-graphs holds only read-only
+//    pre-vertices, Eq. 14);
+//  - per step each workgroup first updates its neurons (consuming the ring
+//    slot of the step), then publishes its spikes (the per-step spike list,
+//    the buffer of Sec. III-C), then delivers: for every spike of the
+//    instance it reads the one segment of the source's synapses that lands
+//    in this tile (the spiking sub-graph, Eq. 11) and adds each weight into
+//    ring slot (step + delay) mod R;
+//  - a spike emitted at step q acts no earlier than q + d_min, so a
+//    workgroup delivering step q after updating step q + d_min - 1 is still
+//    in time; it only waits for the other tiles to have published step q,
+//    which lets tiles drift up to d_min - 1 steps apart (the buffered-spike
+//    overlap of Sec. III-C, on one device).  Steps stay strictly sequential
+//    per neuron (Sec. III-B, "Varied Synaptic Delays").
+// The ring needs only R = d_max - d_min + 1 slots: when step q is delivered
+// after the update of step n = q + d_min - 1, pending arrivals span steps
+// n + 1 .. n + R.
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cortex {
+namespace {
+
+constexpr int kChunk = 1024;      // spikes staged per delivery round
+constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
+
+struct StepArgs {
+    const int32_t* inst_tile0;
+    const int32_t* inst_ntiles;
+    const int64_t* inst_n0;
+    const uint64_t* inst_offbase;
+    const int32_t* tile_inst;
+    const int32_t* tile_size;
+    const uint64_t* row_start;
+    const uint32_t* off_rel;
+    const void* meta;
+    const void* w;
+    float* U;
+    float* y1;
+    float* y2;
+    int32_t* r;
+    float* ring;
+    uint32_t* spk_ids;
+    uint64_t* spk_rec;
+    uint32_t* log_cnt;
+    uint32_t* log_ids;
+    const uint64_t* log_base;
+    uint64_t* log_pos;
+    uint64_t* events;
+    uint64_t* spikes;
+    int32_t* err;
+    const uint32_t* frz_ids;
+    const uint64_t* frz_ptr;
+    float* x_trace;
+    float* v_trace;
+    int64_t n0, n1, log_step0, log_steps, N;
+    int n_tiles, T, R, dmin, H, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
+    float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
+    uint64_t seed;
+    uint32_t thr[kMaxThr];
+};
+
+__device__ __forceinline__ float load_w(const void* w, uint64_t e, bool bf16) {
+    if (bf16) return __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16);
+    return static_cast<const float*>(w)[e];
+}
+
+template <int MODEL, typename META, bool WBF16, int NPT>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int bid = blockIdx.x;
+    const int tile = a.xcd ? ((bid & 7) * (a.n_tiles >> 3) + (bid >> 3)) : bid;
+    const int b = a.tile_inst[tile];
+    const int tile0b = a.inst_tile0[b];
+    const int ntb = a.inst_ntiles[b];
+    const int tl = tile - tile0b;
+    const int64_t n0b = a.inst_n0[b];
+    const int64_t g0 = n0b + (int64_t)tl * a.T;
+    const int tsz = a.tile_size[tile];
+    const uint64_t offb = a.inst_offbase[b];
+    const int T = a.T, R = a.R, H = a.H;
+    const uint32_t tmask = (1u << a.tbits) - 1u;
+
+    float* ring = reinterpret_cast<float*>(lds_raw);
+    uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T + ((R * T) & 1));
+    uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + kChunk);
+    uint32_t* s_spk = s_len + kChunk + 1;
+    uint32_t* s_tcnt = s_spk + T;
+    uint32_t* s_wsum = s_tcnt + a.ntb_max + 1;
+    int* s_misc = reinterpret_cast<int*>(s_wsum + 20);
+    unsigned char* s_frz = reinterpret_cast<unsigned char*>(s_misc + 4);
+
+    // neuron state in registers
+    float U[NPT], Y1[NPT], Y2[NPT];
+    int RF[NPT];
+    uint64_t pw0[NPT], pw1[NPT], pw2[NPT], pw3[NPT];   // Poisson words of the current 8-step block
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = tid + k * bs;
+        U[k] = Y1[k] = Y2[k] = 0.f;
+        RF[k] = 0;
+        pw0[k] = pw1[k] = pw2[k] = pw3[k] = 0;
+        if (li < tsz) {
+            U[k] = a.U[g0 + li];
+            RF[k] = a.r[g0 + li];
+            if (MODEL != CORTEX_MODEL_DELTA) Y1[k] = a.y1[g0 + li];
+            if (MODEL == CORTEX_MODEL_ALPHA) Y2[k] = a.y2[g0 + li];
+        }
+    }
+    for (int i = tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
+    for (int i = tid; i < T; i += bs) s_frz[i] = 0;
+    if (tid == 0) { s_misc[0] = 0; s_misc[1] = 0; }
+    uint64_t log_pos = a.log_pos[tile];
+    const uint64_t log_b = a.log_base[tile], log_cap = a.log_base[tile + 1] - log_b;
+    uint64_t ev = 0, nspk = 0;
+    const int64_t spin_max = (int64_t)1 << a.spin_log2;
+    __syncthreads();
+
+    for (int64_t n = a.n0; n < a.n1; ++n) {
+        // ---------------------------------------------------------- update
+        __syncthreads();   // previous step's deliveries and counter reset are visible
+        if (a.frz_ptr) {
+            const uint64_t f0 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile];
+            const uint64_t f1 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1];
+            for (uint64_t q = f0 + tid; q < f1; q += bs) s_frz[a.frz_ids[q] - g0] = 1;
+            __syncthreads();
+        }
+        const int slot = (int)(n % R);
+        const int sub = (int)(n & 7);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int li = tid + k * bs;
+            if (li < tsz) {
+                const float x = ring[slot * T + li];
+                ring[slot * T + li] = 0.f;
+                if (sub == 0 || n == a.n0) {
+                    const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)(n >> 3), 0,
+                                             kTagPoisson, a.seed, (uint64_t)b);
+                    pw0[k] = p.v[0]; pw1[k] = p.v[1]; pw2[k] = p.v[2]; pw3[k] = p.v[3];
+                }
+                const uint64_t word = (sub < 2) ? pw0[k] : (sub < 4) ? pw1[k] : (sub < 6) ? pw2[k] : pw3[k];
+                const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+                int kc = 0;
+                for (int m = 0; m < a.n_thr; ++m) kc += (u >= a.thr[m]) ? 1 : 0;
+                const float inp = x + a.w_ext * (float)kc;
+                const bool integ = RF[k] == 0;
+                float u_new;
+                if (!integ) {
+                    RF[k] -= 1;
+                    u_new = a.Ur;
+                } else if (MODEL == CORTEX_MODEL_DELTA) {
+                    u_new = a.P22 * U[k] + a.P20Ie + inp;
+                } else if (MODEL == CORTEX_MODEL_EXP) {
+                    u_new = a.P22 * U[k] + a.P21 * Y1[k] + a.P20Ie;
+                } else {
+                    u_new = a.P22 * U[k] + a.P31 * Y1[k] + a.P32 * Y2[k] + a.P20Ie;
+                }
+                if (MODEL == CORTEX_MODEL_EXP) {
+                    Y1[k] = a.P11 * Y1[k] + inp;
+                } else if (MODEL == CORTEX_MODEL_ALPHA) {
+                    Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
+                    Y1[k] = a.P11 * Y1[k] + a.jump * inp;
+                }
+                bool spk;
+                if (a.frz_ptr) {
+                    spk = s_frz[li] != 0;
+                    s_frz[li] = 0;
+                } else {
+                    spk = integ && u_new >= a.theta;
+                }
+                if (spk) {
+                    u_new = a.Ur;
+                    RF[k] = a.n_ref;
+                    const int p = atomicAdd(&s_misc[0], 1);
+                    s_spk[p] = (uint32_t)(g0 + li);
+                }
+                U[k] = u_new;
+                if (a.x_trace) {
+                    a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
+                    a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
+                }
+            }
+        }
+        __syncthreads();
+        // --------------------------------------------------------- publish
+        const int c = s_misc[0];
+        uint32_t* dst = a.spk_ids + (size_t)(n & (H - 1)) * a.N + g0;
+        for (int i = tid; i < c; i += bs) dst[i] = s_spk[i];
+        if (n >= a.log_step0 && n < a.log_step0 + a.log_steps) {
+            if (log_pos + c <= log_cap) {
+                for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = s_spk[i];
+                if (tid == 0) a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = (uint32_t)c;
+                log_pos += c;
+            } else if (tid == 0) {
+                a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = 0xFFFFFFFFu;   // overflow mark
+            }
+        }
+        nspk += c;
+        if (tid < c) __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            s_misc[0] = 0;
+            __hip_atomic_store(&a.spk_rec[(size_t)(n & (H - 1)) * a.n_tiles + tile],
+                               ((uint64_t)(n + 1) << 32) | (uint32_t)c, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // --------------------------------------------------------- deliver
+        const int64_t q = n - a.dmin + 1;
+        if (q < 0) continue;
+        const int qs = (int)(q & (H - 1));
+        bool bail = false;
+        for (int i = tid; i < ntb; i += bs) {
+            uint64_t* rp = &a.spk_rec[(size_t)qs * a.n_tiles + tile0b + i];
+            uint64_t v = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t spins = 0;
+            while ((v >> 32) != (uint64_t)(q + 1)) {
+                if (++spins > spin_max ||
+                    __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    bail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                v = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_tcnt[i] = bail ? 0u : (uint32_t)v;
+            if (bail) break;
+        }
+        if (bail) {
+            s_misc[1] = 1;
+            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (s_misc[1]) break;
+        const uint32_t S = block_excl_scan(s_tcnt, ntb, s_wsum);
+        int base_slot = (int)((q + a.dmin) % R);
+        for (uint32_t c0 = 0; c0 < S; c0 += kChunk) {
+            const int cn = (int)min((uint32_t)kChunk, S - c0);
+            for (int k = tid; k < cn; k += bs) {
+                const uint32_t kk = c0 + k;
+                const int tt = seg_of(s_tcnt, ntb, kk);
+                const uint32_t j = a.spk_ids[(size_t)qs * a.N + n0b + (int64_t)tt * T + (kk - s_tcnt[tt])];
+                const uint64_t rs = a.row_start[j];
+                const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+                const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
+                s_beg[k] = rs + o0;
+                s_len[k] = o1 - o0;
+            }
+            __syncthreads();
+            const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
+            for (uint32_t f = tid; f < EL; f += bs) {
+                const int k = seg_of(s_len, cn, f);
+                const uint64_t e = s_beg[k] + (f - s_len[k]);
+                const uint32_t m = static_cast<const META*>(a.meta)[e];
+                const float wv = load_w(a.w, e, WBF16);
+                int sl = base_slot + (int)(m >> a.tbits);
+                if (sl >= R) sl -= R;
+                atomicAdd(&ring[sl * T + (m & tmask)], wv);
+            }
+            ev += EL;
+            __syncthreads();
+        }
+    }
+    // ------------------------------------------------------------- save
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = tid + k * bs;
+        if (li < tsz) {
+            a.U[g0 + li] = U[k];
+            a.r[g0 + li] = RF[k];
+            if (MODEL != CORTEX_MODEL_DELTA) a.y1[g0 + li] = Y1[k];
+            if (MODEL == CORTEX_MODEL_ALPHA) a.y2[g0 + li] = Y2[k];
+        }
+    }
+    for (int i = tid; i < R * T; i += bs) a.ring[(size_t)tile * R * T + i] = ring[i];
+    if (tid == 0) {
+        a.events[tile] += ev;
+        a.spikes[tile] += nspk;
+        a.log_pos[tile] = log_pos;
+    }
+}
+
+using KernelFn = void (*)(StepArgs);
+
+template <int MODEL, typename META, bool WBF16>
+KernelFn pick_npt(int npt) {
+    if (npt == 1) return step_kernel<MODEL, META, WBF16, 1>;
+    if (npt == 2) return step_kernel<MODEL, META, WBF16, 2>;
+    return step_kernel<MODEL, META, WBF16, 4>;
+}
+
+template <int MODEL>
+KernelFn pick_fmt(int meta_bytes, int w_bytes, int npt) {
+    if (meta_bytes == 2) {
+        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true>(npt) : pick_npt<MODEL, uint16_t, false>(npt);
+    }
+    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true>(npt) : pick_npt<MODEL, uint32_t, false>(npt);
+}
+
+KernelFn pick_kernel(const cortex_net* n) {
+    switch (n->spec.model) {
+        case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA>(n->meta_bytes, n->w_bytes, n->NPT);
+        case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP>(n->meta_bytes, n->w_bytes, n->NPT);
+        default: return pick_fmt<CORTEX_MODEL_ALPHA>(n->meta_bytes, n->w_bytes, n->NPT);
+    }
+}
+
+}  // namespace
+
+size_t step_lds_bytes(int R, int T, int BS, int ntiles_max) {
+    (void)BS;
+    size_t b = (size_t)R * T * 4 + 4 * (((size_t)R * T) & 1);
+    b += (size_t)kChunk * 8;            // s_beg
+    b += (size_t)(kChunk + 1) * 4;      // s_len
+    b += (size_t)T * 4;                 // s_spk
+    b += (size_t)(ntiles_max + 1) * 4;  // s_tcnt
+    b += 20 * 4 + 4 * 4;                // s_wsum, s_misc
+    b += (size_t)T;                     // s_frz
+    return (b + 15) & ~(size_t)15;
+}
+
+int step_max_blocks_per_cu(cortex_net* n) {
+    KernelFn f = pick_kernel(n);
+    CX_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)n->lds_bytes));
+    int nb = 0;
+    CX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, n->BS, n->lds_bytes));
+    return nb;
+}
+
+void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
+                      const uint64_t* frz_ptr, float* x_trace, float* v_trace) {
+    if (n_steps <= 0) return;
+    require(n->n_thr <= kMaxThr, CORTEX_EUNSUPPORTED, "Poisson mean too large for the FP32 kernel");
+    StepArgs a{};
+    a.inst_tile0 = n->d_inst_tile0;
+    a.inst_ntiles = n->d_inst_ntiles;
+    a.inst_n0 = n->d_inst_n0;
+    a.inst_offbase = n->d_inst_offbase;
+    a.tile_inst = n->d_tile_inst;
+    a.tile_size = n->d_tile_size;
+    a.row_start = n->d_row_start;
+    a.off_rel = n->d_off_rel;
+    a.meta = n->d_meta;
+    a.w = n->d_w;
+    a.U = n->d_U;
+    a.y1 = n->d_y1;
+    a.y2 = n->d_y2;
+    a.r = n->d_r;
+    a.ring = n->d_ring;
+    a.spk_ids = n->d_spk_ids;
+    a.spk_rec = n->d_spk_rec;
+    a.log_cnt = n->d_log_cnt;
+    a.log_ids = n->d_log_ids;
+    a.log_base = n->d_log_base;
+    a.log_pos = n->d_log_pos;
+    a.events = n->d_events;
+    a.spikes = n->d_spikes;
+    a.err = n->d_err;
+    a.frz_ids = frz_ids;
+    a.frz_ptr = frz_ptr;
+    a.x_trace = x_trace;
+    a.v_trace = v_trace;
+    a.n0 = n->step;
+    a.n1 = n->step + n_steps;
+    a.log_step0 = n->log_step0;
+    a.log_steps = n->log_steps;
+    a.N = n->N;
+    a.n_tiles = n->n_tiles;
+    a.T = n->T;
+    a.R = n->R;
+    a.dmin = n->dmin;
+    a.H = n->H;
+    a.tbits = n->tbits;
+    a.n_ref = n->k.n_ref;
+    a.n_thr = n->n_thr;
+    a.xcd = n->xcd_map;
+    a.spin_log2 = n->spec.spin_limit_log2 > 0 ? n->spec.spin_limit_log2 : 22;
+    int ntb_max = 0;
+    for (int b = 0; b < n->n_inst; ++b) ntb_max = std::max(ntb_max, n->inst_ntiles[b]);
+    a.ntb_max = ntb_max;
+    a.P22 = (float)n->k.P22;
+    a.P20Ie = (float)(n->k.P20 * n->spec.I_e);
+    a.P11 = (float)n->k.P11;
+    a.P21 = (float)n->k.P21;
+    a.P31 = (float)n->k.P31;
+    a.P32 = (float)n->k.P32;
+    a.P21s = (float)n->k.P21s;
+    a.P22s = (float)n->k.P22s;
+    a.jump = (float)n->k.jump;
+    a.theta = (float)(n->spec.V_th - n->spec.E_L);
+    a.Ur = (float)(n->spec.V_reset - n->spec.E_L);
+    a.w_ext = (float)n->w_ext_native;
+    a.E_L = (float)n->spec.E_L;
+    a.seed = n->seed;
+    for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
+    KernelFn f = pick_kernel(n);
+    CX_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)n->lds_bytes));
+    void* params[] = {&a};
+    CX_HIP(hipLaunchCooperativeKernel((const void*)f, dim3(n->n_tiles), dim3(n->BS), params,
+                                      (unsigned)n->lds_bytes, n->stream));
+    n->step += n_steps;
+}
+
+}  // namespace cortex

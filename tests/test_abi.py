@@ -1,0 +1,105 @@
+"""The C ABI: the library loads, exports what the header declares, the Python
+structures match the C layout, and argument errors come back as status codes
+(all without a GPU)."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import netspec
+import paper_2406_03762_amd as cx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return cx.lib()
+
+
+def test_library_exports_every_declared_function(L):
+    names = cx.header_functions()
+    assert len(names) >= 14
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "cortex.h"
+#define F(T, m) printf("%s.%s %zu\\n", #T, #m, offsetof(T, m))
+int main(void) {
+  printf("cortex_spec %zu\\ncortex_pop %zu\\ncortex_proj %zu\\ncortex_device %zu\\n",
+         sizeof(cortex_spec), sizeof(cortex_pop), sizeof(cortex_proj), sizeof(cortex_device));
+  F(cortex_spec, dt); F(cortex_spec, pops); F(cortex_spec, projs); F(cortex_spec, record_steps);
+  F(cortex_spec, ckpt_every); F(cortex_spec, adjoint_steps); F(cortex_spec, spin_limit_log2);
+  F(cortex_proj, k); F(cortex_proj, delay_kind); F(cortex_proj, autapses);
+  F(cortex_device, alloc); F(cortex_device, user);
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().split("\n") if line)
+    assert int(out["cortex_spec"]) == C.sizeof(cx.cortex_spec)
+    assert int(out["cortex_pop"]) == C.sizeof(cx.cortex_pop)
+    assert int(out["cortex_proj"]) == C.sizeof(cx.cortex_proj)
+    assert int(out["cortex_device"]) == C.sizeof(cx.cortex_device)
+    for key, val in out.items():
+        if "." in key:
+            T, m = key.split(".")
+            assert getattr(getattr(cx, T), m).offset == int(val), key
+
+
+def _build(spec_obj, **fields):
+    s, keep = cx.make_spec(spec_obj)
+    for k, v in fields.items():
+        setattr(s, k, v)
+    h = C.c_void_p()
+    rc = cx.lib().cortex_build_network(C.byref(s), 1, None, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("struct_size", 8), ("model", 7), ("precision", 5), ("dt", 0.0),
+    ("tau_m", -1.0), ("V_reset", 30.0), ("poisson_lambda", -1.0), ("n_instances", 0),
+    ("block_size", 300),
+])
+def test_invalid_spec_is_rejected_before_any_device_work(field, value):
+    rc, h = _build(netspec.small_brunel(), **{field: value})
+    assert rc == cx.EINVAL
+    assert not h.value
+    assert cx.lib().cortex_last_error().decode()
+
+
+def test_bad_projection_rejected():
+    net = netspec.small_brunel()
+    net.instances[0].projs[0].d0 = 0          # uniform delay with lo < 1
+    rc, h = _build(net)
+    assert rc == cx.EINVAL and "delay" in cx.lib().cortex_last_error().decode()
+    net = netspec.small_brunel()
+    net.instances[0].projs[0].tgt = 5         # population index out of range
+    rc, h = _build(net)
+    assert rc == cx.EINVAL
+
+
+def test_null_handles_return_einval(L):
+    v = C.c_int64()
+    assert L.cortex_step(None, 1) == cx.EINVAL
+    assert L.cortex_query(None, 0, C.byref(v)) == cx.EINVAL
+    assert L.cortex_reset(None) == cx.EINVAL
+    assert L.cortex_get_spikes(None, 0, 1, None, None, 0, C.byref(v)) == cx.EINVAL
+    assert L.cortex_backward(None, None, None, None) == cx.EINVAL
+    L.cortex_destroy(None)
+
+
+def test_python_names_match_c_names():
+    for nm in cx.header_functions():
+        if nm in ("cortex_last_error",):
+            continue
+        assert hasattr(cx, nm) or nm in ("cortex_export_canonical",), nm

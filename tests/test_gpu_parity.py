@@ -1,0 +1,251 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Integers (graph structure, Poisson counts, FP64 rasters) must match bit for
+bit; FP32 inputs within 1e-5 of the summed absolute weights of the events
+they add up; FP32 closed-loop rasters statistically (population rate within
+2 %, ISI CV within 5 %).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import netspec
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_03762_amd as m
+    m.lib()
+    return m
+
+
+def test_graph_matches_oracle_fixed_indegree(cx, orc):
+    spec = netspec.small_brunel(n_e=800, n_i=200, c_e=80, c_i=20, delay="uniform_int", d0=5, d1=30,
+                                w_rel_sd=0.1)
+    case("graph fixed-indegree N=1000 T=128 seed 7")
+    g = cx.Network(spec, 7, tile_size=128)
+    o = orc.OracleNet(spec, 7)
+    assert g.E == o.E == 1000 * 100
+    assert g.query("TILES") == 8 and g.query("MIN_DELAY") == 5 and g.query("MAX_DELAY") == 30
+    gt, gs, gd, gw = helpers.sorted_edges(*g.graph())
+    ot, os_, od, ow = helpers.sorted_edges(*o.graph())
+    assert np.array_equal(gt, ot) and np.array_equal(gs, os_) and np.array_equal(gd, od)
+    w32 = ow.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(gw - w32) <= np.spacing(np.abs(w32).astype(np.float32)).astype(np.float64))
+
+
+def test_graph_matches_oracle_pairwise_normal_delays(cx, orc):
+    inst = netspec.microcircuit_instance(total=1500, target_synapses=1500 * 150.0)
+    spec = netspec.NetSpec(model="exp", instances=[inst], poisson_lambda=0.5, w_ext=80.0)
+    case("graph pairwise N=1500 auto tiles seed 3")
+    g = cx.Network(spec, 3)
+    o = orc.OracleNet(spec, 3)
+    assert g.E == o.E
+    assert g.query("MIN_DELAY") == o.d_min and g.query("MAX_DELAY") == o.d_max
+    gt, gs, gd, gw = helpers.sorted_edges(*g.graph())
+    ot, os_, od, ow = helpers.sorted_edges(*o.graph())
+    assert np.array_equal(gt, ot) and np.array_equal(gs, os_) and np.array_equal(gd, od)
+    w32 = ow.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(gw - w32) <= np.spacing(np.abs(w32).astype(np.float32)).astype(np.float64))
+
+
+def test_tiles_partition_the_targets_and_own_their_in_edges(cx):
+    # Eq. 8-10: disjoint tiles covering V; Eq. 5/14: a tile's sub-graph holds
+    # exactly the in-edges of its targets
+    spec = netspec.small_brunel(n_e=700, n_i=170, c_e=30, c_i=8)
+    case("tiles N=870 T=100")
+    g = cx.Network(spec, 2, tile_size=100)
+    start, size, inst = g.tiles()
+    assert start[0] == 0 and np.all(start[1:] == start[:-1] + size[:-1])
+    assert start[-1] + size[-1] == g.N and size[-1] == 70
+    src, tgt, w, d = g.graph()
+    tile_of = np.searchsorted(start, tgt, side="right") - 1
+    counts = np.bincount(tile_of, minlength=len(start))
+    assert counts.sum() == g.E
+    for t in range(len(start)):
+        assert counts[t] == 38 * size[t]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_initial_state_matches_oracle(cx, orc, precision):
+    spec = netspec.small_brunel(n_e=300, n_i=75, precision=precision)
+    g = cx.Network(spec, 11)
+    o = orc.OracleNet(spec, 11)
+    V, r, _, _ = g.state()
+    Vo = o.state()[0]
+    if precision == "fp64":
+        assert np.array_equal(V, Vo)
+    else:
+        assert np.array_equal(V, Vo.astype(np.float32).astype(np.float64))
+    assert np.all(r == 0)
+
+
+def _counting_spec(lam, n, precision):
+    inst = netspec.Instance([netspec.Population("A", n)], [])
+    return netspec.NetSpec(model="delta", tau_m=1e300, poisson_lambda=lam, w_ext=1.0, V_th=1e12,
+                           V_reset=0.0, v0_lo=0.0, v0_hi=0.0, instances=[inst], precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_poisson_counts_bit_exact(cx, orc, precision):
+    n, T = 3000, 300
+    spec = _counting_spec(2.0, n, precision)
+    case(f"poisson counts {precision}")
+    g = cx.Network(spec, 5, tile_size=256 if precision == "fp32" else 0)
+    o = orc.OracleNet(spec, 5)
+    _, v = g.run_frozen(np.zeros(0), np.zeros(0), T)
+    _, vo = o.run_frozen(np.zeros(0, np.int64), np.zeros(0, np.int64), T, record_x=False)
+    v = v.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.diff(v, axis=0), np.diff(vo, axis=0))
+    assert np.array_equal(v[0], vo[0])
+
+
+def test_fp64_closed_loop_raster_bit_exact_config1(cx, orc):
+    spec = netspec.config1()
+    case("config1 FP64 closed loop 1000 steps")
+    g = cx.Network(spec, 1, record_steps=1000)
+    g.step(1000)
+    st, ids = g.spikes(0, 1000)
+    o = orc.OracleNet(spec, 1)
+    o.run(1000)
+    ost, oids = o.spikes()
+    assert len(ost) > 1000
+    assert np.array_equal(st.astype(np.int64), ost) and np.array_equal(ids.astype(np.int64), oids)
+    V, r, _, _ = g.state()
+    Vo, ro, _, _ = o.state()
+    assert np.array_equal(V, Vo) and np.array_equal(r, ro)
+    assert g.query("EVENTS") == o.events
+
+
+@pytest.mark.parametrize("model", ["delta", "exp", "alpha"])
+def test_fp64_frozen_traces_bit_exact(cx, orc, model):
+    spec = netspec.small_brunel(model=model, n_e=400, n_i=100, c_e=40, c_i=10, delay="uniform_int",
+                                d0=2, d1=9, w_rel_sd=0.0, precision="fp64",
+                                J=0.1 if model == "delta" else 20.0)
+    T = 150
+    steps, ids = netspec.synthetic_raster(500, T, 0.02, seed=4)
+    case(f"fp64 frozen {model}")
+    g = cx.Network(spec, 9)
+    o = orc.OracleNet(spec, 9)
+    x, v = g.run_frozen(steps, ids, T)
+    xo, vo = o.run_frozen(steps, ids, T)
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.array_equal(v.cpu().numpy(), vo)
+    # the same run split over several calls reproduces every bit
+    g.reset()
+    parts = [g.run_frozen(steps, ids, k) for k in (40, 1, 59, 50)]
+    assert np.array_equal(np.concatenate([p[0].cpu().numpy() for p in parts]), xo)
+
+
+def _fp32_open_loop(cx, orc, spec, T, p, seed, tile_size, sel=None):
+    N = spec.n_neurons
+    steps, ids = netspec.synthetic_raster(N, T, p, seed=seed)
+    g = cx.Network(spec, seed, tile_size=tile_size)
+    x, v = g.run_frozen(steps, ids, T)
+    o = orc.OracleNet(spec, seed, sel=sel)
+    xo, vo = o.run_frozen(steps, ids, T)
+    src, tgt, w, d = o.graph()
+    cols = np.arange(N) if sel is None else np.asarray(sel)
+    B = helpers.abs_input_bound(src, tgt, w, d, steps, ids, N, T)[:, cols]
+    xg = x.cpu().numpy().astype(np.float64)[:, cols]
+    vg = v.cpu().numpy().astype(np.float64)[:, cols]
+    return g, xg, vg, xo, vo, B, steps, ids
+
+
+@pytest.mark.parametrize("model,d0,d1", [("delta", 5, 30), ("exp", 1, 12), ("alpha", 5, 30),
+                                         ("alpha", 1, 1)])
+def test_fp32_open_loop_delivery_matches_oracle(cx, orc, model, d0, d1):
+    spec = netspec.small_brunel(model=model, n_e=2400, n_i=600, c_e=240, c_i=60, delay="uniform_int",
+                                d0=d0, d1=d1, w_rel_sd=0.1, weight_unit="psp_mV")
+    case(f"fp32 open loop {model} delays {d0}..{d1}")
+    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 200, 0.01, 13, 256)
+    assert g.query("TILES") == 12
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.abs(xo).max() > 0
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
+def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc):
+    spec = netspec.small_brunel(n_e=1600, n_i=400, c_e=160, c_i=40, delay="uniform_int", d0=3, d1=17,
+                                w_rel_sd=0.0, J=1.0, g=2.0)
+    T = 160
+    steps, ids = netspec.synthetic_raster(2000, T, 0.02, seed=21)
+    case("fp32 integer weights, split calls")
+    g = cx.Network(spec, 17, tile_size=192)
+    o = orc.OracleNet(spec, 17)
+    xo, _ = o.run_frozen(steps, ids, T)
+    parts = [g.run_frozen(steps, ids, k)[0].cpu().numpy() for k in (1, 63, 16, 80)]
+    assert np.array_equal(np.concatenate(parts).astype(np.float64), xo)
+    # steps up to T - d_min are delivered; later ones are pending in the rings
+    src, _, _, _ = o.graph()
+    outdeg = np.bincount(src, minlength=2000)
+    m = steps <= T - g.query("MIN_DELAY")
+    assert g.query("EVENTS") == outdeg[ids[m]].sum()
+
+
+def test_fp32_closed_loop_statistics_scaled_config2(cx, orc):
+    spec = netspec.config2(scale_n=0.1, scale_k=0.1)
+    T = 10000
+    case("fp32 closed loop config2 x0.1, 1 s")
+    g = cx.Network(spec, 2, record_steps=T)
+    g.step(T)
+    st, ids = g.spikes(0, T)
+    o = orc.OracleNet(spec, 2)
+    o.run(T)
+    ost, oids = o.spikes()
+    rg = helpers.rates_and_cv(st, ids, spec, 1000, T)
+    ro = helpers.rates_and_cv(ost, oids, spec, 1000, T)
+    print("gpu", rg, "oracle", ro, flush=True)
+    for (rate_g, cv_g), (rate_o, cv_o) in zip(rg, ro):
+        assert rate_o > 0.5
+        assert abs(rate_g - rate_o) <= 0.02 * rate_o
+        assert abs(cv_g - cv_o) <= 0.05 * cv_o
+    # every delivered event is a (spike, out-synapse) pair
+    src, _, _, _ = o.graph()
+    outdeg = np.bincount(src, minlength=spec.n_neurons)
+    delivered_steps = T - g.query("MIN_DELAY") + 1
+    m = st < delivered_steps
+    assert g.query("EVENTS") == outdeg[ids[m]].sum()
+
+
+def test_full_size_config2_sampled_open_loop(cx, orc):
+    spec = netspec.config2()
+    N = spec.n_neurons
+    sel = np.unique(np.concatenate([[0, 439, 440, N - 1],
+                                    netspec.sample_targets(N, 28, seed=5)]))
+    T = 60
+    case("config2 full size sampled open loop")
+    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, T, 0.002, 2, 0, sel=sel)
+    assert g.E == 112500 * 11250
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
+def test_error_paths(cx):
+    import ctypes as C
+    spec = netspec.small_brunel()
+    g = cx.Network(spec, 1, record_steps=10)
+    with pytest.raises(cx.CortexError) as e:
+        g.step(-1)
+    assert e.value.status == cx.EINVAL
+    with pytest.raises(cx.CortexError) as e:
+        g.run_frozen(np.array([3, 1]), np.array([0, 0]), 5)
+    assert e.value.status == cx.EINVAL
+    with pytest.raises(cx.CortexError) as e:
+        g.backward(None)
+    assert e.value.status in (cx.ESTATE, cx.EUNSUPPORTED)
+    g.step(20)
+    cnt = C.c_int64()
+    rc = cx.lib().cortex_get_spikes(g._h, 0, 20, None, None, 0, C.byref(cnt))
+    assert rc == cx.ETRUNC
