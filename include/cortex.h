@@ -113,6 +113,7 @@ typedef struct {
     int32_t ckpt_every;       /* adjoint checkpoint interval in steps; 0 = no adjoint */
     int64_t adjoint_steps;    /* longest forward window the adjoint covers */
     int32_t spin_limit_log2;  /* device wait limit, 2^k polls (0 = default 22) */
+    int32_t steps_per_sync;   /* FP32: time steps per exchange of spikes, 1..d_min (0 = auto) */
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device

@@ -53,7 +53,7 @@ class cortex_spec(C.Structure):
                 ("n_projs", C.c_int32), ("projs", C.POINTER(cortex_proj)),
                 ("tile_size", C.c_int32), ("block_size", C.c_int32), ("record_steps", C.c_int64),
                 ("ckpt_every", C.c_int32), ("adjoint_steps", C.c_int64),
-                ("spin_limit_log2", C.c_int32)]
+                ("spin_limit_log2", C.c_int32), ("steps_per_sync", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -117,7 +117,8 @@ _UNIT = {"native": 0, "psp_mV": 1}
 
 
 def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 0,
-              ckpt_every: int = 0, adjoint_steps: int = 0, spin_limit_log2: int = 0):
+              ckpt_every: int = 0, adjoint_steps: int = 0, spin_limit_log2: int = 0,
+              steps_per_sync: int = 0):
     """Marshal a network description (netspec.NetSpec) into cortex_spec.
 
     Returns (spec, keepalive)."""
@@ -153,6 +154,7 @@ def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 
     s.ckpt_every = ckpt_every
     s.adjoint_steps = adjoint_steps
     s.spin_limit_log2 = spin_limit_log2
+    s.steps_per_sync = steps_per_sync
     return s, (pa, qa)
 
 

@@ -192,7 +192,7 @@ static void validate(const cortex_spec* s) {
     require(s->block_size == 0 || s->block_size == 256 || s->block_size == 512 || s->block_size == 1024,
             CORTEX_EINVAL, "block_size must be 0, 256, 512 or 1024");
     require(s->tile_size >= 0 && s->record_steps >= 0 && s->ckpt_every >= 0 && s->adjoint_steps >= 0 &&
-                s->spin_limit_log2 >= 0 && s->spin_limit_log2 <= 40,
+                s->spin_limit_log2 >= 0 && s->spin_limit_log2 <= 40 && s->steps_per_sync >= 0,
             CORTEX_EINVAL, "negative planning field");
     require(s->n_projs >= 0 && (s->n_projs == 0 || s->projs), CORTEX_EINVAL, "projection list is NULL");
     int prev = 0;
@@ -323,9 +323,18 @@ static void plan_tiles(cortex_net* n) {
         return t;
     };
     auto ntb_max_for = [&](int64_t T) { return (int)((maxN + T - 1) / T); };
+    // smallest staging chunk that keeps the workgroup inside its LDS share
+    auto lds_for = [&](int T, int per_cu, int* chunk) {
+        for (int c = 1024; c >= 128; c /= 2) {
+            const size_t l = step_lds_bytes(n->R, T, n->W, ntb_max_for(T), c);
+            if (l * per_cu <= lds_cu) { *chunk = c; return l; }
+        }
+        *chunk = 128;
+        return step_lds_bytes(n->R, T, n->W, ntb_max_for(T), 128);
+    };
     int T = n->spec.tile_size;
     int BS = n->spec.block_size;
-    require(BS == 0 || BS == 256 || BS == 512 || BS == 1024, CORTEX_EINVAL, "block_size must be 0, 256, 512 or 1024");
+    int chunk = 1024;
     if (T <= 0) {
         bool found = false;
         for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
@@ -337,20 +346,25 @@ static void plan_tiles(cortex_net* n) {
             }
             const int t = (int)lo;
             const int bs = BS ? BS : (t > 1024 ? 1024 : (t > 256 ? 512 : 256));
-            const size_t lds = step_lds_bytes(n->R, t, bs, ntb_max_for(t));
+            int c = 1024;
+            const size_t lds = lds_for(t, per_cu, &c);
             if (t <= 4 * bs && lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
                 T = t;
                 BS = bs;
+                chunk = c;
                 found = true;
             }
         }
         require(found, CORTEX_EUNSUPPORTED,
                 "network too large for workgroup-local input rings on this device");
+    } else {
+        if (BS == 0) BS = T > 1024 ? 1024 : (T > 256 ? 512 : 256);
+        lds_for(T, 1, &chunk);
     }
-    if (BS == 0) BS = T > 1024 ? 1024 : (T > 256 ? 512 : 256);
     require(T <= 4 * BS, CORTEX_EINVAL, "tile_size larger than 4 x block_size");
     n->T = T;
     n->BS = BS;
+    n->chunk = chunk;
     n->NPT = (T + BS - 1) / BS;
     if (n->NPT == 3) n->NPT = 4;
     n->n_tiles = 0;
@@ -374,7 +388,8 @@ static void plan_tiles(cortex_net* n) {
         }
         n->n_tiles += nt;
     }
-    n->lds_bytes = step_lds_bytes(n->R, T, BS, ntb_max_for(T));
+    n->ntb_max = ntb_max_for(T);
+    n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk);
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
     n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
 }
@@ -402,8 +417,8 @@ static void alloc_state_fp32(cortex_net* n) {
     n->d_y2 = dev_alloc_t<float>(n, N);
     n->d_r = dev_alloc_t<int32_t>(n, N);
     n->d_ring = dev_alloc_t<float>(n, (size_t)n->n_tiles * n->R * n->T);
-    n->d_spk_ids = dev_alloc_t<uint32_t>(n, (size_t)n->H * N);
-    n->d_spk_rec = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles);
+    // (+8 words: a reader fetches a few id words past a record without bounds checks)
+    n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
     n->d_log_cnt = dev_alloc_t<uint32_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles);
     std::vector<uint64_t> base(n->n_tiles + 1, 0);
@@ -425,7 +440,7 @@ static void zero_dynamic_fp32(cortex_net* n) {
     dev_zero(n, n->d_y2, N * sizeof(float));
     dev_zero(n, n->d_r, N * sizeof(int32_t));
     dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * sizeof(float));
-    dev_zero(n, n->d_spk_rec, (size_t)n->H * n->n_tiles * sizeof(uint64_t));
+    dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
     dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
     dev_zero(n, n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles * sizeof(uint32_t));
     dev_zero(n, n->d_events, n->n_tiles * sizeof(uint64_t));
@@ -493,8 +508,12 @@ static void build(cortex_net* n) {
         if (!host_delay_range(n, &dmin, &dmax)) delay_range(n, &dmin, &dmax);
         n->dmin = dmin;
         n->dmax = dmax;
-        n->R = dmax - dmin + 1;
-        n->H = pow2_at_least(std::max(8, 2 * dmin + 2));
+        // spikes are exchanged every W steps (W <= d_min keeps every input on
+        // time); pending arrivals then span d_max - d_min + W steps
+        n->W = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
+        require(n->W >= 1 && n->W <= dmin, CORTEX_EINVAL, "steps_per_sync must lie in [1, d_min]");
+        n->R = dmax - dmin + n->W;
+        n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
         plan_tiles(n);
         upload_tables_fp32(n);
         build_graph_fp32(n);

@@ -95,6 +95,7 @@ struct cortex_net {
     std::vector<int64_t> tile_start;
     std::vector<int32_t> tile_size, tile_inst;
     int dmin = 1, dmax = 1, R = 1, H = 64;
+    int W = 1, chunk = 1024, ntb_max = 1;   // steps per spike exchange, staged spikes, tiles per instance
     int tbits = 0, meta_bytes = 2, w_bytes = 4;
     size_t lds_bytes = 0;
     int xcd_map = 0;
@@ -127,8 +128,7 @@ struct cortex_net {
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
     float* d_ring = nullptr;           // [n_tiles][R][T]
-    uint32_t* d_spk_ids = nullptr;     // [H][N]
-    uint64_t* d_spk_rec = nullptr;     // [H][n_tiles]
+    uint64_t* d_pub = nullptr;         // [H][n_tiles][T + 1] tagged spike records
     uint32_t* d_log_cnt = nullptr;     // [log_steps][n_tiles]
     uint32_t* d_log_ids = nullptr;
     uint64_t* d_log_base = nullptr;    // [n_tiles + 1]
@@ -176,7 +176,7 @@ void init_state(cortex_net* n);
 // step.hip
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                       const uint64_t* frz_ptr, float* x_trace, float* v_trace);
-size_t step_lds_bytes(int R, int T, int BS, int ntiles_max);
+size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk);
 int step_max_blocks_per_cu(cortex_net* n);
 // verify.hip
 void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits,

@@ -10,21 +10,20 @@
 //    every write of the delivery is local and no global atomic is needed
 //    (the shared part of two indegree sub-graphs holds only read-only
 //    pre-vertices, Eq. 14);
-//  - per step each workgroup first updates its neurons (consuming the ring
-//    slot of the step), then publishes its spikes (the per-step spike list,
-//    the buffer of Sec. III-C), then delivers: for every spike of the
-//    instance it reads the one segment of the source's synapses that lands
-//    in this tile (the spiking sub-graph, Eq. 11) and adds each weight into
-//    ring slot (step + delay) mod R;
-//  - a spike emitted at step q acts no earlier than q + d_min, so a
-//    workgroup delivering step q after updating step q + d_min - 1 is still
-//    in time; it only waits for the other tiles to have published step q,
-//    which lets tiles drift up to d_min - 1 steps apart (the buffered-spike
-//    overlap of Sec. III-C, on one device).  Steps stay strictly sequential
-//    per neuron (Sec. III-B, "Varied Synaptic Delays").
-// The ring needs only R = d_max - d_min + 1 slots: when step q is delivered
-// after the update of step n = q + d_min - 1, pending arrivals span steps
-// n + 1 .. n + R.
+//  - a spike emitted at step q acts no earlier than q + d_min, so the
+//    workgroups exchange spikes once per W <= d_min steps: a "window"
+//    [t0, t0 + W) first delivers the spikes of steps [t0 - d_min,
+//    t0 - d_min + W) (all published by every tile before the window began:
+//    the buffered spikes of Sec. III-C), then updates its neurons W times,
+//    publishing each step's spikes.  Steps stay strictly sequential per
+//    neuron (Sec. III-B, "Varied Synaptic Delays");
+//  - delivery reads, for every spike of the window, the one segment of the
+//    source's synapses that lands in this tile (the spiking sub-graph,
+//    Eq. 11) and adds each weight into ring slot (step + delay) mod R.
+//    Pending arrivals span R = d_max - d_min + W steps.
+// Spikes are published as 64-bit words tagged with the step (coherent
+// device-scope stores, no cache flushes); a reader accepts a word only when
+// its tag matches the step it waits for.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -33,8 +32,8 @@
 namespace cortex {
 namespace {
 
-constexpr int kChunk = 1024;      // spikes staged per delivery round
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
+constexpr int kInline = 3;        // spike ids fetched together with a tile's step record
 
 struct StepArgs {
     const int32_t* inst_tile0;
@@ -52,8 +51,7 @@ struct StepArgs {
     float* y2;
     int32_t* r;
     float* ring;
-    uint32_t* spk_ids;
-    uint64_t* spk_rec;
+    uint64_t* pub;              // [H][n_tiles][T + 1] tagged step records and spike ids
     uint32_t* log_cnt;
     uint32_t* log_ids;
     const uint64_t* log_base;
@@ -66,7 +64,7 @@ struct StepArgs {
     float* x_trace;
     float* v_trace;
     int64_t n0, n1, log_step0, log_steps, N;
-    int n_tiles, T, R, dmin, H, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
+    int n_tiles, T, R, dmin, H, W, chunk, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
     uint64_t seed;
     uint32_t thr[kMaxThr];
@@ -77,10 +75,34 @@ __device__ __forceinline__ float load_w(const void* w, uint64_t e, bool bf16) {
     return static_cast<const float*>(w)[e];
 }
 
+__device__ __forceinline__ uint64_t coherent_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Re-read a published word until it carries `tag` (bounded).
+__device__ __noinline__ uint64_t wait_tag(const uint64_t* p, uint64_t v, uint32_t tag, int64_t spin_max,
+                                          int32_t* err, bool* bail) {
+    int64_t spins = 0;
+    while ((uint32_t)(v >> 32) != tag) {
+        if (++spins > spin_max ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            *bail = true;
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = coherent_load(p);
+    }
+    return v;
+}
+
 template <int MODEL, typename META, bool WBF16, int NPT>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x, bs = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
     const int bid = blockIdx.x;
     const int tile = a.xcd ? ((bid & 7) * (a.n_tiles >> 3) + (bid >> 3)) : bid;
     const int b = a.tile_inst[tile];
@@ -91,19 +113,23 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     const int64_t g0 = n0b + (int64_t)tl * a.T;
     const int tsz = a.tile_size[tile];
     const uint64_t offb = a.inst_offbase[b];
-    const int T = a.T, R = a.R, H = a.H;
+    const int T = a.T, R = a.R, H = a.H, CH = a.chunk;
     const uint32_t tmask = (1u << a.tbits) - 1u;
+    const size_t pub_tile = (size_t)T + 1;
+    const size_t pub_slot = (size_t)a.n_tiles * pub_tile;
+    const int pairs_max = a.W * a.ntb_max;
 
     float* ring = reinterpret_cast<float*>(lds_raw);
     uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T + ((R * T) & 1));
-    uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + kChunk);
-    uint32_t* s_spk = s_len + kChunk + 1;
-    uint32_t* s_tcnt = s_spk + T;
-    uint32_t* s_wsum = s_tcnt + a.ntb_max + 1;
-    int* s_misc = reinterpret_cast<int*>(s_wsum + 20);
+    uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + CH);     // CH + 1
+    uint32_t* s_qof = s_len + CH + 1;                               // CH
+    uint32_t* s_spk = s_qof + CH;                                   // T
+    uint32_t* s_pc = s_spk + T;                                     // pairs_max + 1
+    uint32_t* s_pid = s_pc + pairs_max + 1;                         // pairs_max * kInline
+    uint32_t* s_wsum = s_pid + (size_t)pairs_max * kInline;         // 20
+    int* s_misc = reinterpret_cast<int*>(s_wsum + 20);              // 4
     unsigned char* s_frz = reinterpret_cast<unsigned char*>(s_misc + 4);
 
-    // neuron state in registers
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
     uint64_t pw0[NPT], pw1[NPT], pw2[NPT], pw3[NPT];   // Poisson words of the current 8-step block
@@ -127,154 +153,219 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     const uint64_t log_b = a.log_base[tile], log_cap = a.log_base[tile + 1] - log_b;
     uint64_t ev = 0, nspk = 0;
     const int64_t spin_max = (int64_t)1 << a.spin_log2;
+    bool bail = false;
     __syncthreads();
 
-    for (int64_t n = a.n0; n < a.n1; ++n) {
-        // ---------------------------------------------------------- update
-        __syncthreads();   // previous step's deliveries and counter reset are visible
-        if (a.frz_ptr) {
-            const uint64_t f0 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile];
-            const uint64_t f1 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1];
-            for (uint64_t q = f0 + tid; q < f1; q += bs) s_frz[a.frz_ids[q] - g0] = 1;
-            __syncthreads();
-        }
-        const int slot = (int)(n % R);
-        const int sub = (int)(n & 7);
+    for (int64_t t0 = a.n0; t0 < a.n1; t0 += a.W) {
+        const int wn = (int)min((int64_t)a.W, a.n1 - t0);
+        // ------------------------------------------------------------ deliver
+        const int64_t q_hi = t0 - a.dmin + wn;
+        const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
+        if (q_hi > q_lo) {
+            const int nq = (int)(q_hi - q_lo);
+            const int pairs = nq * ntb;
+            // step records of every tile of the instance, with their first ids
+            for (int p = tid; p < pairs; p += bs) {
+                const int qi = p / ntb, tt = p - qi * ntb;
+                const int64_t q = q_lo + qi;
+                const uint32_t tag = (uint32_t)(q + 1);
+                const uint64_t* base = a.pub + (size_t)(q & (H - 1)) * pub_slot + (size_t)(tile0b + tt) * pub_tile;
+                uint64_t rec = coherent_load(base);
+                uint64_t idw[kInline];
 #pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const int li = tid + k * bs;
-            if (li < tsz) {
-                const float x = ring[slot * T + li];
-                ring[slot * T + li] = 0.f;
-                if (sub == 0 || n == a.n0) {
-                    const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)(n >> 3), 0,
-                                             kTagPoisson, a.seed, (uint64_t)b);
-                    pw0[k] = p.v[0]; pw1[k] = p.v[1]; pw2[k] = p.v[2]; pw3[k] = p.v[3];
+                for (int k = 0; k < kInline; ++k) idw[k] = coherent_load(base + 1 + k);
+                rec = wait_tag(base, rec, tag, spin_max, a.err, &bail);
+                const uint32_t c = (uint32_t)rec;
+                s_pc[p] = c;
+#pragma unroll
+                for (int k = 0; k < kInline; ++k) {
+                    if ((uint32_t)k < c) {
+                        const uint64_t v = wait_tag(base + 1 + k, idw[k], tag, spin_max, a.err, &bail);
+                        s_pid[p * kInline + k] = (uint32_t)v;
+                    }
                 }
-                const uint64_t word = (sub < 2) ? pw0[k] : (sub < 4) ? pw1[k] : (sub < 6) ? pw2[k] : pw3[k];
-                const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-                int kc = 0;
-                for (int m = 0; m < a.n_thr; ++m) kc += (u >= a.thr[m]) ? 1 : 0;
-                const float inp = x + a.w_ext * (float)kc;
-                const bool integ = RF[k] == 0;
-                float u_new;
-                if (!integ) {
-                    RF[k] -= 1;
-                    u_new = a.Ur;
-                } else if (MODEL == CORTEX_MODEL_DELTA) {
-                    u_new = a.P22 * U[k] + a.P20Ie + inp;
-                } else if (MODEL == CORTEX_MODEL_EXP) {
-                    u_new = a.P22 * U[k] + a.P21 * Y1[k] + a.P20Ie;
-                } else {
-                    u_new = a.P22 * U[k] + a.P31 * Y1[k] + a.P32 * Y2[k] + a.P20Ie;
-                }
-                if (MODEL == CORTEX_MODEL_EXP) {
-                    Y1[k] = a.P11 * Y1[k] + inp;
-                } else if (MODEL == CORTEX_MODEL_ALPHA) {
-                    Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
-                    Y1[k] = a.P11 * Y1[k] + a.jump * inp;
-                }
-                bool spk;
-                if (a.frz_ptr) {
-                    spk = s_frz[li] != 0;
-                    s_frz[li] = 0;
-                } else {
-                    spk = integ && u_new >= a.theta;
-                }
-                if (spk) {
-                    u_new = a.Ur;
-                    RF[k] = a.n_ref;
-                    const int p = atomicAdd(&s_misc[0], 1);
-                    s_spk[p] = (uint32_t)(g0 + li);
-                }
-                U[k] = u_new;
-                if (a.x_trace) {
-                    a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
-                    a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
-                }
+                if (bail) break;
             }
-        }
-        __syncthreads();
-        // --------------------------------------------------------- publish
-        const int c = s_misc[0];
-        uint32_t* dst = a.spk_ids + (size_t)(n & (H - 1)) * a.N + g0;
-        for (int i = tid; i < c; i += bs) dst[i] = s_spk[i];
-        if (n >= a.log_step0 && n < a.log_step0 + a.log_steps) {
-            if (log_pos + c <= log_cap) {
-                for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = s_spk[i];
-                if (tid == 0) a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = (uint32_t)c;
-                log_pos += c;
-            } else if (tid == 0) {
-                a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = 0xFFFFFFFFu;   // overflow mark
-            }
-        }
-        nspk += c;
-        if (tid < c) __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            s_misc[0] = 0;
-            __hip_atomic_store(&a.spk_rec[(size_t)(n & (H - 1)) * a.n_tiles + tile],
-                               ((uint64_t)(n + 1) << 32) | (uint32_t)c, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // --------------------------------------------------------- deliver
-        const int64_t q = n - a.dmin + 1;
-        if (q < 0) continue;
-        const int qs = (int)(q & (H - 1));
-        bool bail = false;
-        for (int i = tid; i < ntb; i += bs) {
-            uint64_t* rp = &a.spk_rec[(size_t)qs * a.n_tiles + tile0b + i];
-            uint64_t v = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t spins = 0;
-            while ((v >> 32) != (uint64_t)(q + 1)) {
-                if (++spins > spin_max ||
-                    __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    bail = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                v = __hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            s_tcnt[i] = bail ? 0u : (uint32_t)v;
-            if (bail) break;
-        }
-        if (bail) {
-            s_misc[1] = 1;
-            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-        if (s_misc[1]) break;
-        const uint32_t S = block_excl_scan(s_tcnt, ntb, s_wsum);
-        int base_slot = (int)((q + a.dmin) % R);
-        for (uint32_t c0 = 0; c0 < S; c0 += kChunk) {
-            const int cn = (int)min((uint32_t)kChunk, S - c0);
-            for (int k = tid; k < cn; k += bs) {
-                const uint32_t kk = c0 + k;
-                const int tt = seg_of(s_tcnt, ntb, kk);
-                const uint32_t j = a.spk_ids[(size_t)qs * a.N + n0b + (int64_t)tt * T + (kk - s_tcnt[tt])];
-                const uint64_t rs = a.row_start[j];
-                const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-                const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
-                s_beg[k] = rs + o0;
-                s_len[k] = o1 - o0;
+            if (bail) {
+                s_misc[1] = 1;
+                __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
-            const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
-            for (uint32_t f = tid; f < EL; f += bs) {
-                const int k = seg_of(s_len, cn, f);
-                const uint64_t e = s_beg[k] + (f - s_len[k]);
-                const uint32_t m = static_cast<const META*>(a.meta)[e];
-                const float wv = load_w(a.w, e, WBF16);
-                int sl = base_slot + (int)(m >> a.tbits);
-                if (sl >= R) sl -= R;
-                atomicAdd(&ring[sl * T + (m & tmask)], wv);
+            if (s_misc[1]) break;
+            const uint32_t S = block_excl_scan(s_pc, pairs, s_wsum);
+            const int base_slot = (int)((q_lo + a.dmin) % R);
+            for (uint32_t c0 = 0; c0 < S; c0 += CH) {
+                const int cn = (int)min((uint32_t)CH, S - c0);
+                for (int k = tid; k < cn; k += bs) {
+                    const uint32_t kk = c0 + k;
+                    const int p = seg_of(s_pc, pairs, kk);
+                    const uint32_t rnk = kk - s_pc[p];
+                    const int qi = p / ntb, tt = p - qi * ntb;
+                    uint32_t j;
+                    if (rnk < (uint32_t)kInline) {
+                        j = s_pid[p * kInline + rnk];
+                    } else {
+                        const int64_t q = q_lo + qi;
+                        const uint64_t* w = a.pub + (size_t)(q & (H - 1)) * pub_slot +
+                                            (size_t)(tile0b + tt) * pub_tile + 1 + rnk;
+                        j = (uint32_t)wait_tag(w, coherent_load(w), (uint32_t)(q + 1), spin_max, a.err, &bail);
+                    }
+                    const uint64_t rs = a.row_start[j];
+                    const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+                    const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
+                    s_beg[k] = rs + o0;
+                    s_len[k] = o1 - o0;
+                    s_qof[k] = (uint32_t)qi;
+                }
+                if (bail) {
+                    s_misc[1] = 1;
+                    __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __syncthreads();
+                if (s_misc[1]) break;
+                const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
+                if (tid == 0) s_len[cn] = EL;
+                __syncthreads();
+                // each wave walks a contiguous range of the flattened
+                // (spike, synapse) space; a lane advances its segment index
+                const uint32_t per = ((EL + n_waves - 1) / n_waves + 63) & ~63u;
+                const uint32_t f_beg = min(EL, (uint32_t)wave * per);
+                const uint32_t f_end = min(EL, f_beg + per);
+                uint32_t f = f_beg + lane;
+                int seg = (f < f_end) ? seg_of(s_len, cn, f) : 0;
+                while (f < f_end) {
+                    constexpr int U4 = 4;
+                    uint64_t e[U4];
+                    int sq[U4];
+                    bool on[U4];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u) {
+                        const uint32_t fu = f + 64u * u;
+                        on[u] = fu < f_end;
+                        e[u] = 0;
+                        sq[u] = 0;
+                        if (on[u]) {
+                            while (s_len[seg + 1] <= fu) ++seg;
+                            e[u] = s_beg[seg] + (fu - s_len[seg]);
+                            sq[u] = (int)s_qof[seg];
+                        }
+                    }
+                    uint32_t m[U4];
+                    float wv[U4];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u) {
+                        m[u] = 0;
+                        wv[u] = 0.f;
+                        if (on[u]) {
+                            m[u] = static_cast<const META*>(a.meta)[e[u]];
+                            wv[u] = load_w(a.w, e[u], WBF16);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U4; ++u) {
+                        if (on[u]) {
+                            int sl = base_slot + sq[u] + (int)(m[u] >> a.tbits);
+                            if (sl >= R) sl -= R;
+                            atomicAdd(&ring[sl * T + (m[u] & tmask)], wv[u]);
+                        }
+                    }
+                    f += 64u * U4;
+                }
+                ev += EL;
+                __syncthreads();
             }
-            ev += EL;
+            if (s_misc[1]) break;
+        }
+        // ------------------------------------------------------------ update
+        for (int si = 0; si < wn; ++si) {
+            const int64_t n = t0 + si;
             __syncthreads();
+            if (a.frz_ptr) {
+                const uint64_t f0 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile];
+                const uint64_t f1 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1];
+                for (uint64_t q = f0 + tid; q < f1; q += bs) s_frz[a.frz_ids[q] - g0] = 1;
+                __syncthreads();
+            }
+            const int slot = (int)(n % R);
+            const int sub = (int)(n & 7);
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int li = tid + k * bs;
+                if (li < tsz) {
+                    const float x = ring[slot * T + li];
+                    ring[slot * T + li] = 0.f;
+                    if (sub == 0 || n == a.n0) {
+                        const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)(n >> 3), 0,
+                                                 kTagPoisson, a.seed, (uint64_t)b);
+                        pw0[k] = p.v[0]; pw1[k] = p.v[1]; pw2[k] = p.v[2]; pw3[k] = p.v[3];
+                    }
+                    const uint64_t word = (sub < 2) ? pw0[k] : (sub < 4) ? pw1[k] : (sub < 6) ? pw2[k] : pw3[k];
+                    const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+                    int kc = 0;
+                    for (int m = 0; m < a.n_thr; ++m) kc += (u >= a.thr[m]) ? 1 : 0;
+                    const float inp = x + a.w_ext * (float)kc;
+                    const bool integ = RF[k] == 0;
+                    float u_new;
+                    if (!integ) {
+                        RF[k] -= 1;
+                        u_new = a.Ur;
+                    } else if (MODEL == CORTEX_MODEL_DELTA) {
+                        u_new = a.P22 * U[k] + a.P20Ie + inp;
+                    } else if (MODEL == CORTEX_MODEL_EXP) {
+                        u_new = a.P22 * U[k] + a.P21 * Y1[k] + a.P20Ie;
+                    } else {
+                        u_new = a.P22 * U[k] + a.P31 * Y1[k] + a.P32 * Y2[k] + a.P20Ie;
+                    }
+                    if (MODEL == CORTEX_MODEL_EXP) {
+                        Y1[k] = a.P11 * Y1[k] + inp;
+                    } else if (MODEL == CORTEX_MODEL_ALPHA) {
+                        Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
+                        Y1[k] = a.P11 * Y1[k] + a.jump * inp;
+                    }
+                    bool spk;
+                    if (a.frz_ptr) {
+                        spk = s_frz[li] != 0;
+                        s_frz[li] = 0;
+                    } else {
+                        spk = integ && u_new >= a.theta;
+                    }
+                    if (spk) {
+                        u_new = a.Ur;
+                        RF[k] = a.n_ref;
+                        const int p = atomicAdd(&s_misc[0], 1);
+                        s_spk[p] = (uint32_t)(g0 + li);
+                    }
+                    U[k] = u_new;
+                    if (a.x_trace) {
+                        a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
+                        a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
+                    }
+                }
+            }
+            __syncthreads();
+            // -------------------------------------------------------- publish
+            const int c = s_misc[0];
+            const uint64_t tag = (uint64_t)(uint32_t)(n + 1) << 32;
+            uint64_t* base = a.pub + (size_t)(n & (H - 1)) * pub_slot + (size_t)tile * pub_tile;
+            for (int i = tid; i < c; i += bs) coherent_store(base + 1 + i, tag | s_spk[i]);
+            if (n >= a.log_step0 && n < a.log_step0 + a.log_steps) {
+                if (log_pos + c <= log_cap) {
+                    for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = s_spk[i];
+                    if (tid == 0) a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = (uint32_t)c;
+                    log_pos += c;
+                } else if (tid == 0) {
+                    a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = 0xFFFFFFFFu;   // overflow mark
+                }
+            }
+            nspk += c;
+            __syncthreads();
+            if (tid == 0) {
+                s_misc[0] = 0;
+                coherent_store(base, tag | (uint32_t)c);
+            }
         }
     }
-    // ------------------------------------------------------------- save
+    // ---------------------------------------------------------------- save
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -321,15 +412,17 @@ KernelFn pick_kernel(const cortex_net* n) {
 
 }  // namespace
 
-size_t step_lds_bytes(int R, int T, int BS, int ntiles_max) {
-    (void)BS;
+size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
     size_t b = (size_t)R * T * 4 + 4 * (((size_t)R * T) & 1);
-    b += (size_t)kChunk * 8;            // s_beg
-    b += (size_t)(kChunk + 1) * 4;      // s_len
-    b += (size_t)T * 4;                 // s_spk
-    b += (size_t)(ntiles_max + 1) * 4;  // s_tcnt
-    b += 20 * 4 + 4 * 4;                // s_wsum, s_misc
-    b += (size_t)T;                     // s_frz
+    b += (size_t)chunk * 8;                       // s_beg
+    b += (size_t)(chunk + 1) * 4;                 // s_len
+    b += (size_t)chunk * 4;                       // s_qof
+    b += (size_t)T * 4;                           // s_spk
+    const size_t pairs = (size_t)W * ntiles_max;
+    b += (pairs + 1) * 4;                         // s_pc
+    b += pairs * kInline * 4;                     // s_pid
+    b += 20 * 4 + 4 * 4;                          // s_wsum, s_misc
+    b += (size_t)T;                               // s_frz
     return (b + 15) & ~(size_t)15;
 }
 
@@ -362,8 +455,7 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.y2 = n->d_y2;
     a.r = n->d_r;
     a.ring = n->d_ring;
-    a.spk_ids = n->d_spk_ids;
-    a.spk_rec = n->d_spk_rec;
+    a.pub = n->d_pub;
     a.log_cnt = n->d_log_cnt;
     a.log_ids = n->d_log_ids;
     a.log_base = n->d_log_base;
@@ -385,14 +477,14 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.R = n->R;
     a.dmin = n->dmin;
     a.H = n->H;
+    a.W = n->W;
+    a.chunk = n->chunk;
     a.tbits = n->tbits;
     a.n_ref = n->k.n_ref;
     a.n_thr = n->n_thr;
     a.xcd = n->xcd_map;
     a.spin_log2 = n->spec.spin_limit_log2 > 0 ? n->spec.spin_limit_log2 : 22;
-    int ntb_max = 0;
-    for (int b = 0; b < n->n_inst; ++b) ntb_max = std::max(ntb_max, n->inst_ntiles[b]);
-    a.ntb_max = ntb_max;
+    a.ntb_max = n->ntb_max;
     a.P22 = (float)n->k.P22;
     a.P20Ie = (float)(n->k.P20 * n->spec.I_e);
     a.P11 = (float)n->k.P11;

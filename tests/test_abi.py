@@ -38,6 +38,7 @@ int main(void) {
          sizeof(cortex_spec), sizeof(cortex_pop), sizeof(cortex_proj), sizeof(cortex_device));
   F(cortex_spec, dt); F(cortex_spec, pops); F(cortex_spec, projs); F(cortex_spec, record_steps);
   F(cortex_spec, ckpt_every); F(cortex_spec, adjoint_steps); F(cortex_spec, spin_limit_log2);
+  F(cortex_spec, steps_per_sync);
   F(cortex_proj, k); F(cortex_proj, delay_kind); F(cortex_proj, autapses);
   F(cortex_device, alloc); F(cortex_device, user);
   return 0;
