@@ -345,10 +345,12 @@ static void plan_tiles(cortex_net* n) {
                 if (tiles_for(mid) <= cap) hi = mid; else lo = mid + 1;
             }
             const int t = (int)lo;
-            const int bs = BS ? BS : (t > 1024 ? 1024 : (t > 256 ? 512 : 256));
+            const int bs = BS ? BS : (t > 1024 ? 512 : (t > 512 ? 1024 : 512));
             int c = 1024;
             const size_t lds = lds_for(t, per_cu, &c);
-            if (t <= 4 * bs && lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
+            const int npt = (t + bs - 1) / bs;
+            const bool fits_threads = npt <= 2 || (npt <= 4 && bs <= 512);
+            if (fits_threads && lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
                 T = t;
                 BS = bs;
                 chunk = c;
@@ -358,15 +360,16 @@ static void plan_tiles(cortex_net* n) {
         require(found, CORTEX_EUNSUPPORTED,
                 "network too large for workgroup-local input rings on this device");
     } else {
-        if (BS == 0) BS = T > 1024 ? 1024 : (T > 256 ? 512 : 256);
+        if (BS == 0) BS = T > 1024 ? 512 : (T > 512 ? 1024 : 512);
         lds_for(T, 1, &chunk);
     }
-    require(T <= 4 * BS, CORTEX_EINVAL, "tile_size larger than 4 x block_size");
+    n->NPT = (T + BS - 1) / BS;
+    if (n->NPT == 3) n->NPT = 4;
+    require(n->NPT <= 2 || (n->NPT == 4 && BS <= 512), CORTEX_EINVAL,
+            "tile_size must be at most 2 x block_size (4 x for block_size <= 512)");
     n->T = T;
     n->BS = BS;
     n->chunk = chunk;
-    n->NPT = (T + BS - 1) / BS;
-    if (n->NPT == 3) n->NPT = 4;
     n->n_tiles = 0;
     n->inst_tile0.assign(n->n_inst, 0);
     n->inst_ntiles.assign(n->n_inst, 0);

@@ -98,8 +98,10 @@ __device__ __noinline__ uint64_t wait_tag(const uint64_t* p, uint64_t v, uint32_
     return v;
 }
 
+// Up to 1024 threads per workgroup with one or two neurons per thread; four
+// neurons per thread (large tiles) need the registers of a 512-thread limit.
 template <int MODEL, typename META, bool WBF16, int NPT>
-__global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
+__global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x, bs = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
@@ -164,27 +166,42 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         if (q_hi > q_lo) {
             const int nq = (int)(q_hi - q_lo);
             const int pairs = nq * ntb;
-            // step records of every tile of the instance, with their first ids
-            for (int p = tid; p < pairs; p += bs) {
-                const int qi = p / ntb, tt = p - qi * ntb;
-                const int64_t q = q_lo + qi;
-                const uint32_t tag = (uint32_t)(q + 1);
-                const uint64_t* base = a.pub + (size_t)(q & (H - 1)) * pub_slot + (size_t)(tile0b + tt) * pub_tile;
-                uint64_t rec = coherent_load(base);
-                uint64_t idw[kInline];
+            // step records of every tile of the instance, with their first
+            // ids: all loads of a thread's pairs are issued before any wait
+            constexpr int kP = 2;
+            for (int p0 = 0; p0 < pairs; p0 += kP * bs) {
+                uint64_t rec[kP], idw[kP][kInline];
+                const uint64_t* base[kP];
 #pragma unroll
-                for (int k = 0; k < kInline; ++k) idw[k] = coherent_load(base + 1 + k);
-                rec = wait_tag(base, rec, tag, spin_max, a.err, &bail);
-                const uint32_t c = (uint32_t)rec;
-                s_pc[p] = c;
+                for (int u = 0; u < kP; ++u) {
+                    const int p = p0 + tid + u * bs;
+                    base[u] = nullptr;
+                    if (p < pairs) {
+                        const int qi = p / ntb, tt = p - qi * ntb;
+                        const int64_t q = q_lo + qi;
+                        base[u] = a.pub + (size_t)(q & (H - 1)) * pub_slot + (size_t)(tile0b + tt) * pub_tile;
+                        rec[u] = coherent_load(base[u]);
 #pragma unroll
-                for (int k = 0; k < kInline; ++k) {
-                    if ((uint32_t)k < c) {
-                        const uint64_t v = wait_tag(base + 1 + k, idw[k], tag, spin_max, a.err, &bail);
-                        s_pid[p * kInline + k] = (uint32_t)v;
+                        for (int k = 0; k < kInline; ++k) idw[u][k] = coherent_load(base[u] + 1 + k);
                     }
                 }
-                if (bail) break;
+#pragma unroll
+                for (int u = 0; u < kP; ++u) {
+                    const int p = p0 + tid + u * bs;
+                    if (p < pairs && !bail) {
+                        const uint32_t tag = (uint32_t)(q_lo + p / ntb + 1);
+                        const uint64_t r = wait_tag(base[u], rec[u], tag, spin_max, a.err, &bail);
+                        const uint32_t c = (uint32_t)r;
+                        s_pc[p] = c;
+#pragma unroll
+                        for (int k = 0; k < kInline; ++k) {
+                            if ((uint32_t)k < c) {
+                                const uint64_t v = wait_tag(base[u] + 1 + k, idw[u][k], tag, spin_max, a.err, &bail);
+                                s_pid[p * kInline + k] = (uint32_t)v;
+                            }
+                        }
+                    }
+                }
             }
             if (bail) {
                 s_misc[1] = 1;
@@ -234,7 +251,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
                 uint32_t f = f_beg + lane;
                 int seg = (f < f_end) ? seg_of(s_len, cn, f) : 0;
                 while (f < f_end) {
-                    constexpr int U4 = 4;
+                    constexpr int U4 = 8;
                     uint64_t e[U4];
                     int sq[U4];
                     bool on[U4];

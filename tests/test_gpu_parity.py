@@ -191,10 +191,11 @@ def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc, steps_per_sy
     xo, _ = o.run_frozen(steps, ids, T)
     parts = [g.run_frozen(steps, ids, k)[0].cpu().numpy() for k in (1, 63, 16, 80)]
     assert np.array_equal(np.concatenate(parts).astype(np.float64), xo)
-    # steps up to T - d_min are delivered; later ones are pending in the rings
+    # a call ending at step T has delivered the spikes of steps < T - d_min;
+    # later ones are delivered by the next call
     src, _, _, _ = o.graph()
     outdeg = np.bincount(src, minlength=2000)
-    m = steps <= T - g.query("MIN_DELAY")
+    m = steps < T - g.query("MIN_DELAY")
     assert g.query("EVENTS") == outdeg[ids[m]].sum()
 
 
@@ -218,8 +219,7 @@ def test_fp32_closed_loop_statistics_scaled_config2(cx, orc):
     # every delivered event is a (spike, out-synapse) pair
     src, _, _, _ = o.graph()
     outdeg = np.bincount(src, minlength=spec.n_neurons)
-    delivered_steps = T - g.query("MIN_DELAY") + 1
-    m = st < delivered_steps
+    m = st < T - g.query("MIN_DELAY")
     assert g.query("EVENTS") == outdeg[ids[m]].sum()
 
 
