@@ -302,6 +302,28 @@ static bool host_delay_range(const cortex_net* n, int* dmin, int* dmax) {
     return true;
 }
 
+// Fraction bits of the 64-bit fixed-point input rings: the largest scale at
+// which every target's total absolute in-weight still fits in 62 bits.  A
+// Box-Muller normal never exceeds sqrt(-2 ln 2^-53) < 8.6, which bounds every
+// drawn weight; pairwise projections count every source as connected.
+static int fixed_point_bits(const cortex_net* n) {
+    const double conv = (n->spec.weight_unit == CORTEX_UNIT_PSP_MV) ? n->k.conv : 1.0;
+    std::vector<double> per_pop(n->pops.size(), 0.0);
+    for (const auto& B : n->blocks) {
+        const double wmax = (std::fabs(B.w_mean) + 8.6 * B.w_sd) * std::fabs(conv) * (1.0 + 1e-6);
+        const double cnt = (B.rule == CORTEX_RULE_FIXED_INDEGREE) ? (double)B.k : (double)B.n_src;
+        for (size_t p = 0; p < n->pops.size(); ++p) {
+            int64_t g0 = 0;
+            for (size_t q = 0; q < p; ++q) g0 += n->pops[q].size;
+            if (g0 == B.tgt0) per_pop[p] += cnt * wmax;
+        }
+    }
+    double bound = 1e-30;
+    for (double v : per_pop) bound = std::max(bound, v);
+    int fx = 61 - (int)std::ceil(std::log2(bound + 1.0));
+    return std::max(0, std::min(fx, 52));
+}
+
 static int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -419,7 +441,7 @@ static void alloc_state_fp32(cortex_net* n) {
     n->d_y1 = dev_alloc_t<float>(n, N);
     n->d_y2 = dev_alloc_t<float>(n, N);
     n->d_r = dev_alloc_t<int32_t>(n, N);
-    n->d_ring = dev_alloc_t<float>(n, (size_t)n->n_tiles * n->R * n->T);
+    n->d_ring = dev_alloc_t<long long>(n, (size_t)n->n_tiles * n->R * n->T);
     // (+8 words: a reader fetches a few id words past a record without bounds checks)
     n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
@@ -442,7 +464,7 @@ static void zero_dynamic_fp32(cortex_net* n) {
     dev_zero(n, n->d_y1, N * sizeof(float));
     dev_zero(n, n->d_y2, N * sizeof(float));
     dev_zero(n, n->d_r, N * sizeof(int32_t));
-    dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * sizeof(float));
+    dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * sizeof(long long));
     dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
     dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
     dev_zero(n, n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles * sizeof(uint32_t));
@@ -517,6 +539,7 @@ static void build(cortex_net* n) {
         require(n->W >= 1 && n->W <= dmin, CORTEX_EINVAL, "steps_per_sync must lie in [1, d_min]");
         n->R = dmax - dmin + n->W;
         n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+        n->fx = fixed_point_bits(n);
         plan_tiles(n);
         upload_tables_fp32(n);
         build_graph_fp32(n);

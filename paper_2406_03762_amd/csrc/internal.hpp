@@ -127,7 +127,8 @@ struct cortex_net {
     // FP32 state
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
-    float* d_ring = nullptr;           // [n_tiles][R][T]
+    long long* d_ring = nullptr;       // [n_tiles][R][T] fixed-point input sums
+    int fx = 32;                       // fixed-point fraction bits of the rings
     uint64_t* d_pub = nullptr;         // [H][n_tiles][T + 1] tagged spike records
     uint32_t* d_log_cnt = nullptr;     // [log_steps][n_tiles]
     uint32_t* d_log_ids = nullptr;

@@ -21,10 +21,15 @@
 //    source's synapses that lands in this tile (the spiking sub-graph,
 //    Eq. 11) and adds each weight into ring slot (step + delay) mod R.
 //    Pending arrivals span R = d_max - d_min + W steps.
+// The rings hold 64-bit fixed-point sums (scale 2^fx, chosen so that no
+// target's total in-weight can overflow): integer LDS atomics are several
+// times faster than float ones, and an integer sum does not depend on the
+// order in which the spikes of a window are added.
 // Spikes are published as 64-bit words tagged with the step (coherent
 // device-scope stores, no cache flushes); a reader accepts a word only when
 // its tag matches the step it waits for.
 #include <algorithm>
+#include <cmath>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -50,7 +55,7 @@ struct StepArgs {
     float* y1;
     float* y2;
     int32_t* r;
-    float* ring;
+    long long* ring;
     uint64_t* pub;              // [H][n_tiles][T + 1] tagged step records and spike ids
     uint32_t* log_cnt;
     uint32_t* log_ids;
@@ -66,6 +71,8 @@ struct StepArgs {
     int64_t n0, n1, log_step0, log_steps, N;
     int n_tiles, T, R, dmin, H, W, chunk, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
+    float fx_scale;             // 2^fx
+    double fx_inv;              // 2^-fx
     uint64_t seed;
     uint32_t thr[kMaxThr];
 };
@@ -121,8 +128,8 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     const size_t pub_slot = (size_t)a.n_tiles * pub_tile;
     const int pairs_max = a.W * a.ntb_max;
 
-    float* ring = reinterpret_cast<float*>(lds_raw);
-    uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T + ((R * T) & 1));
+    long long* ring = reinterpret_cast<long long*>(lds_raw);
+    uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T);
     uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + CH);     // CH + 1
     uint32_t* s_qof = s_len + CH + 1;                               // CH
     uint32_t* s_spk = s_qof + CH;                                   // T
@@ -283,7 +290,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         if (on[u]) {
                             int sl = base_slot + sq[u] + (int)(m[u] >> a.tbits);
                             if (sl >= R) sl -= R;
-                            atomicAdd(&ring[sl * T + (m[u] & tmask)], wv[u]);
+                            const long long iv = __float2ll_rn(wv[u] * a.fx_scale);
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&ring[sl * T + (m[u] & tmask)]),
+                                      (unsigned long long)iv);
                         }
                     }
                     f += 64u * U4;
@@ -309,8 +318,8 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             for (int k = 0; k < NPT; ++k) {
                 const int li = tid + k * bs;
                 if (li < tsz) {
-                    const float x = ring[slot * T + li];
-                    ring[slot * T + li] = 0.f;
+                    const float x = (float)((double)ring[slot * T + li] * a.fx_inv);
+                    ring[slot * T + li] = 0;
                     if (sub == 0 || n == a.n0) {
                         const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)(n >> 3), 0,
                                                  kTagPoisson, a.seed, (uint64_t)b);
@@ -430,7 +439,7 @@ KernelFn pick_kernel(const cortex_net* n) {
 }  // namespace
 
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
-    size_t b = (size_t)R * T * 4 + 4 * (((size_t)R * T) & 1);
+    size_t b = (size_t)R * T * 8;
     b += (size_t)chunk * 8;                       // s_beg
     b += (size_t)(chunk + 1) * 4;                 // s_len
     b += (size_t)chunk * 4;                       // s_qof
@@ -515,6 +524,8 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.Ur = (float)(n->spec.V_reset - n->spec.E_L);
     a.w_ext = (float)n->w_ext_native;
     a.E_L = (float)n->spec.E_L;
+    a.fx_scale = std::ldexp(1.0f, n->fx);
+    a.fx_inv = std::ldexp(1.0, -n->fx);
     a.seed = n->seed;
     for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
     KernelFn f = pick_kernel(n);

@@ -223,6 +223,28 @@ def test_fp32_closed_loop_statistics_scaled_config2(cx, orc):
     assert g.query("EVENTS") == outdeg[ids[m]].sum()
 
 
+def test_fp32_results_do_not_depend_on_the_plan(cx):
+    # fixed-point input sums make the FP32 path independent of tile size,
+    # spike-exchange window and workgroup size, bit for bit
+    spec = netspec.config2(scale_n=0.05, scale_k=0.05)
+    T = 1500
+    outs = []
+    for plan in (dict(), dict(tile_size=300, steps_per_sync=2), dict(tile_size=128, block_size=256,
+                                                                   steps_per_sync=1)):
+        case(f"plan {plan}")
+        g = cx.Network(spec, 4, record_steps=T, **plan)
+        g.step(700)
+        g.step(T - 700)
+        st, ids = g.spikes(0, T)
+        V, r, y1, y2 = g.state()
+        outs.append((st, ids, V, r, y1, y2, g.query("EVENTS")))
+        g.close()
+    assert len(outs[0][0]) > 1000
+    for o in outs[1:]:
+        for a, b in zip(outs[0][:6], o[:6]):
+            assert np.array_equal(a, b)
+
+
 def test_full_size_config2_sampled_open_loop(cx, orc):
     spec = netspec.config2()
     N = spec.n_neurons
