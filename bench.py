@@ -21,7 +21,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per synaptic event of the step kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (calibrated against a 1 GiB copy; profiles/step_kernel_config2.md),
+# valid only for the kernel source it was measured on.
+TRAFFIC_BYTES_PER_EVENT = (3.0661e7 * 2.0 + 1.3077e5 * 1.0) * 1024 / 9.059842e9
+TRAFFIC_SOURCE_HASH = "4228796da84fd39d"
 SIM_STEPS_PER_BENCH_STEP = 10000      # 1 s of biological time at dt = 0.1 ms
+
+
+def step_source_hash():
+    import hashlib
+    p = os.path.join(ROOT, "paper_2406_03762_amd", "csrc", "step.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
 def log(msg):
@@ -68,6 +79,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=4000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size before the timed region "
+                         "(a known-size reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -95,6 +109,16 @@ def main():
     log(f"[bench] built: N={net.N} E={E} tiles={n_tiles} T={net.query('TILE_SIZE')} "
         f"R={net.query('RING_SLOTS')} BS={net.query('BLOCK_SIZE')} rec={B_rec}B "
         f"in {t_build:.1f}s")
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb} bytes done")
+        del src, dst
 
     for w in range(args.warmup):
         net.step(args.sim_steps)
@@ -169,7 +193,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (TRAFFIC_BYTES_PER_EVENT * events / args.steps
+                        if step_source_hash() == TRAFFIC_SOURCE_HASH else None),
             "kernel": "step_kernel",
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "offset_bytes_per_launch": offset_bytes,

@@ -367,7 +367,9 @@ static void plan_tiles(cortex_net* n) {
                 if (tiles_for(mid) <= cap) hi = mid; else lo = mid + 1;
             }
             const int t = (int)lo;
-            const int bs = BS ? BS : (t > 1024 ? 512 : (t > 512 ? 1024 : 512));
+            // as many threads as the CU holds: more waves keep more synapse
+            // loads in flight during delivery
+            const int bs = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu)) / (t > 2048 ? 2 : 1);
             int c = 1024;
             const size_t lds = lds_for(t, per_cu, &c);
             const int npt = (t + bs - 1) / bs;
