@@ -19,6 +19,7 @@ SOURCES = [
     ("graph.hip", ["-ffp-contract=off"]),
     ("verify.hip", ["-ffp-contract=off"]),
     ("step.hip", []),
+    ("adjoint.hip", []),
 ]
 
 ARCH = os.environ.get("CORTEX_OFFLOAD_ARCH", "gfx950")

@@ -1,0 +1,386 @@
+// Adjoint of the membrane-voltage loss with respect to every synaptic weight,
+// spikes frozen to the forward raster.
+//
+// With the raster fixed, each neuron's state is an affine function of the
+// inputs it consumed, and the input consumed by target i at step n is
+// x_i(n) = sum_e w_e s_src(e)(n - d_e) (the delivery of Sec. II-B), so the
+// loss L = sum_b 1/(N_b T) sum_{i,n} (V_i(n) - V*_i(n))^2 is quadratic in the
+// weights and dL/dw_e = sum_{m : src(e) spiked at m} g_tgt(e)(m + d_e), with
+// g_i(n) = dL/dx_i(n) from a backward recursion through the exact
+// propagators.  The forward stores the raster and, every C steps, the neuron
+// state and the input rings.  The backward walks the segments last to first:
+//  1. restore the segment's checkpoint and re-run it on the frozen raster with
+//     the step kernel (integer input sums make this a bit-exact replay), which
+//     yields V(n) and the mask m(n) = "integrated and did not spike";
+//  2. one thread per neuron runs the reverse recursion and writes g(n);
+//  3. one workgroup per tile walks, for every source that spiked in the
+//     window, the segment of its synapses into the tile -- the same spiking
+//     sub-graph (Eq. 11) that delivery reads -- and adds the g values at the
+//     arrival steps; each synapse has a single writer (the tile's workgroup,
+//     one wave per source), so no atomics are needed.
+// A final scatter writes the gradient in canonical synapse order.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cortex {
+namespace {
+
+// Write step records and spike ids of steps [q0, q1) (from the raster) into
+// the publication buffer, as the forward kernel had published them.
+__global__ void republish_kernel(uint64_t* pub, int H, int n_tiles, int T, int64_t q0, int nq,
+                                 const uint32_t* ids, const uint64_t* ptr) {
+    const int64_t pairs = (int64_t)nq * n_tiles;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t qi = p / n_tiles;
+        const int tile = (int)(p - qi * n_tiles);
+        const int64_t q = q0 + qi;
+        const uint64_t tag = (uint64_t)(uint32_t)(q + 1) << 32;
+        uint64_t* base = pub + (size_t)(q & (H - 1)) * n_tiles * (T + 1) + (size_t)tile * (T + 1);
+        const uint64_t b0 = ptr[p], b1 = ptr[p + 1];
+        for (uint64_t k = b0; k < b1; ++k)
+            __hip_atomic_store(base + 1 + (k - b0), tag | ids[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(base, tag | (uint32_t)(b1 - b0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+struct ReverseArgs {
+    const float* vtr;      // [len][N] V after each step of the segment
+    const uint8_t* mtr;    // [len][N]
+    const float* vstar;    // [T][N]
+    float* gtr;            // [len][N] dL/dx
+    double* aU;            // carried adjoint state at step s1
+    double* a1;
+    double* a2;
+    uint8_t* m_next;
+    double* loss;
+    const int64_t* inst_n0;
+    const int64_t* inst_N;
+    int n_inst;
+    int64_t N, s0, len, T;
+    int model;
+    double P22, P11, P21, P31, P32, P21s, P22s, jump;
+};
+
+// Per neuron, with m_n = 1 iff step n integrated and did not spike and
+// l_n = dL/dV_n:  aU_n = l_n + m_{n+1} P22 aU_{n+1};
+// exp:   aI_n = m_{n+1} P21 aU_{n+1} + P11 aI_{n+1},             g_n = aI_n;
+// alpha: a2_n = m_{n+1} P32 aU_{n+1} + P22s a2_{n+1},
+//        a1_n = m_{n+1} P31 aU_{n+1} + P21s a2_{n+1} + P11 a1_{n+1}, g_n = jump a1_n;
+// delta: g_n = m_n aU_n.
+__global__ void __launch_bounds__(256) reverse_kernel(ReverseArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lsum = 0.0;
+    if (i < a.N) {
+        int lo = 0, hi = a.n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.inst_n0[mid] <= i) lo = mid; else hi = mid;
+        }
+        const double scale = 1.0 / ((double)a.inst_N[lo] * (double)a.T);
+        double aU = a.aU[i], a1 = a.a1[i], a2 = a.a2[i];
+        int mn = a.m_next[i];
+        for (int64_t k = a.len - 1; k >= 0; --k) {
+            const double diff = (double)a.vtr[k * a.N + i] - (double)a.vstar[(a.s0 + k) * a.N + i];
+            lsum += scale * diff * diff;
+            const double l = 2.0 * scale * diff;
+            const double naU = l + (mn ? a.P22 * aU : 0.0);
+            double na1 = 0.0, na2 = 0.0;
+            if (a.model == CORTEX_MODEL_EXP) {
+                na1 = (mn ? a.P21 * aU : 0.0) + a.P11 * a1;
+            } else if (a.model == CORTEX_MODEL_ALPHA) {
+                na2 = (mn ? a.P32 * aU : 0.0) + a.P22s * a2;
+                na1 = (mn ? a.P31 * aU : 0.0) + a.P21s * a2 + a.P11 * a1;
+            }
+            aU = naU;
+            a1 = na1;
+            a2 = na2;
+            mn = a.mtr[k * a.N + i];
+            double g;
+            if (a.model == CORTEX_MODEL_DELTA) g = mn ? aU : 0.0;
+            else if (a.model == CORTEX_MODEL_EXP) g = a1;
+            else g = a.jump * a1;
+            a.gtr[k * a.N + i] = (float)g;
+        }
+        a.aU[i] = aU;
+        a.a1[i] = a1;
+        a.a2[i] = a2;
+        a.m_next[i] = (uint8_t)mn;
+    }
+    // block reduction of the loss, one double atomic per block (not delivery)
+    __shared__ double red[256];
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(a.loss, red[0]);
+}
+
+struct WgradArgs {
+    const int32_t* tile_inst;
+    const int32_t* inst_tile0;
+    const int32_t* inst_ntiles;
+    const int32_t* inst_T;
+    const int64_t* inst_n0;
+    const uint64_t* inst_offbase;
+    const uint64_t* row_start;
+    const uint32_t* off_rel;
+    const void* meta;
+    int meta16;
+    int tbits, dmin;
+    const uint64_t* src_ptr;    // [n_inst + 1] into src_id
+    const uint32_t* src_id;     // spiking sources, grouped by instance
+    const uint64_t* spk_ptr;    // [n_src + 1] into spk_step
+    const int64_t* spk_step;
+    const float* gtr;           // [len][N]
+    float* grad;                // [E] storage order
+    int64_t N, s0, s1;
+};
+
+// One workgroup per tile, one wave per spiking source, lanes over the
+// source's segment into the tile.
+__global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
+    const int tile = blockIdx.x;
+    const int b = a.tile_inst[tile];
+    const int tl = tile - a.inst_tile0[b];
+    const int ntb = a.inst_ntiles[b];
+    const int64_t n0b = a.inst_n0[b];
+    const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
+    const uint32_t tmask = (1u << a.tbits) - 1u;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    for (uint64_t s = a.src_ptr[b] + wave; s < a.src_ptr[b + 1]; s += n_waves) {
+        const uint32_t j = a.src_id[s];
+        const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+        const uint64_t e0 = a.row_start[j] + a.off_rel[ob], e1 = a.row_start[j] + a.off_rel[ob + 1];
+        const uint64_t p0 = a.spk_ptr[s], p1 = a.spk_ptr[s + 1];
+        for (uint64_t e = e0 + lane; e < e1; e += 64) {
+            const uint32_t m = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                        : static_cast<const uint32_t*>(a.meta)[e];
+            const int64_t d = a.dmin + (int64_t)(m >> a.tbits);
+            const int64_t tgt = g0 + (m & tmask);
+            float acc = 0.f;
+            for (uint64_t p = p0; p < p1; ++p) {
+                const int64_t tau = a.spk_step[p] + d;
+                if (tau >= a.s0 && tau < a.s1) acc += a.gtr[(tau - a.s0) * a.N + tgt];
+            }
+            if (acc != 0.f) a.grad[e] += acc;
+        }
+    }
+}
+
+__global__ void scatter_kernel(const float* src, const uint32_t* canon, float* dst, int64_t E) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
+         e += (int64_t)gridDim.x * blockDim.x)
+        dst[canon[e]] = src[e];
+}
+
+int grid_of(int64_t work, int bs) {
+    int64_t g = (work + bs - 1) / bs;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+}  // namespace
+
+void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr) {
+    if (q1 <= q0) return;
+    const int64_t pairs = (q1 - q0) * n->n_tiles;
+    hipLaunchKernelGGL(republish_kernel, dim3(grid_of(pairs, 256)), dim3(256), 0, n->stream, n->d_pub, n->H,
+                       n->n_tiles, n->T, q0, (int)(q1 - q0), ids, ptr);
+    CX_HIP(hipGetLastError());
+}
+
+// Host side of the backward pass (see the file comment).
+void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss_out);
+
+}  // namespace cortex
+
+namespace cortex {
+
+// Helpers defined in api.hip.
+std::vector<std::pair<uint32_t, uint32_t>> collect_spikes(cortex_net* n, int64_t s0, int64_t s1, bool* trunc);
+void frozen_lists_at(cortex_net* n, int64_t step0, const std::vector<std::pair<uint32_t, uint32_t>>& spikes,
+                     int64_t n_steps, std::vector<uint32_t>& ids, std::vector<uint64_t>& ptr);
+void restore_checkpoint(cortex_net* n, int k);
+
+void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss_out) {
+    const int64_t T = n->step;
+    const int C = n->ckpt;
+    require(C > 0, CORTEX_ESTATE, "adjoint needs ckpt_every > 0 at build");
+    require(T >= 1 && T <= n->adj_steps, CORTEX_ESTATE, "forward window empty or longer than adjoint_steps");
+    require(n->log_step0 == 0, CORTEX_ESTATE, "spike log was cleared since the build; the raster is incomplete");
+    require(vstar != nullptr && grad_w != nullptr && loss_out != nullptr, CORTEX_EINVAL, "NULL argument");
+    bool trunc = false;
+    const auto raster = collect_spikes(n, 0, T, &trunc);
+    require(!trunc, CORTEX_ESTATE, "spike log overflowed; the raster is incomplete");
+    const int64_t N = n->N;
+    const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
+    const size_t pub_n = (size_t)n->H * n->n_tiles * (n->T + 1) + 8;
+    // keep the forward's end state to restore afterwards
+    float* sv_U = dev_alloc_t<float>(n, N, true);
+    float* sv_y1 = dev_alloc_t<float>(n, N, true);
+    float* sv_y2 = dev_alloc_t<float>(n, N, true);
+    int32_t* sv_r = dev_alloc_t<int32_t>(n, N, true);
+    long long* sv_ring = dev_alloc_t<long long>(n, ring_n, true);
+    uint64_t* sv_pub = dev_alloc_t<uint64_t>(n, pub_n, true);
+    uint64_t* sv_ev = dev_alloc_t<uint64_t>(n, 2 * (size_t)n->n_tiles, true);
+    auto d2d = [&](void* dst, const void* src, size_t bytes) {
+        CX_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, n->stream));
+    };
+    d2d(sv_U, n->d_U, N * 4);
+    d2d(sv_y1, n->d_y1, N * 4);
+    d2d(sv_y2, n->d_y2, N * 4);
+    d2d(sv_r, n->d_r, N * 4);
+    d2d(sv_ring, n->d_ring, ring_n * 8);
+    d2d(sv_pub, n->d_pub, pub_n * 8);
+    d2d(sv_ev, n->d_events, n->n_tiles * 8);
+    d2d(sv_ev + n->n_tiles, n->d_spikes, n->n_tiles * 8);
+    // segment buffers
+    float* vtr = dev_alloc_t<float>(n, (size_t)C * N, true);
+    uint8_t* mtr = dev_alloc_t<uint8_t>(n, (size_t)C * N, true);
+    float* gtr = dev_alloc_t<float>(n, (size_t)C * N, true);
+    double* aU = dev_alloc_t<double>(n, N, true);
+    double* a1 = dev_alloc_t<double>(n, N, true);
+    double* a2 = dev_alloc_t<double>(n, N, true);
+    uint8_t* mnext = dev_alloc_t<uint8_t>(n, N, true);
+    double* dloss = dev_alloc_t<double>(n, 1, true);
+    float* grad = dev_alloc_t<float>(n, n->E, true);
+    int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
+    CX_HIP(hipMemcpyAsync(inst_N, n->inst_N.data(), n->n_inst * 8, hipMemcpyHostToDevice, n->stream));
+    dev_zero(n, aU, N * 8);
+    dev_zero(n, a1, N * 8);
+    dev_zero(n, a2, N * 8);
+    dev_zero(n, mnext, N);
+    dev_zero(n, dloss, 8);
+    dev_zero(n, grad, (size_t)n->E * 4);
+    const int64_t saved_log_steps = n->log_steps;
+    n->log_steps = 0;   // the replays must not append to the spike log
+    // raster index by step
+    std::vector<size_t> first(T + 1, raster.size());
+    for (size_t q = raster.size(); q-- > 0;) first[raster[q].first] = q;
+    for (int64_t s = T - 1; s >= 0; --s) first[s] = std::min(first[s], first[s + 1]);
+    auto slice = [&](int64_t a, int64_t b) {
+        a = std::max<int64_t>(0, a);
+        b = std::min<int64_t>(T, b);
+        std::vector<std::pair<uint32_t, uint32_t>> v;
+        if (b > a) v.assign(raster.begin() + first[a], raster.begin() + first[b]);
+        return v;
+    };
+    const int K = (int)((T + C - 1) / C);
+    try {
+        for (int k = K - 1; k >= 0; --k) {
+            const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
+            restore_checkpoint(n, k);
+            n->step = s0;
+            // spikes of [s0 - d_min, s0) are published but not yet delivered at s0
+            const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
+            if (s0 > r0) {
+                std::vector<uint32_t> ids;
+                std::vector<uint64_t> ptr;
+                frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, ids, ptr);
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
+                if (!ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, n->stream));
+                CX_HIP(hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                republish(n, r0, s0, d_ids, d_ptr);
+            }
+            // bit-exact replay of the segment on the frozen raster
+            {
+                std::vector<uint32_t> ids;
+                std::vector<uint64_t> ptr;
+                frozen_lists_at(n, s0, slice(s0, s1), len, ids, ptr);
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
+                if (!ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, n->stream));
+                CX_HIP(hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                launch_step_fp32(n, len, d_ids, d_ptr, nullptr, vtr, mtr);
+            }
+            // reverse recursion over the segment
+            ReverseArgs ra{};
+            ra.vtr = vtr; ra.mtr = mtr; ra.vstar = vstar; ra.gtr = gtr;
+            ra.aU = aU; ra.a1 = a1; ra.a2 = a2; ra.m_next = mnext; ra.loss = dloss;
+            ra.inst_n0 = n->d_inst_n0; ra.inst_N = inst_N; ra.n_inst = n->n_inst;
+            ra.N = N; ra.s0 = s0; ra.len = len; ra.T = T; ra.model = n->spec.model;
+            ra.P22 = n->k.P22; ra.P11 = n->k.P11; ra.P21 = n->k.P21; ra.P31 = n->k.P31;
+            ra.P32 = n->k.P32; ra.P21s = n->k.P21s; ra.P22s = n->k.P22s; ra.jump = n->k.jump;
+            hipLaunchKernelGGL(reverse_kernel, dim3(grid_of(N, 256)), dim3(256), 0, n->stream, ra);
+            CX_HIP(hipGetLastError());
+            // sources whose arrivals may land in [s0, s1), grouped by instance
+            const auto spk = slice(s0 - n->dmax, s1 - n->dmin);
+            std::vector<std::vector<std::pair<uint32_t, int64_t>>> per_inst(n->n_inst);
+            for (const auto& sp : spk) {
+                int lo = 0, hi = n->n_inst;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) / 2;
+                    if (n->inst_n0[mid] <= (int64_t)sp.second) lo = mid; else hi = mid;
+                }
+                per_inst[lo].emplace_back(sp.second, (int64_t)sp.first);
+            }
+            // CSR: instance -> distinct sources -> their spike steps
+            std::vector<uint64_t> src_ptr(n->n_inst + 1, 0), spk_ptr;
+            std::vector<uint32_t> src_id;
+            std::vector<int64_t> spk_step;
+            for (int b = 0; b < n->n_inst; ++b) {
+                auto& v = per_inst[b];
+                std::sort(v.begin(), v.end());
+                for (size_t q = 0; q < v.size(); ++q) {
+                    if (q == 0 || v[q].first != v[q - 1].first) {
+                        src_id.push_back(v[q].first);
+                        spk_ptr.push_back(spk_step.size());
+                    }
+                    spk_step.push_back(v[q].second);
+                }
+                src_ptr[b + 1] = src_id.size();
+            }
+            spk_ptr.push_back(spk_step.size());
+            if (!src_id.empty()) {
+                uint64_t* d_sp = dev_alloc_t<uint64_t>(n, src_ptr.size(), true);
+                uint32_t* d_si = dev_alloc_t<uint32_t>(n, src_id.size(), true);
+                uint64_t* d_pp = dev_alloc_t<uint64_t>(n, spk_ptr.size(), true);
+                int64_t* d_ss = dev_alloc_t<int64_t>(n, spk_step.size(), true);
+                CX_HIP(hipMemcpyAsync(d_sp, src_ptr.data(), src_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                CX_HIP(hipMemcpyAsync(d_si, src_id.data(), src_id.size() * 4, hipMemcpyHostToDevice, n->stream));
+                CX_HIP(hipMemcpyAsync(d_pp, spk_ptr.data(), spk_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                CX_HIP(hipMemcpyAsync(d_ss, spk_step.data(), spk_step.size() * 8, hipMemcpyHostToDevice, n->stream));
+                WgradArgs wa{};
+                wa.tile_inst = n->d_tile_inst; wa.inst_tile0 = n->d_inst_tile0; wa.inst_ntiles = n->d_inst_ntiles;
+                wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0; wa.inst_offbase = n->d_inst_offbase;
+                wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
+                wa.meta16 = n->meta_bytes == 2; wa.tbits = n->tbits; wa.dmin = n->dmin;
+                wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
+                wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
+                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(256), 0, n->stream, wa);
+                CX_HIP(hipGetLastError());
+            }
+            CX_HIP(hipStreamSynchronize(n->stream));
+            // per-segment scratch (lists) is released; large buffers stay
+        }
+        hipLaunchKernelGGL(scatter_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad, n->d_canon,
+                           grad_w, n->E);
+        CX_HIP(hipGetLastError());
+        CX_HIP(hipMemcpyAsync(loss_out, dloss, 8, hipMemcpyDeviceToHost, n->stream));
+    } catch (...) {
+        n->log_steps = saved_log_steps;
+        throw;
+    }
+    n->log_steps = saved_log_steps;
+    d2d(n->d_U, sv_U, N * 4);
+    d2d(n->d_y1, sv_y1, N * 4);
+    d2d(n->d_y2, sv_y2, N * 4);
+    d2d(n->d_r, sv_r, N * 4);
+    d2d(n->d_ring, sv_ring, ring_n * 8);
+    d2d(n->d_pub, sv_pub, pub_n * 8);
+    d2d(n->d_events, sv_ev, n->n_tiles * 8);
+    d2d(n->d_spikes, sv_ev + n->n_tiles, n->n_tiles * 8);
+    n->step = T;
+    CX_HIP(hipStreamSynchronize(n->stream));
+}
+
+}  // namespace cortex

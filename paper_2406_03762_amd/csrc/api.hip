@@ -20,6 +20,8 @@ thread_local std::string g_error = "";
 
 void set_error(const std::string& msg) { g_error = msg; }
 
+static void save_checkpoint(cortex_net* n, int k);
+
 // ----------------------------------------------------------------------------
 // Model constants.  The membrane equation tau dU/dt = -U + R I (Eq. 1, with
 // U = u - u_rest and R = tau/C) is linear between spikes, so one step of
@@ -330,52 +332,78 @@ static int pow2_at_least(int x) {
     return p;
 }
 
-// Tile size: the fewest, largest tiles whose input rings fit the
-// workgroup-local memory, with every tile's workgroup resident at once.
+// Tile sizes.  Every tile's workgroup must be resident at once and its input
+// ring must fit the workgroup-local memory.  Instances of different sizes get
+// different tile sizes so that every tile holds about the same number of
+// synapses (the memory/edge-count balance of Sec. III-A): T_b ~ C / K_b for
+// mean in-degree K_b, with C the smallest load that fits the device.
 static void plan_tiles(cortex_net* n) {
     hipDeviceProp_t prop;
     CX_HIP(hipGetDeviceProperties(&prop, n->device));
     const int n_cu = prop.multiProcessorCount;
     const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
     const int thr_cu = prop.maxThreadsPerMultiProcessor ? prop.maxThreadsPerMultiProcessor : 2048;
-    const int64_t maxN = *std::max_element(n->inst_N.begin(), n->inst_N.end());
-    auto tiles_for = [&](int64_t T) {
+    std::vector<double> K(n->n_inst, 0.0);
+    for (const auto& B : n->blocks) {
+        const double per_tgt = B.rule == CORTEX_RULE_FIXED_INDEGREE
+                                   ? (double)B.k
+                                   : (B.all_pairs ? 1.0 : std::ldexp((double)B.thr_p, -64)) * (double)B.n_src;
+        K[B.instance] += per_tgt * (double)B.n_tgt;
+    }
+    for (int b = 0; b < n->n_inst; ++b) K[b] = std::max(1.0, K[b] / (double)n->inst_N[b]);
+    auto sizes_for = [&](double C, int Tcap) {
+        std::vector<int32_t> Tb(n->n_inst);
+        for (int b = 0; b < n->n_inst; ++b) {
+            const double t = std::floor(C / K[b]);
+            Tb[b] = (int32_t)std::max<double>(1.0, std::min<double>({t, (double)n->inst_N[b], (double)Tcap}));
+        }
+        return Tb;
+    };
+    auto tiles_of = [&](const std::vector<int32_t>& Tb) {
         int64_t t = 0;
-        for (int64_t Nb : n->inst_N) t += (Nb + T - 1) / T;
+        for (int b = 0; b < n->n_inst; ++b) t += (n->inst_N[b] + Tb[b] - 1) / Tb[b];
         return t;
     };
-    auto ntb_max_for = [&](int64_t T) { return (int)((maxN + T - 1) / T); };
-    // smallest staging chunk that keeps the workgroup inside its LDS share
-    auto lds_for = [&](int T, int per_cu, int* chunk) {
+    auto ntb_max_of = [&](const std::vector<int32_t>& Tb) {
+        int m = 1;
+        for (int b = 0; b < n->n_inst; ++b) m = std::max<int>(m, (int)((n->inst_N[b] + Tb[b] - 1) / Tb[b]));
+        return m;
+    };
+    auto lds_for = [&](int T, int ntbm, int per_cu, int* chunk) {
         for (int c = 1024; c >= 128; c /= 2) {
-            const size_t l = step_lds_bytes(n->R, T, n->W, ntb_max_for(T), c);
+            const size_t l = step_lds_bytes(n->R, T, n->W, ntbm, c);
             if (l * per_cu <= lds_cu) { *chunk = c; return l; }
         }
         *chunk = 128;
-        return step_lds_bytes(n->R, T, n->W, ntb_max_for(T), 128);
+        return step_lds_bytes(n->R, T, n->W, ntbm, 128);
     };
-    int T = n->spec.tile_size;
+    std::vector<int32_t> Tb;
     int BS = n->spec.block_size;
     int chunk = 1024;
-    if (T <= 0) {
+    if (n->spec.tile_size > 0) {
+        Tb.assign(n->n_inst, n->spec.tile_size);
+        const int T = n->spec.tile_size;
+        if (BS == 0) BS = T > 2048 ? 512 : 1024;
+        lds_for(T, ntb_max_of(Tb), 1, &chunk);
+    } else {
         bool found = false;
         for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
             const int64_t cap = (int64_t)n_cu * per_cu;
-            int64_t lo = 1, hi = std::max<int64_t>(1, maxN);
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) / 2;
-                if (tiles_for(mid) <= cap) hi = mid; else lo = mid + 1;
+            const int bs = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu));
+            const int Tcap = bs <= 512 ? 4 * bs : 2 * bs;
+            double lo = 1.0, hi = 1.0;
+            for (int b = 0; b < n->n_inst; ++b) hi = std::max(hi, K[b] * (double)n->inst_N[b]);
+            if (tiles_of(sizes_for(hi, Tcap)) > cap) continue;
+            for (int it = 0; it < 100 && hi - lo > 0.5; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (tiles_of(sizes_for(mid, Tcap)) <= cap) hi = mid; else lo = mid;
             }
-            const int t = (int)lo;
-            // as many threads as the CU holds: more waves keep more synapse
-            // loads in flight during delivery
-            const int bs = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu)) / (t > 2048 ? 2 : 1);
+            auto cand = sizes_for(hi, Tcap);
+            const int Tm = *std::max_element(cand.begin(), cand.end());
             int c = 1024;
-            const size_t lds = lds_for(t, per_cu, &c);
-            const int npt = (t + bs - 1) / bs;
-            const bool fits_threads = npt <= 2 || (npt <= 4 && bs <= 512);
-            if (fits_threads && lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
-                T = t;
+            const size_t lds = lds_for(Tm, ntb_max_of(cand), per_cu, &c);
+            if (lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
+                Tb = cand;
                 BS = bs;
                 chunk = c;
                 found = true;
@@ -383,15 +411,14 @@ static void plan_tiles(cortex_net* n) {
         }
         require(found, CORTEX_EUNSUPPORTED,
                 "network too large for workgroup-local input rings on this device");
-    } else {
-        if (BS == 0) BS = T > 1024 ? 512 : (T > 512 ? 1024 : 512);
-        lds_for(T, 1, &chunk);
     }
+    const int T = *std::max_element(Tb.begin(), Tb.end());
     n->NPT = (T + BS - 1) / BS;
     if (n->NPT == 3) n->NPT = 4;
     require(n->NPT <= 2 || (n->NPT == 4 && BS <= 512), CORTEX_EINVAL,
             "tile_size must be at most 2 x block_size (4 x for block_size <= 512)");
     n->T = T;
+    n->inst_T = Tb;
     n->BS = BS;
     n->chunk = chunk;
     n->n_tiles = 0;
@@ -403,19 +430,20 @@ static void plan_tiles(cortex_net* n) {
     n->tile_inst.clear();
     uint64_t off = 0;
     for (int b = 0; b < n->n_inst; ++b) {
-        const int nt = (int)((n->inst_N[b] + T - 1) / T);
+        const int Tb_ = Tb[b];
+        const int nt = (int)((n->inst_N[b] + Tb_ - 1) / Tb_);
         n->inst_tile0[b] = n->n_tiles;
         n->inst_ntiles[b] = nt;
         n->inst_offbase[b] = off;
         off += (uint64_t)n->inst_N[b] * (nt + 1);
         for (int t = 0; t < nt; ++t) {
-            n->tile_start.push_back(n->inst_n0[b] + (int64_t)t * T);
-            n->tile_size.push_back((int32_t)std::min<int64_t>(T, n->inst_N[b] - (int64_t)t * T));
+            n->tile_start.push_back(n->inst_n0[b] + (int64_t)t * Tb_);
+            n->tile_size.push_back((int32_t)std::min<int64_t>(Tb_, n->inst_N[b] - (int64_t)t * Tb_));
             n->tile_inst.push_back(b);
         }
         n->n_tiles += nt;
     }
-    n->ntb_max = ntb_max_for(T);
+    n->ntb_max = ntb_max_of(Tb);
     n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk);
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
     n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
@@ -427,13 +455,27 @@ static void upload_tables_fp32(cortex_net* n) {
     n->d_tile_inst = dev_alloc_t<int32_t>(n, n->n_tiles);
     n->d_inst_tile0 = dev_alloc_t<int32_t>(n, n->n_inst);
     n->d_inst_ntiles = dev_alloc_t<int32_t>(n, n->n_inst);
+    n->d_inst_T = dev_alloc_t<int32_t>(n, n->n_inst);
     n->d_inst_offbase = dev_alloc_t<uint64_t>(n, n->n_inst);
     upload(n, n->d_tile_start, n->tile_start);
     upload(n, n->d_tile_size, n->tile_size);
     upload(n, n->d_tile_inst, n->tile_inst);
     upload(n, n->d_inst_tile0, n->inst_tile0);
     upload(n, n->d_inst_ntiles, n->inst_ntiles);
+    upload(n, n->d_inst_T, n->inst_T);
     upload(n, n->d_inst_offbase, n->inst_offbase);
+}
+
+static void alloc_checkpoints(cortex_net* n) {
+    if (n->ckpt <= 0) return;
+    n->n_ckpt = (int)((n->adj_steps + n->ckpt - 1) / n->ckpt);
+    const int64_t N = n->N;
+    const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
+    n->d_ck_U = dev_alloc_t<float>(n, (size_t)n->n_ckpt * N);
+    n->d_ck_y1 = dev_alloc_t<float>(n, (size_t)n->n_ckpt * N);
+    n->d_ck_y2 = dev_alloc_t<float>(n, (size_t)n->n_ckpt * N);
+    n->d_ck_r = dev_alloc_t<int32_t>(n, (size_t)n->n_ckpt * N);
+    n->d_ck_ring = dev_alloc_t<long long>(n, (size_t)n->n_ckpt * ring_n);
 }
 
 static void alloc_state_fp32(cortex_net* n) {
@@ -447,6 +489,7 @@ static void alloc_state_fp32(cortex_net* n) {
     // (+8 words: a reader fetches a few id words past a record without bounds checks)
     n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
+    if (n->ckpt > 0) n->log_steps = std::max(n->log_steps, n->adj_steps);   // the adjoint replays the raster
     n->d_log_cnt = dev_alloc_t<uint32_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles);
     std::vector<uint64_t> base(n->n_tiles + 1, 0);
     const int64_t per = (n->log_steps + n->k.n_ref) / (n->k.n_ref + 1);
@@ -523,7 +566,9 @@ static void build(cortex_net* n) {
     make_blocks(n);
     n->d_inst_n0 = dev_alloc_t<int64_t>(n, n->n_inst);
     upload(n, n->d_inst_n0, n->inst_n0);
-    n->ckpt = s.ckpt_every;
+    n->ckpt = s.precision == CORTEX_FP64_VERIFY ? 0 : s.ckpt_every;
+    n->adj_steps = s.adjoint_steps;
+    require(n->ckpt == 0 || n->adj_steps >= 1, CORTEX_EINVAL, "adjoint_steps must be >= 1 with ckpt_every > 0");
     if (s.precision == CORTEX_FP64_VERIFY) {
         build_graph_fp64(n);
         alloc_state_fp64(n);
@@ -546,8 +591,10 @@ static void build(cortex_net* n) {
         upload_tables_fp32(n);
         build_graph_fp32(n);
         alloc_state_fp32(n);
+        alloc_checkpoints(n);
         init_state(n);
         zero_dynamic_fp32(n);
+        save_checkpoint(n, 0);
         const int per_cu = step_max_blocks_per_cu(n);
         hipDeviceProp_t prop;
         CX_HIP(hipGetDeviceProperties(&prop, n->device));
@@ -561,29 +608,113 @@ static void build(cortex_net* n) {
     CX_HIP(hipStreamSynchronize(n->stream));
 }
 
-// Per-(step, tile) lists of a frozen raster for the FP32 kernel.
-static void frozen_lists(cortex_net* n, const uint32_t* st, const uint32_t* id, int64_t ns,
-                         int64_t n_steps, std::vector<uint32_t>& ids, std::vector<uint64_t>& ptr) {
+// Per-(step, tile) lists of a frozen raster for the FP32 kernel: spikes with
+// step in [step0, step0 + n_steps), sorted by (step, id).
+void frozen_lists_at(cortex_net* n, int64_t step0, const std::vector<std::pair<uint32_t, uint32_t>>& spikes,
+                     int64_t n_steps, std::vector<uint32_t>& ids, std::vector<uint64_t>& ptr) {
     ptr.assign((size_t)n_steps * n->n_tiles + 1, 0);
     ids.clear();
-    int64_t q = 0;
+    size_t q = 0;
+    const size_t ns = spikes.size();
     for (int64_t s = 0; s < n_steps; ++s) {
-        const int64_t step = n->step + s;
-        while (q < ns && (int64_t)st[q] < step) ++q;
-        int tile_cursor = 0;
+        const int64_t step = step0 + s;
+        while (q < ns && (int64_t)spikes[q].first < step) ++q;
         for (int t = 0; t < n->n_tiles; ++t) {
             ptr[(size_t)s * n->n_tiles + t] = ids.size();
             const int64_t t0 = n->tile_start[t], t1 = t0 + n->tile_size[t];
-            while (q < ns && (int64_t)st[q] == step && (int64_t)id[q] < t1) {
-                require((int64_t)id[q] >= t0, CORTEX_EINVAL, "raster not sorted by (step, id)");
-                ids.push_back(id[q]);
+            while (q < ns && (int64_t)spikes[q].first == step && (int64_t)spikes[q].second < t1) {
+                require((int64_t)spikes[q].second >= t0, CORTEX_EINVAL, "raster not sorted by (step, id)");
+                ids.push_back(spikes[q].second);
                 ++q;
             }
-            tile_cursor = t;
         }
-        (void)tile_cursor;
     }
     ptr[(size_t)n_steps * n->n_tiles] = ids.size();
+}
+
+// Spikes with step in [s0, s1) from the log, sorted by (step, id).
+std::vector<std::pair<uint32_t, uint32_t>> collect_spikes(cortex_net* n, int64_t step0, int64_t step1,
+                                                          bool* trunc) {
+    const int64_t w0 = n->log_step0, w1 = std::min(n->log_step0 + n->log_steps, n->step);
+    *trunc = step0 < w0 || step1 > w1;
+    const int64_t s0 = std::max(step0, w0), s1 = std::min(step1, w1);
+    std::vector<std::pair<uint32_t, uint32_t>> out;
+    if (s1 <= s0) return out;
+    if (n->spec.precision == CORTEX_FP64_VERIFY) {
+        auto bits = download(n, n->d_raster + (size_t)(s0 - w0) * n->W64, (size_t)(s1 - s0) * n->W64);
+        for (int64_t s = s0; s < s1; ++s)
+            for (int64_t w = 0; w < n->W64; ++w) {
+                uint64_t x = bits[(size_t)(s - s0) * n->W64 + w];
+                while (x) {
+                    const int b = __builtin_ctzll(x);
+                    out.emplace_back((uint32_t)s, (uint32_t)(w * 64 + b));
+                    x &= x - 1;
+                }
+            }
+        return out;
+    }
+    auto cnt = download(n, n->d_log_cnt, (size_t)(s1 - w0) * n->n_tiles);
+    auto pos = download(n, n->d_log_pos, n->n_tiles);
+    auto base = download(n, n->d_log_base, n->n_tiles + 1);
+    for (int t = 0; t < n->n_tiles; ++t) {
+        auto tid = download(n, n->d_log_ids + base[t], (size_t)pos[t]);
+        uint64_t p = 0;
+        for (int64_t s = w0; s < s1; ++s) {
+            const uint32_t c = cnt[(size_t)(s - w0) * n->n_tiles + t];
+            if (c == 0xFFFFFFFFu) { *trunc = true; break; }
+            if (s >= s0)
+                for (uint32_t k = 0; k < c; ++k) out.emplace_back((uint32_t)s, tid[p + k]);
+            p += c;
+        }
+    }
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+// Adjoint checkpoints: neuron state and input rings at steps k * ckpt.
+static void save_checkpoint(cortex_net* n, int k) {
+    if (k < 0 || k >= n->n_ckpt) return;
+    const int64_t N = n->N;
+    const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
+    auto d2d = [&](void* dst, const void* src, size_t bytes) {
+        CX_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, n->stream));
+    };
+    d2d(n->d_ck_U + (size_t)k * N, n->d_U, N * 4);
+    d2d(n->d_ck_y1 + (size_t)k * N, n->d_y1, N * 4);
+    d2d(n->d_ck_y2 + (size_t)k * N, n->d_y2, N * 4);
+    d2d(n->d_ck_r + (size_t)k * N, n->d_r, N * 4);
+    d2d(n->d_ck_ring + (size_t)k * ring_n, n->d_ring, ring_n * 8);
+}
+
+void restore_checkpoint(cortex_net* n, int k) {
+    const int64_t N = n->N;
+    const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
+    auto d2d = [&](void* dst, const void* src, size_t bytes) {
+        CX_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, n->stream));
+    };
+    d2d(n->d_U, n->d_ck_U + (size_t)k * N, N * 4);
+    d2d(n->d_y1, n->d_ck_y1 + (size_t)k * N, N * 4);
+    d2d(n->d_y2, n->d_ck_y2 + (size_t)k * N, N * 4);
+    d2d(n->d_r, n->d_ck_r + (size_t)k * N, N * 4);
+    d2d(n->d_ring, n->d_ck_ring + (size_t)k * ring_n, ring_n * 8);
+}
+
+// Advance the FP32 network, splitting launches at checkpoint steps when the
+// adjoint is enabled.  Frozen lists and traces are indexed from the call's
+// first step.
+static void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
+                         float* x_trace, float* v_trace) {
+    const int64_t first = n->step;
+    int64_t left = n_steps;
+    while (left > 0) {
+        int64_t chunk = left;
+        if (n->ckpt > 0) chunk = std::min<int64_t>(left, (n->step / n->ckpt + 1) * n->ckpt - n->step);
+        const int64_t off = n->step - first;
+        launch_step_fp32(n, chunk, frz_ids, frz_ptr ? frz_ptr + off * n->n_tiles : nullptr,
+                         x_trace ? x_trace + off * n->N : nullptr, v_trace ? v_trace + off * n->N : nullptr);
+        left -= chunk;
+        if (n->ckpt > 0 && n->step % n->ckpt == 0) save_checkpoint(n, (int)(n->step / n->ckpt));
+    }
 }
 
 }  // namespace cortex
@@ -650,7 +781,7 @@ int cortex_step(cortex_net* n, int64_t n_steps) {
     require_net(n);
     require(n_steps >= 0, CORTEX_EINVAL, "n_steps must be >= 0");
     if (n->spec.precision == CORTEX_FP64_VERIFY) launch_step_fp64(n, n_steps, nullptr, nullptr, nullptr);
-    else launch_step_fp32(n, n_steps, nullptr, nullptr, nullptr, nullptr);
+    else advance_fp32(n, n_steps, nullptr, nullptr, nullptr, nullptr);
     return CORTEX_OK;
     CX_API_END
 }
@@ -662,41 +793,8 @@ int cortex_get_spikes(cortex_net* n, int64_t step0, int64_t step1, uint32_t* ste
     require(count != nullptr && capacity >= 0 && (capacity == 0 || (steps && ids)), CORTEX_EINVAL,
             "bad output buffers");
     check_device_flag(n);
-    const int64_t w0 = n->log_step0, w1 = std::min(n->log_step0 + n->log_steps, n->step);
-    bool trunc = step0 < w0 || step1 > w1;
-    const int64_t s0 = std::max(step0, w0), s1 = std::min(step1, w1);
-    std::vector<std::pair<uint32_t, uint32_t>> out;
-    if (s1 > s0) {
-        if (n->spec.precision == CORTEX_FP64_VERIFY) {
-            auto bits = download(n, n->d_raster + (size_t)(s0 - w0) * n->W64, (size_t)(s1 - s0) * n->W64);
-            for (int64_t s = s0; s < s1; ++s)
-                for (int64_t w = 0; w < n->W64; ++w) {
-                    uint64_t x = bits[(size_t)(s - s0) * n->W64 + w];
-                    while (x) {
-                        const int b = __builtin_ctzll(x);
-                        out.emplace_back((uint32_t)s, (uint32_t)(w * 64 + b));
-                        x &= x - 1;
-                    }
-                }
-        } else {
-            auto cnt = download(n, n->d_log_cnt, (size_t)(s1 - w0) * n->n_tiles);
-            auto pos = download(n, n->d_log_pos, n->n_tiles);
-            std::vector<uint64_t> base(n->n_tiles + 1);
-            CX_HIP(hipMemcpy(base.data(), n->d_log_base, base.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
-            for (int t = 0; t < n->n_tiles; ++t) {
-                auto tid = download(n, n->d_log_ids + base[t], (size_t)pos[t]);
-                uint64_t p = 0;
-                for (int64_t s = w0; s < s1; ++s) {
-                    const uint32_t c = cnt[(size_t)(s - w0) * n->n_tiles + t];
-                    if (c == 0xFFFFFFFFu) { trunc = true; break; }
-                    if (s >= s0)
-                        for (uint32_t k = 0; k < c; ++k) out.emplace_back((uint32_t)s, tid[p + k]);
-                    p += c;
-                }
-            }
-            std::sort(out.begin(), out.end());
-        }
-    }
+    bool trunc = false;
+    const auto out = collect_spikes(n, step0, step1, &trunc);
     *count = (int64_t)out.size();
     const int64_t m = std::min<int64_t>(capacity, (int64_t)out.size());
     for (int64_t i = 0; i < m; ++i) {
@@ -748,12 +846,14 @@ int cortex_run_frozen(cortex_net* n, const uint32_t* r_steps, const uint32_t* r_
     } else {
         std::vector<uint32_t> ids;
         std::vector<uint64_t> ptr;
-        frozen_lists(n, r_steps, r_ids, n_spikes, n_steps, ids, ptr);
+        std::vector<std::pair<uint32_t, uint32_t>> spikes((size_t)n_spikes);
+        for (int64_t q = 0; q < n_spikes; ++q) spikes[q] = {r_steps[q], r_ids[q]};
+        frozen_lists_at(n, n->step, spikes, n_steps, ids, ptr);
         uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
         uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
         upload(n, d_ids, ids);
         upload(n, d_ptr, ptr);
-        launch_step_fp32(n, n_steps, d_ids, d_ptr, static_cast<float*>(x_trace), static_cast<float*>(v_trace));
+        advance_fp32(n, n_steps, d_ids, d_ptr, static_cast<float*>(x_trace), static_cast<float*>(v_trace));
     }
     check_device_flag(n);
     free_scratch(n);
@@ -764,8 +864,11 @@ int cortex_run_frozen(cortex_net* n, const uint32_t* r_steps, const uint32_t* r_
 int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss) {
     CX_API_BEGIN
     require_net(n);
-    (void)vstar; (void)grad_w; (void)loss;
-    throw Error{CORTEX_EUNSUPPORTED, "adjoint not built in this library version"};
+    require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "the adjoint runs in FP32 mode");
+    require(n->ckpt > 0, CORTEX_ESTATE, "adjoint not enabled (ckpt_every = 0 at build)");
+    check_device_flag(n);
+    adjoint_backward(n, vstar, grad_w, loss);
+    free_scratch(n);
     CX_API_END
 }
 
@@ -851,7 +954,7 @@ int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, in
             for (int t = 0; t < nt; ++t) {
                 for (uint64_t e = rs[j] + off[ob + t]; e < rs[j] + off[ob + t + 1]; ++e) {
                     if (src) src[e] = j;
-                    if (tgt) tgt[e] = n->inst_n0[b] + (int64_t)t * n->T + (meta[e] & tmask);
+                    if (tgt) tgt[e] = n->inst_n0[b] + (int64_t)t * n->inst_T[b] + (meta[e] & tmask);
                     if (w) w[e] = wv[e];
                     if (d) d[e] = n->dmin + (int32_t)(meta[e] >> n->tbits);
                 }

@@ -48,7 +48,7 @@ struct GenArgs {
     uint32_t* cnt;              // [sum N_b (nt_b + 1)] counts, then cursors
     const uint64_t* inst_offbase;
     const int32_t* inst_ntiles;
-    int T;
+    const int32_t* inst_T;      // tile size per instance
     const uint64_t* row_start;
     const uint32_t* off_rel;
     void* meta;
@@ -153,7 +153,8 @@ __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_
     }
     if (MODE == kCountTiles || MODE == kFillTiles) {
         const int ntb = a.inst_ntiles[B.instance];
-        const int64_t tile_local = tl / a.T;
+        const int Tb = a.inst_T[B.instance];
+        const int64_t tile_local = tl / Tb;
         const uint64_t key = a.inst_offbase[B.instance] +
                              (uint64_t)(B.src0_local + dr.src_in_pop) * (uint64_t)(ntb + 1) +
                              (uint64_t)tile_local;
@@ -162,7 +163,7 @@ __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_
         } else {
             const uint32_t k = atomicAdd(&a.cnt[key], 1u);
             const uint64_t pos = a.row_start[src_global] + a.off_rel[key] + k;
-            const uint32_t m = (uint32_t)(tl - tile_local * a.T) |
+            const uint32_t m = (uint32_t)(tl - tile_local * Tb) |
                                ((uint32_t)(dr.d - a.dmin) << a.tbits);
             if (a.meta16) static_cast<uint16_t*>(a.meta)[pos] = (uint16_t)m;
             else static_cast<uint32_t*>(a.meta)[pos] = m;
@@ -437,7 +438,7 @@ GenArgs base_args(cortex_net* n, const Tables& t) {
     a.dt = n->spec.dt;
     a.inst_offbase = n->d_inst_offbase;
     a.inst_ntiles = n->d_inst_ntiles;
-    a.T = n->T;
+    a.inst_T = n->d_inst_T;
     return a;
 }
 

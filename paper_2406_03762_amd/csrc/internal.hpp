@@ -91,7 +91,8 @@ struct cortex_net {
     std::vector<int64_t> inst_n0, inst_N;
     std::vector<int32_t> inst_tile0, inst_ntiles;
     std::vector<uint64_t> inst_offbase;     // start of the instance's off_rel block
-    int n_tiles = 0, T = 0, BS = 512, NPT = 1;
+    int n_tiles = 0, T = 0, BS = 512, NPT = 1;   // T: largest tile (LDS and buffer stride)
+    std::vector<int32_t> inst_T;                 // tile size of each instance
     std::vector<int64_t> tile_start;
     std::vector<int32_t> tile_size, tile_inst;
     int dmin = 1, dmax = 1, R = 1, H = 64;
@@ -115,6 +116,7 @@ struct cortex_net {
     int32_t* d_tile_inst = nullptr;
     int32_t* d_inst_tile0 = nullptr;
     int32_t* d_inst_ntiles = nullptr;
+    int32_t* d_inst_T = nullptr;
     int64_t* d_inst_n0 = nullptr;
     uint64_t* d_inst_offbase = nullptr;
     // production graph
@@ -122,8 +124,7 @@ struct cortex_net {
     uint32_t* d_off_rel = nullptr;     // [sum_b N_b (nt_b + 1)]
     void* d_meta = nullptr;            // u16/u32 [E]
     void* d_w = nullptr;               // f32/bf16 [E]
-    uint32_t* d_canon = nullptr;       // [E] instance-local canonical index (adjoint)
-    uint64_t* d_inst_e0 = nullptr;     // canonical edge base per instance
+    uint32_t* d_canon = nullptr;       // [E] canonical index of each stored synapse (adjoint)
     // FP32 state
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
@@ -153,11 +154,15 @@ struct cortex_net {
     int64_t W64 = 0;
     double events_fp64 = 0;
 
-    // adjoint
+    // adjoint: checkpoints of (U, y1, y2, r) and the rings every ckpt steps
     int ckpt = 0;
     int64_t adj_steps = 0;
-    float* d_ckpt = nullptr;           // checkpoints of (U, y1, y2, r) per ckpt
-    float* d_ckpt_ring = nullptr;      // rings per checkpoint
+    int n_ckpt = 0;
+    float* d_ck_U = nullptr;           // [n_ckpt][N]
+    float* d_ck_y1 = nullptr;
+    float* d_ck_y2 = nullptr;
+    int32_t* d_ck_r = nullptr;
+    long long* d_ck_ring = nullptr;    // [n_ckpt][n_tiles][R][T]
 };
 
 namespace cortex {
@@ -176,7 +181,11 @@ void build_graph_fp64(cortex_net* n);
 void init_state(cortex_net* n);
 // step.hip
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
-                      const uint64_t* frz_ptr, float* x_trace, float* v_trace);
+                      const uint64_t* frz_ptr, float* x_trace, float* v_trace,
+                      uint8_t* m_trace = nullptr);
+// adjoint.hip
+void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss);
+void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr);
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk);
 int step_max_blocks_per_cu(cortex_net* n);
 // verify.hip

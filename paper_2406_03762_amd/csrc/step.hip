@@ -43,6 +43,7 @@ constexpr int kInline = 3;        // spike ids fetched together with a tile's st
 struct StepArgs {
     const int32_t* inst_tile0;
     const int32_t* inst_ntiles;
+    const int32_t* inst_T;
     const int64_t* inst_n0;
     const uint64_t* inst_offbase;
     const int32_t* tile_inst;
@@ -68,6 +69,7 @@ struct StepArgs {
     const uint64_t* frz_ptr;
     float* x_trace;
     float* v_trace;
+    uint8_t* m_trace;           // 1 where a neuron integrated and did not spike (adjoint)
     int64_t n0, n1, log_step0, log_steps, N;
     int n_tiles, T, R, dmin, H, W, chunk, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     const int ntb = a.inst_ntiles[b];
     const int tl = tile - tile0b;
     const int64_t n0b = a.inst_n0[b];
-    const int64_t g0 = n0b + (int64_t)tl * a.T;
+    const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
     const int tsz = a.tile_size[tile];
     const uint64_t offb = a.inst_offbase[b];
     const int T = a.T, R = a.R, H = a.H, CH = a.chunk;
@@ -362,10 +364,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         s_spk[p] = (uint32_t)(g0 + li);
                     }
                     U[k] = u_new;
-                    if (a.x_trace) {
-                        a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
-                        a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
-                    }
+                    if (a.x_trace) a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
+                    if (a.v_trace) a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
+                    if (a.m_trace) a.m_trace[(n - a.n0) * a.N + g0 + li] = (integ && !spk) ? 1 : 0;
                 }
             }
             __syncthreads();
@@ -462,12 +463,13 @@ int step_max_blocks_per_cu(cortex_net* n) {
 }
 
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
-                      const uint64_t* frz_ptr, float* x_trace, float* v_trace) {
+                      const uint64_t* frz_ptr, float* x_trace, float* v_trace, uint8_t* m_trace) {
     if (n_steps <= 0) return;
     require(n->n_thr <= kMaxThr, CORTEX_EUNSUPPORTED, "Poisson mean too large for the FP32 kernel");
     StepArgs a{};
     a.inst_tile0 = n->d_inst_tile0;
     a.inst_ntiles = n->d_inst_ntiles;
+    a.inst_T = n->d_inst_T;
     a.inst_n0 = n->d_inst_n0;
     a.inst_offbase = n->d_inst_offbase;
     a.tile_inst = n->d_tile_inst;
@@ -493,6 +495,7 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.frz_ptr = frz_ptr;
     a.x_trace = x_trace;
     a.v_trace = v_trace;
+    a.m_trace = m_trace;
     a.n0 = n->step;
     a.n1 = n->step + n_steps;
     a.log_step0 = n->log_step0;

@@ -275,3 +275,113 @@ def test_error_paths(cx):
     cnt = C.c_int64()
     rc = cx.lib().cortex_get_spikes(g._h, 0, 20, None, None, 0, C.byref(cnt))
     assert rc == cx.ETRUNC
+
+
+BATCH_SIZES = [200, 450, 1000, 2200, 5000]
+
+
+def test_batched_instances_graph_and_tiles(cx, orc):
+    spec = netspec.config4(BATCH_SIZES)
+    case("batched graph, 5 instances")
+    g = cx.Network(spec, 4)
+    o = orc.OracleNet(spec, 4)
+    assert g.E == o.E
+    start, size, inst = g.tiles()
+    # tiles never straddle instances; instances with more synapses per target
+    # get smaller tiles
+    bounds = np.cumsum([0] + BATCH_SIZES)
+    for b in range(len(BATCH_SIZES)):
+        m = inst == b
+        assert start[m][0] == bounds[b] and start[m][-1] + size[m][-1] == bounds[b + 1]
+    tmax = [size[inst == b].max() for b in range(len(BATCH_SIZES))]
+    assert tmax[-1] <= tmax[0]
+    gt, gs, gd, gw = helpers.sorted_edges(*g.graph())
+    ot, os_, od, ow = helpers.sorted_edges(*o.graph())
+    assert np.array_equal(gt, ot) and np.array_equal(gs, os_) and np.array_equal(gd, od)
+    assert np.array_equal(gw, ow.astype(np.float32).astype(np.float64))
+
+
+def test_batched_open_loop_matches_oracle(cx, orc):
+    spec = netspec.config4(BATCH_SIZES)
+    case("batched open loop")
+    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 120, 0.01, 4, 0)
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
+def test_batched_closed_loop_rates(cx, orc):
+    sizes = [1000, 2000, 4000]
+    spec = netspec.config4(sizes)
+    T = 2000
+    case("batched closed loop rates")
+    g = cx.Network(spec, 5, record_steps=T)
+    g.step(T)
+    st, ids = g.spikes(0, T)
+    o = orc.OracleNet(spec, 5)
+    o.run(T)
+    ost, oids = o.spikes()
+    rg = helpers.rates_and_cv(st, ids, spec, 500, T)
+    ro = helpers.rates_and_cv(ost, oids, spec, 500, T)
+    print("gpu", rg, "oracle", ro, flush=True)
+    for (rate_g, cv_g), (rate_o, cv_o) in zip(rg, ro):
+        assert rate_o > 1.0
+        assert abs(rate_g - rate_o) <= 0.03 * rate_o
+
+
+def _adjoint_case(cx, orc, spec, T, ckpt, seed, p_spike=0.02):
+    import torch
+    N = spec.n_neurons
+    steps, ids = netspec.refractory_raster(N, T, p_spike, seed=seed, n_ref=20)
+    vstar = netspec.target_trace(N, T, 10.0, 20.0, seed=seed + 1)
+    g = cx.Network(spec, seed, ckpt_every=ckpt, adjoint_steps=T)
+    g.run_frozen(steps, ids, T, traces=False)
+    vs = torch.tensor(vstar, dtype=torch.float32, device="cuda")
+    grad, loss = g.backward(vs)
+    o = orc.OracleNet(spec, seed)
+    gro, loss_o = o.backward(steps, ids, T, vstar.astype(np.float32).astype(np.float64))
+    return g, o, grad.cpu().numpy().astype(np.float64), loss, gro, loss_o
+
+
+@pytest.mark.parametrize("model", ["delta", "exp", "alpha"])
+def test_adjoint_matches_oracle_on_frozen_raster(cx, orc, model):
+    spec = netspec.small_brunel(model=model, n_e=400, n_i=100, c_e=40, c_i=10, delay="uniform_int",
+                                d0=2, d1=9, w_rel_sd=0.1, J=0.1 if model == "delta" else 20.0)
+    case(f"adjoint {model}")
+    g, o, gr, loss, gro, loss_o = _adjoint_case(cx, orc, spec, 260, 50, 31)
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    scale = np.abs(gro).max()
+    assert scale > 0
+    assert np.allclose(gr, gro, rtol=1e-3, atol=1e-4 * scale)
+    # canonical order of the export matches the oracle's edge order
+    canon = g.canonical()
+    src, tgt, w, d = g.graph()
+    os_, ot, ow, od = o.graph()
+    assert np.array_equal(os_[canon], src) and np.array_equal(ot[canon], tgt) and np.array_equal(od[canon], d)
+
+
+def test_adjoint_batched_instances(cx, orc):
+    spec = netspec.config4([300, 700, 1500])
+    case("adjoint batched")
+    g, o, gr, loss, gro, loss_o = _adjoint_case(cx, orc, spec, 230, 100, 41)
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    assert np.allclose(gr, gro, rtol=1e-3, atol=1e-4 * np.abs(gro).max())
+
+
+def test_adjoint_closed_loop_is_repeatable_and_restores_state(cx):
+    import torch
+    spec = netspec.config4([1000, 2000])
+    T = 300
+    case("adjoint closed loop")
+    g = cx.Network(spec, 6, ckpt_every=100, adjoint_steps=T)
+    g.step(T)
+    before = g.state()
+    vs = torch.tensor(netspec.target_trace(spec.n_neurons, T, 10.0, 20.0, seed=3), dtype=torch.float32,
+                      device="cuda")
+    g1, l1 = g.backward(vs)
+    g1 = g1.cpu().numpy().copy()
+    after = g.state()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    g2, l2 = g.backward(vs)
+    assert l1 == l2 and np.array_equal(g1, g2.cpu().numpy())
+    assert np.count_nonzero(g1) > 0
