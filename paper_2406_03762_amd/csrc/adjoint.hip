@@ -32,7 +32,7 @@ namespace {
 // Write step records and spike ids of steps [q0, q1) (from the raster) into
 // the publication buffer, as the forward kernel had published them.
 __global__ void republish_kernel(uint64_t* pub, int H, int n_tiles, int T, int64_t q0, int nq,
-                                 const uint32_t* ids, const uint64_t* ptr) {
+                                 const uint32_t* ids, const uint64_t* ptr, uint64_t n_ids) {
     const int64_t pairs = (int64_t)nq * n_tiles;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -41,7 +41,8 @@ __global__ void republish_kernel(uint64_t* pub, int H, int n_tiles, int T, int64
         const int64_t q = q0 + qi;
         const uint64_t tag = (uint64_t)(uint32_t)(q + 1) << 32;
         uint64_t* base = pub + (size_t)(q & (H - 1)) * n_tiles * (T + 1) + (size_t)tile * (T + 1);
-        const uint64_t b0 = ptr[p], b1 = ptr[p + 1];
+        const uint64_t b1 = min(ptr[p + 1], n_ids), b0 = min(ptr[p], b1);
+        if (b1 - b0 > (uint64_t)T) continue;   // a tile publishes at most T ids
         for (uint64_t k = b0; k < b1; ++k)
             __hip_atomic_store(base + 1 + (k - b0), tag | ids[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(base, tag | (uint32_t)(b1 - b0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -187,11 +188,12 @@ int grid_of(int64_t work, int bs) {
 
 }  // namespace
 
-void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr) {
+void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr,
+               uint64_t n_ids) {
     if (q1 <= q0) return;
     const int64_t pairs = (q1 - q0) * n->n_tiles;
     hipLaunchKernelGGL(republish_kernel, dim3(grid_of(pairs, 256)), dim3(256), 0, n->stream, n->d_pub, n->H,
-                       n->n_tiles, n->T, q0, (int)(q1 - q0), ids, ptr);
+                       n->n_tiles, n->T, q0, (int)(q1 - q0), ids, ptr, n_ids);
     CX_HIP(hipGetLastError());
 }
 
@@ -218,6 +220,8 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     bool trunc = false;
     const auto raster = collect_spikes(n, 0, T, &trunc);
     require(!trunc, CORTEX_ESTATE, "spike log overflowed; the raster is incomplete");
+    for (const auto& sp : raster)
+        require((int64_t)sp.first < T && (int64_t)sp.second < n->N, CORTEX_EDEVICE, "spike log holds an invalid entry");
     const int64_t N = n->N;
     const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
     const size_t pub_n = (size_t)n->H * n->n_tiles * (n->T + 1) + 8;
@@ -272,35 +276,53 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
         return v;
     };
     const int K = (int)((T + C - 1) / C);
+    // Host staging of every asynchronous upload of a segment.  The copies
+    // read these vectors when the stream reaches them, so they live at
+    // function scope and are refilled only after the stream has drained
+    // (end of each segment, or the error path below).
+    std::vector<uint32_t> rp_ids, fr_ids, src_id;
+    std::vector<uint64_t> rp_ptr, fr_ptr, src_ptr, spk_ptr;
+    std::vector<int64_t> spk_step;
     try {
         for (int k = K - 1; k >= 0; --k) {
             const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
             restore_checkpoint(n, k);
             n->step = s0;
+            // Records left in the publication buffer by the forward run or a
+            // later segment carry the same step tags as this replay's and
+            // may list the same spikes in another order; a reader mixing two
+            // of them would deliver a spike twice and drop another.  Clear
+            // the buffer (tag 0 matches no step) before republishing.
+            dev_zero(n, n->d_pub, pub_n * 8);
             // spikes of [s0 - d_min, s0) are published but not yet delivered at s0
             const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
             if (s0 > r0) {
-                std::vector<uint32_t> ids;
-                std::vector<uint64_t> ptr;
-                frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, ids, ptr);
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
-                if (!ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                republish(n, r0, s0, d_ids, d_ptr);
+                frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, rp_ids, rp_ptr);
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, rp_ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, rp_ptr.size(), true);
+                if (!rp_ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, rp_ids.data(), rp_ids.size() * 4, hipMemcpyHostToDevice,
+                                          n->stream));
+                CX_HIP(hipMemcpyAsync(d_ptr, rp_ptr.data(), rp_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                republish(n, r0, s0, d_ids, d_ptr, rp_ids.size());
             }
             // bit-exact replay of the segment on the frozen raster
             {
-                std::vector<uint32_t> ids;
-                std::vector<uint64_t> ptr;
-                frozen_lists_at(n, s0, slice(s0, s1), len, ids, ptr);
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
-                if (!ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                launch_step_fp32(n, len, d_ids, d_ptr, nullptr, vtr, mtr);
+                frozen_lists_at(n, s0, slice(s0, s1), len, fr_ids, fr_ptr);
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, fr_ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, fr_ptr.size(), true);
+                if (!fr_ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, fr_ids.data(), fr_ids.size() * 4, hipMemcpyHostToDevice,
+                                          n->stream));
+                CX_HIP(hipMemcpyAsync(d_ptr, fr_ptr.data(), fr_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                launch_step_fp32(n, len, d_ids, d_ptr, fr_ids.size(), nullptr, vtr, mtr);
+                CX_HIP(hipStreamSynchronize(n->stream));
+                int32_t e = 0;
+                CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
+                if (e != 0) {
+                    n->failed = true;
+                    throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
+                }
             }
             // reverse recursion over the segment
             ReverseArgs ra{};
@@ -324,9 +346,10 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 per_inst[lo].emplace_back(sp.second, (int64_t)sp.first);
             }
             // CSR: instance -> distinct sources -> their spike steps
-            std::vector<uint64_t> src_ptr(n->n_inst + 1, 0), spk_ptr;
-            std::vector<uint32_t> src_id;
-            std::vector<int64_t> spk_step;
+            src_ptr.assign(n->n_inst + 1, 0);
+            spk_ptr.clear();
+            src_id.clear();
+            spk_step.clear();
             for (int b = 0; b < n->n_inst; ++b) {
                 auto& v = per_inst[b];
                 std::sort(v.begin(), v.end());
@@ -367,6 +390,8 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
         CX_HIP(hipGetLastError());
         CX_HIP(hipMemcpyAsync(loss_out, dloss, 8, hipMemcpyDeviceToHost, n->stream));
     } catch (...) {
+        // drain queued uploads before the staging vectors go away
+        (void)hipStreamSynchronize(n->stream);
         n->log_steps = saved_log_steps;
         throw;
     }

@@ -154,10 +154,12 @@ void dev_zero(cortex_net* n, void* p, size_t bytes) {
     if (bytes) CX_HIP(hipMemsetAsync(p, 0, bytes, n->stream));
 }
 
+// Host-to-device copy that has completed on return, so `src` may be freed.
 template <class T>
 static void upload(cortex_net* n, T* dst, const std::vector<T>& src) {
-    if (!src.empty())
-        CX_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, n->stream));
+    if (src.empty()) return;
+    CX_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, n->stream));
+    CX_HIP(hipStreamSynchronize(n->stream));
 }
 
 template <class T>
@@ -703,14 +705,14 @@ void restore_checkpoint(cortex_net* n, int k) {
 // adjoint is enabled.  Frozen lists and traces are indexed from the call's
 // first step.
 static void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
-                         float* x_trace, float* v_trace) {
+                         uint64_t frz_n, float* x_trace, float* v_trace) {
     const int64_t first = n->step;
     int64_t left = n_steps;
     while (left > 0) {
         int64_t chunk = left;
         if (n->ckpt > 0) chunk = std::min<int64_t>(left, (n->step / n->ckpt + 1) * n->ckpt - n->step);
         const int64_t off = n->step - first;
-        launch_step_fp32(n, chunk, frz_ids, frz_ptr ? frz_ptr + off * n->n_tiles : nullptr,
+        launch_step_fp32(n, chunk, frz_ids, frz_ptr ? frz_ptr + off * n->n_tiles : nullptr, frz_n,
                          x_trace ? x_trace + off * n->N : nullptr, v_trace ? v_trace + off * n->N : nullptr);
         left -= chunk;
         if (n->ckpt > 0 && n->step % n->ckpt == 0) save_checkpoint(n, (int)(n->step / n->ckpt));
@@ -781,7 +783,7 @@ int cortex_step(cortex_net* n, int64_t n_steps) {
     require_net(n);
     require(n_steps >= 0, CORTEX_EINVAL, "n_steps must be >= 0");
     if (n->spec.precision == CORTEX_FP64_VERIFY) launch_step_fp64(n, n_steps, nullptr, nullptr, nullptr);
-    else advance_fp32(n, n_steps, nullptr, nullptr, nullptr, nullptr);
+    else advance_fp32(n, n_steps, nullptr, nullptr, 0, nullptr, nullptr);
     return CORTEX_OK;
     CX_API_END
 }
@@ -853,7 +855,8 @@ int cortex_run_frozen(cortex_net* n, const uint32_t* r_steps, const uint32_t* r_
         uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, ptr.size(), true);
         upload(n, d_ids, ids);
         upload(n, d_ptr, ptr);
-        advance_fp32(n, n_steps, d_ids, d_ptr, static_cast<float*>(x_trace), static_cast<float*>(v_trace));
+        advance_fp32(n, n_steps, d_ids, d_ptr, ids.size(), static_cast<float*>(x_trace),
+                     static_cast<float*>(v_trace));
     }
     check_device_flag(n);
     free_scratch(n);
@@ -869,6 +872,7 @@ int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* lo
     check_device_flag(n);
     adjoint_backward(n, vstar, grad_w, loss);
     free_scratch(n);
+    return CORTEX_OK;
     CX_API_END
 }
 

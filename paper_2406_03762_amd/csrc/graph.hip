@@ -425,6 +425,7 @@ Tables upload_tables(cortex_net* n) {
     CX_HIP(hipMemcpyAsync(t.pop_t0, pt0.data(), t.n_pops * sizeof(int64_t), hipMemcpyHostToDevice, n->stream));
     CX_HIP(hipMemcpyAsync(t.pop_blk0, pb0.data(), t.n_pops * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
     CX_HIP(hipMemcpyAsync(t.pop_blk1, pb1.data(), t.n_pops * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    CX_HIP(hipStreamSynchronize(n->stream));   // the host tables above go out of scope
     return t;
 }
 

@@ -180,12 +180,15 @@ void build_graph_fp32(cortex_net* n);
 void build_graph_fp64(cortex_net* n);
 void init_state(cortex_net* n);
 // step.hip
+// Frozen runs pass the per-(step, tile) id lists (frz_ptr into frz_ids,
+// frz_n ids in all); the kernel clamps every list to [0, frz_n).
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
-                      const uint64_t* frz_ptr, float* x_trace, float* v_trace,
+                      const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
                       uint8_t* m_trace = nullptr);
 // adjoint.hip
 void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss);
-void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr);
+void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr,
+               uint64_t n_ids);
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk);
 int step_max_blocks_per_cu(cortex_net* n);
 // verify.hip

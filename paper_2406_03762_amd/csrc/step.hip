@@ -67,6 +67,7 @@ struct StepArgs {
     int32_t* err;
     const uint32_t* frz_ids;
     const uint64_t* frz_ptr;
+    uint64_t frz_n;             // ids in frz_ids
     float* x_trace;
     float* v_trace;
     uint8_t* m_trace;           // 1 where a neuron integrated and did not spike (adjoint)
@@ -236,6 +237,14 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                                             (size_t)(tile0b + tt) * pub_tile + 1 + rnk;
                         j = (uint32_t)wait_tag(w, coherent_load(w), (uint32_t)(q + 1), spin_max, a.err, &bail);
                     }
+                    if (bail) {
+                        // the id never arrived: the kernel stops after this
+                        // chunk, so the entry is only kept in range
+                        s_beg[k] = 0;
+                        s_len[k] = 0;
+                        s_qof[k] = 0;
+                        continue;
+                    }
                     const uint64_t rs = a.row_start[j];
                     const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
                     const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
@@ -309,9 +318,12 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             const int64_t n = t0 + si;
             __syncthreads();
             if (a.frz_ptr) {
-                const uint64_t f0 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile];
-                const uint64_t f1 = a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1];
-                for (uint64_t q = f0 + tid; q < f1; q += bs) s_frz[a.frz_ids[q] - g0] = 1;
+                const uint64_t f0 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile], a.frz_n);
+                const uint64_t f1 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1], a.frz_n);
+                for (uint64_t q = f0 + tid; q < f1; q += bs) {
+                    const int64_t li = (int64_t)a.frz_ids[q] - g0;
+                    if (li >= 0 && li < tsz) s_frz[li] = 1;
+                }
                 __syncthreads();
             }
             const int slot = (int)(n % R);
@@ -463,7 +475,8 @@ int step_max_blocks_per_cu(cortex_net* n) {
 }
 
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
-                      const uint64_t* frz_ptr, float* x_trace, float* v_trace, uint8_t* m_trace) {
+                      const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
+                      uint8_t* m_trace) {
     if (n_steps <= 0) return;
     require(n->n_thr <= kMaxThr, CORTEX_EUNSUPPORTED, "Poisson mean too large for the FP32 kernel");
     StepArgs a{};
@@ -493,6 +506,7 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.err = n->d_err;
     a.frz_ids = frz_ids;
     a.frz_ptr = frz_ptr;
+    a.frz_n = frz_n;
     a.x_trace = x_trace;
     a.v_trace = v_trace;
     a.m_trace = m_trace;
