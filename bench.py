@@ -67,6 +67,69 @@ def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
     }
 
 
+def batched_and_adjoint(cx, torch, seed, sim_steps):
+    """Secondary figures on the batched workload (64 Brunel instances of
+    log-uniform size 1,250-50,000, delta LIF, 1.5 ms delays): one persistent
+    launch for all instances vs the same instances run one after another, and
+    the adjoint (backward) against its forward."""
+    import netspec
+    spec = netspec.config4()
+    out = {"workload": "64 balanced delta-LIF instances, N log-uniform 1,250-50,000 (seeded), "
+                       "in-degree 10% of each population, delay 1.5 ms, FP32",
+           "sim_steps": sim_steps}
+    log("[bench] batched: building 64 instances")
+    net = cx.Network(spec, seed)
+    out["neurons"], out["synapses"] = net.N, net.E
+    net.step(200)
+    torch.cuda.synchronize()
+    e0 = net.query("EVENTS")
+    t0 = time.perf_counter()
+    net.step(sim_steps)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    ev_b = net.query("EVENTS") - e0
+    net.close()
+    del net
+    log(f"[bench] batched: {ev_b / dt_b:.3e} events/s")
+    ev_s, dt_s = 0, 0.0
+    for b, inst in enumerate(spec.instances):
+        one = netspec.NetSpec(**{**spec.__dict__, "instances": [inst]})
+        g = cx.Network(one, seed + 1000 + b)
+        g.step(200)
+        torch.cuda.synchronize()
+        e0 = g.query("EVENTS")
+        t0 = time.perf_counter()
+        g.step(sim_steps)
+        torch.cuda.synchronize()
+        dt_s += time.perf_counter() - t0
+        ev_s += g.query("EVENTS") - e0
+        g.close()
+    log(f"[bench] sequential: {ev_s / dt_s:.3e} events/s")
+    out.update(events_per_s=ev_b / dt_b, sequential_events_per_s=ev_s / dt_s,
+               speedup=(ev_b / dt_b) / (ev_s / dt_s))
+    # adjoint: checkpointed forward, then the gradient of the voltage loss
+    log("[bench] adjoint: forward with checkpoints")
+    net = cx.Network(spec, seed, ckpt_every=100, adjoint_steps=sim_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.step(sim_steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    ev_f = net.query("EVENTS")
+    vstar = torch.empty((sim_steps, net.N), dtype=torch.float32, device="cuda").uniform_(10.0, 20.0)
+    grad = torch.empty(net.E, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, loss = net.backward(vstar, grad)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    log(f"[bench] adjoint: forward {t_fwd:.3f}s backward {t_bwd:.3f}s loss {loss:.4g}")
+    out["adjoint"] = {"forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+                      "forward_events": ev_f, "loss": loss, "checkpoint_every_steps": 100}
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,9 +139,13 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--steps-per-sync", type=int, default=0,
+                    help="time steps per spike exchange (0 = the planner's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=4000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size before the timed region "
                          "(a known-size reference for HBM byte counters)")
@@ -100,14 +167,17 @@ def main():
     spec = netspec.config2()
     log("[bench] building config2 network")
     t0 = time.perf_counter()
-    net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size)
+    net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size,
+                     steps_per_sync=args.steps_per_sync)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     E = net.E
     B_rec = net.query("EDGE_BYTES")
     n_tiles = net.query("TILES")
+    tile_size = net.query("TILE_SIZE")
+    block_size = net.query("BLOCK_SIZE")
     log(f"[bench] built: N={net.N} E={E} tiles={n_tiles} T={net.query('TILE_SIZE')} "
-        f"R={net.query('RING_SLOTS')} BS={net.query('BLOCK_SIZE')} rec={B_rec}B "
+        f"R={net.query('RING_SLOTS')} W={net.query('STEPS_PER_SYNC')} BS={net.query('BLOCK_SIZE')} rec={B_rec}B "
         f"in {t_build:.1f}s")
 
     if args.copy_calibration_mib > 0:
@@ -159,6 +229,16 @@ def main():
         cpu = cpu_baseline(spec, rate_hz, args.seed, args.cpu_targets, args.cpu_steps)
         log(f"[bench] cpu baseline {cpu['value']:.3e} events/s")
 
+    net.close()
+    del net
+    batched = None
+    if not args.no_batched:
+        try:
+            batched = batched_and_adjoint(cx, torch, 4, args.batched_steps)
+        except cx.CortexError as e:
+            log(f"[bench] batched/adjoint leg failed: {e}")
+            batched = {"error": str(e)}
+
     out = {
         "metric": "synaptic events/s (1 GPU)",
         "value": ev_per_s,
@@ -177,11 +257,11 @@ def main():
                         "in-degree 9,000 E + 2,250 I, 1.27e9 synapses, weights Normal(J, (0.1J)^2) "
                         "as PSP peaks, delays uniform 0.5-3.0 ms, dt 0.1 ms, FP32; "
                         f"one step = {args.sim_steps} time steps ({args.sim_steps * spec.dt:.0f} ms)",
-            "neurons": net.N,
+            "neurons": spec.n_neurons,
             "synapses": E,
             "tiles": n_tiles,
-            "tile_size": net.query("TILE_SIZE"),
-            "block_size": net.query("BLOCK_SIZE"),
+            "tile_size": tile_size,
+            "block_size": block_size,
             "record_bytes": B_rec,
         },
         "rtf": wall / sim_s,
@@ -202,9 +282,9 @@ def main():
         },
         "cpu_baseline": cpu,
         "graph_build_s": t_build,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
-    net.close()
 
 
 if __name__ == "__main__":

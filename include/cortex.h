@@ -113,7 +113,7 @@ typedef struct {
     int32_t ckpt_every;       /* adjoint checkpoint interval in steps; 0 = no adjoint */
     int64_t adjoint_steps;    /* longest forward window the adjoint covers */
     int32_t spin_limit_log2;  /* device wait limit, 2^k polls (0 = default 22) */
-    int32_t steps_per_sync;   /* FP32: time steps per exchange of spikes, 1..d_min (0 = auto) */
+    int32_t steps_per_sync;   /* FP32: time steps per exchange of spikes, 1..min(d_min, 8) (0 = auto) */
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device
@@ -208,7 +208,8 @@ enum {
     CORTEX_Q_EDGE_BYTES = 11,     /* bytes of one stored synapse record */
     CORTEX_Q_BLOCK_SIZE = 12,
     CORTEX_Q_LDS_BYTES = 13,      /* workgroup-local memory per workgroup */
-    CORTEX_Q_OFFSET_BYTES = 14    /* bytes of the per-(source, tile) offset table */
+    CORTEX_Q_OFFSET_BYTES = 14,   /* bytes of the per-(source, tile) offset table */
+    CORTEX_Q_STEPS_PER_SYNC = 15  /* FP32: time steps per spike exchange chosen at build */
 };
 /* Scalar facts about the network into *value.  EVENTS and SPIKES
    synchronise. */

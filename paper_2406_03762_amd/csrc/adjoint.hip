@@ -58,7 +58,7 @@ struct ReverseArgs {
     double* a1;
     double* a2;
     uint8_t* m_next;
-    double* loss;
+    double* loss_part;     // [gridDim.x] per-block partial sums of the loss
     const int64_t* inst_n0;
     const int64_t* inst_N;
     int n_inst;
@@ -74,9 +74,9 @@ struct ReverseArgs {
 //        a1_n = m_{n+1} P31 aU_{n+1} + P21s a2_{n+1} + P11 a1_{n+1}, g_n = jump a1_n;
 // delta: g_n = m_n aU_n.
 __global__ void __launch_bounds__(256) reverse_kernel(ReverseArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double lsum = 0.0;
-    if (i < a.N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
+         i += (int64_t)gridDim.x * blockDim.x) {
         int lo = 0, hi = a.n_inst;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -112,7 +112,8 @@ __global__ void __launch_bounds__(256) reverse_kernel(ReverseArgs a) {
         a.a2[i] = a2;
         a.m_next[i] = (uint8_t)mn;
     }
-    // block reduction of the loss, one double atomic per block (not delivery)
+    // block reduction of the loss into this block's slot; the slots are
+    // summed in a fixed order afterwards, so the loss is reproducible
     __shared__ double red[256];
     red[threadIdx.x] = lsum;
     __syncthreads();
@@ -120,7 +121,23 @@ __global__ void __launch_bounds__(256) reverse_kernel(ReverseArgs a) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(a.loss, red[0]);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = red[0];
+}
+
+// loss += sum of the per-block partials, in block order (one workgroup).
+__global__ void __launch_bounds__(256) loss_sum_kernel(const double* part, int n_part, double* loss) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const int per = (n_part + 255) / 256;
+    const int b0 = min(n_part, (int)threadIdx.x * per), b1 = min(n_part, b0 + per);
+    for (int b = b0; b < b1; ++b) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss += red[0];
 }
 
 struct WgradArgs {
@@ -253,6 +270,8 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     double* a2 = dev_alloc_t<double>(n, N, true);
     uint8_t* mnext = dev_alloc_t<uint8_t>(n, N, true);
     double* dloss = dev_alloc_t<double>(n, 1, true);
+    const int rev_grid = grid_of(N, 256);
+    double* dloss_part = dev_alloc_t<double>(n, rev_grid, true);
     float* grad = dev_alloc_t<float>(n, n->E, true);
     int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
     CX_HIP(hipMemcpyAsync(inst_N, n->inst_N.data(), n->n_inst * 8, hipMemcpyHostToDevice, n->stream));
@@ -327,12 +346,14 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             // reverse recursion over the segment
             ReverseArgs ra{};
             ra.vtr = vtr; ra.mtr = mtr; ra.vstar = vstar; ra.gtr = gtr;
-            ra.aU = aU; ra.a1 = a1; ra.a2 = a2; ra.m_next = mnext; ra.loss = dloss;
+            ra.aU = aU; ra.a1 = a1; ra.a2 = a2; ra.m_next = mnext; ra.loss_part = dloss_part;
             ra.inst_n0 = n->d_inst_n0; ra.inst_N = inst_N; ra.n_inst = n->n_inst;
             ra.N = N; ra.s0 = s0; ra.len = len; ra.T = T; ra.model = n->spec.model;
             ra.P22 = n->k.P22; ra.P11 = n->k.P11; ra.P21 = n->k.P21; ra.P31 = n->k.P31;
             ra.P32 = n->k.P32; ra.P21s = n->k.P21s; ra.P22s = n->k.P22s; ra.jump = n->k.jump;
-            hipLaunchKernelGGL(reverse_kernel, dim3(grid_of(N, 256)), dim3(256), 0, n->stream, ra);
+            hipLaunchKernelGGL(reverse_kernel, dim3(rev_grid), dim3(256), 0, n->stream, ra);
+            CX_HIP(hipGetLastError());
+            hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, n->stream, dloss_part, rev_grid, dloss);
             CX_HIP(hipGetLastError());
             // sources whose arrivals may land in [s0, s1), grouped by instance
             const auto spk = slice(s0 - n->dmax, s1 - n->dmin);

@@ -392,23 +392,40 @@ static void plan_tiles(cortex_net* n) {
         for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
             const int64_t cap = (int64_t)n_cu * per_cu;
             const int bs = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu));
-            const int Tcap = bs <= 512 ? 4 * bs : 2 * bs;
-            double lo = 1.0, hi = 1.0;
-            for (int b = 0; b < n->n_inst; ++b) hi = std::max(hi, K[b] * (double)n->inst_N[b]);
-            if (tiles_of(sizes_for(hi, Tcap)) > cap) continue;
-            for (int it = 0; it < 100 && hi - lo > 0.5; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                if (tiles_of(sizes_for(mid, Tcap)) <= cap) hi = mid; else lo = mid;
-            }
-            auto cand = sizes_for(hi, Tcap);
-            const int Tm = *std::max_element(cand.begin(), cand.end());
-            int c = 1024;
-            const size_t lds = lds_for(Tm, ntb_max_of(cand), per_cu, &c);
-            if (lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
-                Tb = cand;
-                BS = bs;
-                chunk = c;
-                found = true;
+            int Tcap = bs <= 512 ? 4 * bs : 2 * bs;
+            double hi0 = 1.0;
+            for (int b = 0; b < n->n_inst; ++b) hi0 = std::max(hi0, K[b] * (double)n->inst_N[b]);
+            // Balance synapses per tile (bisection on the per-tile synapse
+            // budget), then cap tiles whose input rings would overflow the
+            // workgroup's share of LDS and balance again.
+            for (int pass = 0; pass < 4 && !found; ++pass) {
+                if (tiles_of(sizes_for(hi0, Tcap)) > cap) break;
+                double lo = 1.0, hi = hi0;
+                for (int it = 0; it < 100 && hi - lo > 0.5; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (tiles_of(sizes_for(mid, Tcap)) <= cap) hi = mid; else lo = mid;
+                }
+                auto cand = sizes_for(hi, Tcap);
+                const int Tm = *std::max_element(cand.begin(), cand.end());
+                const int ntbm = ntb_max_of(cand);
+                int c = 1024;
+                const size_t lds = lds_for(Tm, ntbm, per_cu, &c);
+                if (lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
+                    Tb = cand;
+                    BS = bs;
+                    chunk = c;
+                    found = true;
+                    break;
+                }
+                // largest tile whose LDS fits at this occupancy
+                int tl = 1, th = Tm;
+                while (th - tl > 1) {
+                    const int mid = (tl + th) / 2;
+                    int cc = 128;
+                    if (lds_for(mid, ntbm, per_cu, &cc) * per_cu <= lds_cu) tl = mid; else th = mid;
+                }
+                if (tl >= Tcap) break;
+                Tcap = tl;
             }
         }
         require(found, CORTEX_EUNSUPPORTED,
@@ -584,12 +601,22 @@ static void build(cortex_net* n) {
         n->dmax = dmax;
         // spikes are exchanged every W steps (W <= d_min keeps every input on
         // time); pending arrivals then span d_max - d_min + W steps
-        n->W = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
-        require(n->W >= 1 && n->W <= dmin, CORTEX_EINVAL, "steps_per_sync must lie in [1, d_min]");
-        n->R = dmax - dmin + n->W;
-        n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+        // fewer steps per exchange shorten the rings when a plan does not
+        // fit workgroup-local memory
+        const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
+        require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
+        for (int W = W0;; W = std::max(1, W / 2)) {
+            n->W = W;
+            n->R = dmax - dmin + n->W;
+            n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+            try {
+                plan_tiles(n);
+                break;
+            } catch (const Error& e) {
+                if (e.status != CORTEX_EUNSUPPORTED || W == 1 || s.steps_per_sync > 0) throw;
+            }
+        }
         n->fx = fixed_point_bits(n);
-        plan_tiles(n);
         upload_tables_fp32(n);
         build_graph_fp32(n);
         alloc_state_fp32(n);
@@ -1017,6 +1044,7 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
             *value = (int64_t)off_len * 4;
             break;
         }
+        case CORTEX_Q_STEPS_PER_SYNC: *value = fp64 ? 1 : n->W; break;
         case CORTEX_Q_EVENTS:
         case CORTEX_Q_SPIKES: {
             require(!n->failed, CORTEX_ESTATE, "network failed earlier");

@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
 constexpr int kInline = 3;        // spike ids fetched together with a tile's step record
+constexpr int kBlk = 512;         // 64-edge blocks per piece of a delivery chunk
 
 struct StepArgs {
     const int32_t* inst_tile0;
@@ -135,22 +136,24 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T);
     uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + CH);     // CH + 1
     uint32_t* s_qof = s_len + CH + 1;                               // CH
-    uint32_t* s_spk = s_qof + CH;                                   // T
-    uint32_t* s_pc = s_spk + T;                                     // pairs_max + 1
+    uint32_t* s_spk = s_qof + CH;                                   // W * T (spikes per step of a window)
+    uint32_t* s_pc = s_spk + (size_t)a.W * T;                       // pairs_max + 1
     uint32_t* s_pid = s_pc + pairs_max + 1;                         // pairs_max * kInline
     uint32_t* s_wsum = s_pid + (size_t)pairs_max * kInline;         // 20
     int* s_misc = reinterpret_cast<int*>(s_wsum + 20);              // 4
-    unsigned char* s_frz = reinterpret_cast<unsigned char*>(s_misc + 4);
+    int* s_cnt = s_misc + 4;                                        // 8 (spike count per step of a window)
+    uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_cnt + 8);      // T (bit si: frozen spike at step si)
+    uint32_t* s_thr = s_frz + T;                                    // kMaxThr Poisson thresholds
+    unsigned char* s_kcb = reinterpret_cast<unsigned char*>(s_thr + kMaxThr);  // 2 x 8 x T Poisson counts
+    uint32_t* s_blk = reinterpret_cast<uint32_t*>(s_kcb + (size_t)16 * T);        // kBlk
 
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
-    uint64_t pw0[NPT], pw1[NPT], pw2[NPT], pw3[NPT];   // Poisson words of the current 8-step block
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int li = tid + k * bs;
         U[k] = Y1[k] = Y2[k] = 0.f;
         RF[k] = 0;
-        pw0[k] = pw1[k] = pw2[k] = pw3[k] = 0;
         if (li < tsz) {
             U[k] = a.U[g0 + li];
             RF[k] = a.r[g0 + li];
@@ -161,15 +164,63 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     for (int i = tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
     for (int i = tid; i < T; i += bs) s_frz[i] = 0;
     if (tid == 0) { s_misc[0] = 0; s_misc[1] = 0; }
+    if (tid < 8) s_cnt[tid] = 0;
+    if (tid < kMaxThr) s_thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xFFFFFFFFu;
     uint64_t log_pos = a.log_pos[tile];
     const uint64_t log_b = a.log_base[tile], log_cap = a.log_base[tile + 1] - log_b;
     uint64_t ev = 0, nspk = 0;
     const int64_t spin_max = (int64_t)1 << a.spin_log2;
     bool bail = false;
+    int64_t kc_blk[2] = {-1, -1};   // 8-step blocks held in s_kcb (same in every thread)
     __syncthreads();
 
     for (int64_t t0 = a.n0; t0 < a.n1; t0 += a.W) {
         const int wn = (int)min((int64_t)a.W, a.n1 - t0);
+        // Per-window work that does not depend on the network state (frozen
+        // spike marks, Poisson counts) runs while the step records are in
+        // flight.  Readers are separated from it by a workgroup barrier.
+        bool marked = false, prepared = false;
+        auto mark_frozen = [&]() {
+            if (a.frz_ptr) {
+                for (int si = 0; si < wn; ++si) {
+                    const int64_t n = t0 + si;
+                    const uint64_t f0 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile], a.frz_n);
+                    const uint64_t f1 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1], a.frz_n);
+                    for (uint64_t q = f0 + tid; q < f1; q += bs) {
+                        const int64_t li = (int64_t)a.frz_ids[q] - g0;
+                        if (li >= 0 && li < tsz) atomicOr(&s_frz[li], 1u << si);
+                    }
+                }
+            }
+            marked = true;
+        };
+        // Poisson counts, 8 steps of one neuron per Philox call, for the 8-step
+        // blocks the window touches; the two most recent blocks stay in
+        // workgroup-local memory, so each block is generated once
+        auto prepare = [&]() {
+            const int64_t blk0 = t0 >> 3, blk1 = (t0 + wn - 1) >> 3;
+            for (int64_t blk = blk0; blk <= blk1; ++blk) {
+                if (kc_blk[blk & 1] == blk) continue;
+                unsigned char* dst = s_kcb + (size_t)(blk & 1) * 8 * T;
+                for (int li = tid; li < tsz; li += bs) {
+                    const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)blk, 0, kTagPoisson, a.seed,
+                                             (uint64_t)b);
+#pragma unroll
+                    for (int sub = 0; sub < 8; ++sub) {
+                        const uint64_t word = p.v[sub >> 1];
+                        const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+                        // inversion: the count is the number of thresholds at
+                        // or below u (the table is increasing; unused entries
+                        // are 2^32 - 1 and end the scan)
+                        int kc = 0;
+                        while (kc < kMaxThr && s_thr[kc] != 0xFFFFFFFFu && u >= s_thr[kc]) ++kc;
+                        dst[sub * T + li] = (unsigned char)kc;
+                    }
+                }
+                kc_blk[blk & 1] = blk;
+            }
+            prepared = true;
+        };
         // ------------------------------------------------------------ deliver
         const int64_t q_hi = t0 - a.dmin + wn;
         const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
@@ -195,6 +246,8 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         for (int k = 0; k < kInline; ++k) idw[u][k] = coherent_load(base[u] + 1 + k);
                     }
                 }
+                if (!marked) mark_frozen();
+                if (!prepared) prepare();
 #pragma unroll
                 for (int u = 0; u < kP; ++u) {
                     const int p = p0 + tid + u * bs;
@@ -261,45 +314,50 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
                 if (tid == 0) s_len[cn] = EL;
                 __syncthreads();
+                // The flattened edges are walked in pieces of at most 64 * kBlk;
+                // s_blk[b] is the segment holding the piece's edge 64 b, so a
+                // lane starts its segment search next to its edge
+                for (uint32_t pc0 = 0; pc0 < EL; pc0 += 64u * kBlk) {
+                const uint32_t pc1 = min(EL, pc0 + 64u * kBlk);
+                for (int k = tid; k < cn; k += bs) {
+                    const uint32_t lo = max(s_len[k], pc0), hi = min(s_len[k + 1], pc1);
+                    for (uint32_t bb = (lo + 63u) >> 6; (bb << 6) < hi; ++bb) s_blk[bb - (pc0 >> 6)] = (uint32_t)k;
+                }
+                __syncthreads();
                 // each wave walks a contiguous range of the flattened
                 // (spike, synapse) space; a lane advances its segment index
-                const uint32_t per = ((EL + n_waves - 1) / n_waves + 63) & ~63u;
-                const uint32_t f_beg = min(EL, (uint32_t)wave * per);
-                const uint32_t f_end = min(EL, f_beg + per);
+                const uint32_t per = ((pc1 - pc0 + n_waves - 1) / n_waves + 63) & ~63u;
+                const uint32_t f_beg = pc0 + min(pc1 - pc0, (uint32_t)wave * per);
+                const uint32_t f_end = min(pc1, f_beg + per);
                 uint32_t f = f_beg + lane;
-                int seg = (f < f_end) ? seg_of(s_len, cn, f) : 0;
                 while (f < f_end) {
-                    constexpr int U4 = 8;
-                    uint64_t e[U4];
-                    int sq[U4];
-                    bool on[U4];
+                    // all loads of a batch are issued before any is used; the
+                    // step offset of each edge (< 8) is kept in 4-bit fields
+                    constexpr int U4 = 16;
+                    uint32_t m[U4];
+                    float wv[U4];
+                    uint32_t qpk[U4 / 8];
+#pragma unroll
+                    for (int h = 0; h < U4 / 8; ++h) qpk[h] = 0;
 #pragma unroll
                     for (int u = 0; u < U4; ++u) {
                         const uint32_t fu = f + 64u * u;
-                        on[u] = fu < f_end;
-                        e[u] = 0;
-                        sq[u] = 0;
-                        if (on[u]) {
-                            while (s_len[seg + 1] <= fu) ++seg;
-                            e[u] = s_beg[seg] + (fu - s_len[seg]);
-                            sq[u] = (int)s_qof[seg];
-                        }
-                    }
-                    uint32_t m[U4];
-                    float wv[U4];
-#pragma unroll
-                    for (int u = 0; u < U4; ++u) {
                         m[u] = 0;
                         wv[u] = 0.f;
-                        if (on[u]) {
-                            m[u] = static_cast<const META*>(a.meta)[e[u]];
-                            wv[u] = load_w(a.w, e[u], WBF16);
+                        if (fu < f_end) {
+                            int seg = (int)s_blk[((fu - (uint32_t)lane) - pc0) >> 6];
+                            while (s_len[seg + 1] <= fu) ++seg;
+                            const uint64_t e = s_beg[seg] + (fu - s_len[seg]);
+                            qpk[u >> 3] |= (s_qof[seg] | 8u) << (4 * (u & 7));
+                            m[u] = static_cast<const META*>(a.meta)[e];
+                            wv[u] = load_w(a.w, e, WBF16);
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < U4; ++u) {
-                        if (on[u]) {
-                            int sl = base_slot + sq[u] + (int)(m[u] >> a.tbits);
+                        const uint32_t q = (qpk[u >> 3] >> (4 * (u & 7))) & 15u;
+                        if (q & 8u) {
+                            int sl = base_slot + (int)(q & 7u) + (int)(m[u] >> a.tbits);
                             if (sl >= R) sl -= R;
                             const long long iv = __float2ll_rn(wv[u] * a.fx_scale);
                             atomicAdd(reinterpret_cast<unsigned long long*>(&ring[sl * T + (m[u] & tmask)]),
@@ -308,41 +366,35 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     }
                     f += 64u * U4;
                 }
+                __syncthreads();   // s_blk is refilled for the next piece
+                }
                 ev += EL;
                 __syncthreads();
             }
             if (s_misc[1]) break;
         }
         // ------------------------------------------------------------ update
-        for (int si = 0; si < wn; ++si) {
-            const int64_t n = t0 + si;
-            __syncthreads();
-            if (a.frz_ptr) {
-                const uint64_t f0 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile], a.frz_n);
-                const uint64_t f1 = min(a.frz_ptr[(n - a.n0) * a.n_tiles + tile + 1], a.frz_n);
-                for (uint64_t q = f0 + tid; q < f1; q += bs) {
-                    const int64_t li = (int64_t)a.frz_ids[q] - g0;
-                    if (li >= 0 && li < tsz) s_frz[li] = 1;
-                }
-                __syncthreads();
-            }
-            const int slot = (int)(n % R);
-            const int sub = (int)(n & 7);
+        // Every input of the window's steps has been delivered (W <= d_min),
+        // so each thread advances its neurons through all wn steps without
+        // workgroup barriers; spikes go to per-step lists.
+        // threads whose waves had no synapses to load (or a window without
+        // deliveries) finish the per-window work here; the barrier is taken
+        // by every thread
+        if (!marked) mark_frozen();
+        if (!prepared) prepare();
+        __syncthreads();
+        const int slot0 = (int)(t0 % R);
 #pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                const int li = tid + k * bs;
-                if (li < tsz) {
+        for (int k = 0; k < NPT; ++k) {
+            const int li = tid + k * bs;
+            if (li < tsz) {
+                const uint32_t frz = a.frz_ptr ? s_frz[li] : 0u;
+                int slot = slot0;
+                for (int si = 0; si < wn; ++si, slot = (slot + 1 == R) ? 0 : slot + 1) {
+                    const int64_t n = t0 + si;
                     const float x = (float)((double)ring[slot * T + li] * a.fx_inv);
                     ring[slot * T + li] = 0;
-                    if (sub == 0 || n == a.n0) {
-                        const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)(n >> 3), 0,
-                                                 kTagPoisson, a.seed, (uint64_t)b);
-                        pw0[k] = p.v[0]; pw1[k] = p.v[1]; pw2[k] = p.v[2]; pw3[k] = p.v[3];
-                    }
-                    const uint64_t word = (sub < 2) ? pw0[k] : (sub < 4) ? pw1[k] : (sub < 6) ? pw2[k] : pw3[k];
-                    const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-                    int kc = 0;
-                    for (int m = 0; m < a.n_thr; ++m) kc += (u >= a.thr[m]) ? 1 : 0;
+                    const int kc = s_kcb[(size_t)((n >> 3) & 1) * 8 * T + (size_t)(n & 7) * T + li];
                     const float inp = x + a.w_ext * (float)kc;
                     const bool integ = RF[k] == 0;
                     float u_new;
@@ -362,34 +414,37 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
                         Y1[k] = a.P11 * Y1[k] + a.jump * inp;
                     }
-                    bool spk;
-                    if (a.frz_ptr) {
-                        spk = s_frz[li] != 0;
-                        s_frz[li] = 0;
-                    } else {
-                        spk = integ && u_new >= a.theta;
-                    }
+                    const bool spk = a.frz_ptr ? ((frz >> si) & 1u) != 0 : (integ && u_new >= a.theta);
                     if (spk) {
                         u_new = a.Ur;
                         RF[k] = a.n_ref;
-                        const int p = atomicAdd(&s_misc[0], 1);
-                        s_spk[p] = (uint32_t)(g0 + li);
+                        const int p = atomicAdd(&s_cnt[si], 1);
+                        s_spk[si * T + p] = (uint32_t)(g0 + li);
                     }
                     U[k] = u_new;
-                    if (a.x_trace) a.x_trace[(n - a.n0) * a.N + g0 + li] = x;
-                    if (a.v_trace) a.v_trace[(n - a.n0) * a.N + g0 + li] = u_new + a.E_L;
-                    if (a.m_trace) a.m_trace[(n - a.n0) * a.N + g0 + li] = (integ && !spk) ? 1 : 0;
+                    const size_t ti = (size_t)(n - a.n0) * a.N + g0 + li;
+                    if (a.x_trace) a.x_trace[ti] = x;
+                    if (a.v_trace) a.v_trace[ti] = u_new + a.E_L;
+                    if (a.m_trace) a.m_trace[ti] = (integ && !spk) ? 1 : 0;
                 }
+                if (a.frz_ptr) s_frz[li] = 0;
             }
-            __syncthreads();
-            // -------------------------------------------------------- publish
-            const int c = s_misc[0];
+        }
+        __syncthreads();
+        // -------------------------------------------------------- publish
+        // id words first, then the step's count word; a reader validates the
+        // step tag of every word it uses, so no ordering between them is needed
+        for (int si = 0; si < wn; ++si) {
+            const int64_t n = t0 + si;
+            const int c = s_cnt[si];
             const uint64_t tag = (uint64_t)(uint32_t)(n + 1) << 32;
             uint64_t* base = a.pub + (size_t)(n & (H - 1)) * pub_slot + (size_t)tile * pub_tile;
-            for (int i = tid; i < c; i += bs) coherent_store(base + 1 + i, tag | s_spk[i]);
+            const uint32_t* ls = s_spk + (size_t)si * T;
+            for (int i = tid; i < c; i += bs) coherent_store(base + 1 + i, tag | ls[i]);
+            if (tid == si) coherent_store(base, tag | (uint32_t)c);
             if (n >= a.log_step0 && n < a.log_step0 + a.log_steps) {
                 if (log_pos + c <= log_cap) {
-                    for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = s_spk[i];
+                    for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = ls[i];
                     if (tid == 0) a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = (uint32_t)c;
                     log_pos += c;
                 } else if (tid == 0) {
@@ -397,12 +452,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 }
             }
             nspk += c;
-            __syncthreads();
-            if (tid == 0) {
-                s_misc[0] = 0;
-                coherent_store(base, tag | (uint32_t)c);
-            }
         }
+        __syncthreads();
+        if (tid < wn) s_cnt[tid] = 0;
     }
     // ---------------------------------------------------------------- save
     __syncthreads();
@@ -456,12 +508,15 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
     b += (size_t)chunk * 8;                       // s_beg
     b += (size_t)(chunk + 1) * 4;                 // s_len
     b += (size_t)chunk * 4;                       // s_qof
-    b += (size_t)T * 4;                           // s_spk
+    b += (size_t)W * T * 4;                       // s_spk
     const size_t pairs = (size_t)W * ntiles_max;
     b += (pairs + 1) * 4;                         // s_pc
     b += pairs * kInline * 4;                     // s_pid
-    b += 20 * 4 + 4 * 4;                          // s_wsum, s_misc
-    b += (size_t)T;                               // s_frz
+    b += 20 * 4 + 4 * 4 + 8 * 4;                  // s_wsum, s_misc, s_cnt
+    b += (size_t)T * 4;                           // s_frz
+    b += (size_t)kMaxThr * 4;                     // s_thr
+    b += (size_t)16 * T;                          // s_kcb
+    b += (size_t)kBlk * 4;                        // s_blk
     return (b + 15) & ~(size_t)15;
 }
 
