@@ -67,30 +67,60 @@ def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
     }
 
 
+def _pack_instances(cx, netspec, spec, seed):
+    """Greedy packing of the instances into as few co-resident launches as the
+    device allows: each group is the longest prefix of the remaining
+    instances whose plan fits (a plan that does not fit fails before the graph
+    is generated)."""
+    groups, rest = [], list(spec.instances)
+    while rest:
+        k = len(rest)
+        while True:
+            sub = netspec.NetSpec(**{**spec.__dict__, "instances": rest[:k]})
+            try:
+                net = cx.Network(sub, seed + len(groups))
+                break
+            except cx.CortexError as e:
+                if e.status != cx.EUNSUPPORTED or k == 1:
+                    raise
+                k = max(1, (k * 3) // 4)
+        groups.append((sub, net))
+        rest = rest[k:]
+    return groups
+
+
 def batched_and_adjoint(cx, torch, seed, sim_steps):
     """Secondary figures on the batched workload (64 Brunel instances of
-    log-uniform size 1,250-50,000, delta LIF, 1.5 ms delays): one persistent
-    launch for all instances vs the same instances run one after another, and
-    the adjoint (backward) against its forward."""
+    log-uniform size 1,250-50,000, delta LIF, 1.5 ms delays): the instances
+    packed into as few persistent launches as fit the device vs the same
+    instances run one after another, and the adjoint (backward) against its
+    forward on the first packed group."""
     import netspec
     spec = netspec.config4()
     out = {"workload": "64 balanced delta-LIF instances, N log-uniform 1,250-50,000 (seeded), "
                        "in-degree 10% of each population, delay 1.5 ms, FP32",
-           "sim_steps": sim_steps}
-    log("[bench] batched: building 64 instances")
-    net = cx.Network(spec, seed)
-    out["neurons"], out["synapses"] = net.N, net.E
-    net.step(200)
+           "sim_steps": sim_steps, "neurons": spec.n_neurons}
+    log("[bench] batched: packing 64 instances into co-resident launches")
+    groups = _pack_instances(cx, netspec, spec, seed)
+    out["launches"] = len(groups)
+    out["instances_per_launch"] = [len(g.instances) for g, _ in groups]
+    out["synapses"] = int(sum(net.E for _, net in groups))
+    log(f"[bench] batched: {len(groups)} launches of {out['instances_per_launch']} instances")
+    for _, net in groups:
+        net.step(200)
     torch.cuda.synchronize()
-    e0 = net.query("EVENTS")
+    e0 = [net.query("EVENTS") for _, net in groups]
     t0 = time.perf_counter()
-    net.step(sim_steps)
+    for _, net in groups:
+        net.step(sim_steps)
     torch.cuda.synchronize()
     dt_b = time.perf_counter() - t0
-    ev_b = net.query("EVENTS") - e0
-    net.close()
-    del net
+    ev_b = sum(net.query("EVENTS") - e for (_, net), e in zip(groups, e0))
     log(f"[bench] batched: {ev_b / dt_b:.3e} events/s")
+    adj_spec = groups[0][0]
+    for _, net in groups:
+        net.close()
+    del groups
     ev_s, dt_s = 0, 0.0
     for b, inst in enumerate(spec.instances):
         one = netspec.NetSpec(**{**spec.__dict__, "instances": [inst]})
@@ -104,12 +134,12 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
         dt_s += time.perf_counter() - t0
         ev_s += g.query("EVENTS") - e0
         g.close()
-    log(f"[bench] sequential: {ev_s / dt_s:.3e} events/s")
+    log(f"[bench] one instance per launch: {ev_s / dt_s:.3e} events/s")
     out.update(events_per_s=ev_b / dt_b, sequential_events_per_s=ev_s / dt_s,
-               speedup=(ev_b / dt_b) / (ev_s / dt_s))
+               speedup=(ev_b / dt_b) / (ev_s / dt_s), batched_wall_s=dt_b, sequential_wall_s=dt_s)
     # adjoint: checkpointed forward, then the gradient of the voltage loss
     log("[bench] adjoint: forward with checkpoints")
-    net = cx.Network(spec, seed, ckpt_every=100, adjoint_steps=sim_steps)
+    net = cx.Network(adj_spec, seed, ckpt_every=100, adjoint_steps=sim_steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.step(sim_steps)
@@ -124,9 +154,47 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     log(f"[bench] adjoint: forward {t_fwd:.3f}s backward {t_bwd:.3f}s loss {loss:.4g}")
-    out["adjoint"] = {"forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+    out["adjoint"] = {"instances": len(adj_spec.instances), "neurons": net.N, "synapses": net.E,
+                      "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
                       "forward_events": ev_f, "loss": loss, "checkpoint_every_steps": 100}
     net.close()
+    return out
+
+
+def secondary_configs(cx, torch, netspec):
+    """Events/s and real-time factor of the other single-GPU workloads: the
+    77,169-neuron exp-current microcircuit stand-in (FP32, 1 s) and the
+    1,250-neuron delta-LIF net in the FP64 verification mode (100 ms)."""
+    out = {}
+    for name, spec, seed, steps in (("microcircuit_77k_fp32", netspec.config3(), 3, 10000),
+                                    ("brunel_1250_fp64_verify", netspec.config1(), 1, 1000)):
+        try:
+            log(f"[bench] {name}: building")
+            t0 = time.perf_counter()
+            net = cx.Network(spec, seed)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - t0
+            net.step(min(1000, steps))
+            torch.cuda.synchronize()
+            e0, s0 = net.query("EVENTS"), net.query("SPIKES")
+            t0 = time.perf_counter()
+            net.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ev, sp = net.query("EVENTS") - e0, net.query("SPIKES") - s0
+            sim_s = steps * spec.dt * 1e-3
+            out[name] = {"neurons": net.N, "synapses": net.E, "sim_steps": steps,
+                         "events_per_s": ev / wall, "rtf": wall / sim_s,
+                         "firing_rate_hz": sp / (net.N * sim_s), "graph_build_s": t_build}
+            if spec.precision != "fp64":
+                out[name].update(tiles=net.query("TILES"), tile_size=net.query("TILE_SIZE"),
+                                 steps_per_sync=net.query("STEPS_PER_SYNC"),
+                                 ring_slots=net.query("RING_SLOTS"), record_bytes=net.query("EDGE_BYTES"))
+            log(f"[bench] {name}: {ev / wall:.3e} events/s, rtf {wall / sim_s:.3f}")
+            net.close()
+        except cx.CortexError as e:
+            log(f"[bench] {name} failed: {e}")
+            out[name] = {"error": str(e)}
     return out
 
 
@@ -145,6 +213,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=4000)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size before the timed region "
@@ -231,6 +300,9 @@ def main():
 
     net.close()
     del net
+    secondary = None
+    if not args.no_secondary:
+        secondary = secondary_configs(cx, torch, netspec)
     batched = None
     if not args.no_batched:
         try:
@@ -282,6 +354,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "graph_build_s": t_build,
+        "other_workloads": secondary,
         "batched": batched,
     }
     print(json.dumps(out), flush=True)

@@ -328,6 +328,18 @@ static int fixed_point_bits(const cortex_net* n) {
     return std::max(0, std::min(fx, 52));
 }
 
+// Shift that keeps every single weight below 2^31 at scale 2^(fx - shift),
+// so the kernel converts a weight with one 32-bit rounding and widens it to
+// the ring's 64-bit scale 2^fx with an exact shift.
+static int fixed_point_shift(const cortex_net* n, int fx) {
+    const double conv = (n->spec.weight_unit == CORTEX_UNIT_PSP_MV) ? n->k.conv : 1.0;
+    double wmax = 1e-30;
+    for (const auto& B : n->blocks)
+        wmax = std::max(wmax, (std::fabs(B.w_mean) + 8.6 * B.w_sd) * std::fabs(conv) * (1.0 + 1e-6));
+    const int fxw = 30 - (int)std::ceil(std::log2(wmax));
+    return std::max(0, fx - std::max(0, fxw));
+}
+
 static int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -389,43 +401,55 @@ static void plan_tiles(cortex_net* n) {
         lds_for(T, ntb_max_of(Tb), 1, &chunk);
     } else {
         bool found = false;
+        auto bits_for = [](int64_t x) { int t = 0; while ((int64_t)1 << t < x) ++t; return t; };
+        const int w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
         for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
             const int64_t cap = (int64_t)n_cu * per_cu;
-            const int bs = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu));
-            int Tcap = bs <= 512 ? 4 * bs : 2 * bs;
-            double hi0 = 1.0;
-            for (int b = 0; b < n->n_inst; ++b) hi0 = std::max(hi0, K[b] * (double)n->inst_N[b]);
-            // Balance synapses per tile (bisection on the per-tile synapse
-            // budget), then cap tiles whose input rings would overflow the
-            // workgroup's share of LDS and balance again.
-            for (int pass = 0; pass < 4 && !found; ++pass) {
-                if (tiles_of(sizes_for(hi0, Tcap)) > cap) break;
-                double lo = 1.0, hi = hi0;
-                for (int it = 0; it < 100 && hi - lo > 0.5; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (tiles_of(sizes_for(mid, Tcap)) <= cap) hi = mid; else lo = mid;
+            const int bs_top = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu));
+            for (int bs = bs_top; bs >= (BS ? BS : 256) && !found; bs /= 2) {
+                int Tcap = bs <= 512 ? 4 * bs : 2 * bs;
+                double hi0 = 1.0;
+                for (int b = 0; b < n->n_inst; ++b) hi0 = std::max(hi0, K[b] * (double)n->inst_N[b]);
+                // Balance synapses per tile (bisection on the per-tile synapse
+                // budget), then cap tiles whose input rings would overflow the
+                // workgroup's share of LDS and balance again.
+                for (int pass = 0; pass < 4 && !found; ++pass) {
+                    if (tiles_of(sizes_for(hi0, Tcap)) > cap) break;
+                    double lo = 1.0, hi = hi0;
+                    for (int it = 0; it < 100 && hi - lo > 0.5; ++it) {
+                        const double mid = 0.5 * (lo + hi);
+                        if (tiles_of(sizes_for(mid, Tcap)) <= cap) hi = mid; else lo = mid;
+                    }
+                    auto cand = sizes_for(hi, Tcap);
+                    const int Tm = *std::max_element(cand.begin(), cand.end());
+                    const int ntbm = ntb_max_of(cand);
+                    int c = 1024;
+                    const size_t lds = lds_for(Tm, ntbm, per_cu, &c);
+                    if (lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
+                        // the variant's registers must allow per_cu resident
+                        // workgroups of bs threads
+                        int npt = (Tm + bs - 1) / bs;
+                        if (npt == 3) npt = 4;
+                        const int meta = bits_for(Tm) + bits_for(n->R) <= 16 ? 2 : 4;
+                        if (npt <= 4 && step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds) >= per_cu) {
+                            Tb = cand;
+                            BS = bs;
+                            chunk = c;
+                            found = true;
+                        }
+                        break;
+                    }
+                    // largest tile whose LDS fits at this occupancy
+                    int tl = 1, th = Tm;
+                    while (th - tl > 1) {
+                        const int mid = (tl + th) / 2;
+                        int cc = 128;
+                        if (lds_for(mid, ntbm, per_cu, &cc) * per_cu <= lds_cu) tl = mid; else th = mid;
+                    }
+                    if (tl >= Tcap) break;
+                    Tcap = tl;
                 }
-                auto cand = sizes_for(hi, Tcap);
-                const int Tm = *std::max_element(cand.begin(), cand.end());
-                const int ntbm = ntb_max_of(cand);
-                int c = 1024;
-                const size_t lds = lds_for(Tm, ntbm, per_cu, &c);
-                if (lds * per_cu <= lds_cu && bs * per_cu <= thr_cu) {
-                    Tb = cand;
-                    BS = bs;
-                    chunk = c;
-                    found = true;
-                    break;
-                }
-                // largest tile whose LDS fits at this occupancy
-                int tl = 1, th = Tm;
-                while (th - tl > 1) {
-                    const int mid = (tl + th) / 2;
-                    int cc = 128;
-                    if (lds_for(mid, ntbm, per_cu, &cc) * per_cu <= lds_cu) tl = mid; else th = mid;
-                }
-                if (tl >= Tcap) break;
-                Tcap = tl;
+                if (BS) break;
             }
         }
         require(found, CORTEX_EUNSUPPORTED,
@@ -617,6 +641,7 @@ static void build(cortex_net* n) {
             }
         }
         n->fx = fixed_point_bits(n);
+        n->fx_shift = fixed_point_shift(n, n->fx);
         upload_tables_fp32(n);
         build_graph_fp32(n);
         alloc_state_fp32(n);

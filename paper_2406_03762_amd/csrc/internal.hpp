@@ -130,6 +130,7 @@ struct cortex_net {
     int32_t* d_r = nullptr;
     long long* d_ring = nullptr;       // [n_tiles][R][T] fixed-point input sums
     int fx = 32;                       // fixed-point fraction bits of the rings
+    int fx_shift = 0;                  // weights are rounded at 2^(fx - fx_shift), then shifted
     uint64_t* d_pub = nullptr;         // [H][n_tiles][T + 1] tagged spike records
     uint32_t* d_log_cnt = nullptr;     // [log_steps][n_tiles]
     uint32_t* d_log_ids = nullptr;
@@ -191,6 +192,9 @@ void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const
                uint64_t n_ids);
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk);
 int step_max_blocks_per_cu(cortex_net* n);
+// Resident workgroups per CU of the step kernel variant for a model, record
+// format, neurons per thread, workgroup size and LDS bytes (0 if none fit).
+int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds);
 // verify.hip
 void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits,
                       double* x_trace, double* v_trace);

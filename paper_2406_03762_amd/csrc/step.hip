@@ -38,7 +38,7 @@ namespace cortex {
 namespace {
 
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
-constexpr int kInline = 3;        // spike ids fetched together with a tile's step record
+constexpr int kInline = 1;        // spike ids fetched together with a tile's step record
 constexpr int kBlk = 512;         // 64-edge blocks per piece of a delivery chunk
 
 struct StepArgs {
@@ -75,7 +75,8 @@ struct StepArgs {
     int64_t n0, n1, log_step0, log_steps, N;
     int n_tiles, T, R, dmin, H, W, chunk, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
-    float fx_scale;             // 2^fx
+    float fxw_scale;            // 2^(fx - fx_shift): synaptic weight to 32-bit fixed point
+    int fx_shift;               // left shift from the 32-bit weight scale to the ring's 2^fx
     double fx_inv;              // 2^-fx
     uint64_t seed;
     uint32_t thr[kMaxThr];
@@ -132,11 +133,14 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     const size_t pub_slot = (size_t)a.n_tiles * pub_tile;
     const int pairs_max = a.W * a.ntb_max;
 
-    long long* ring = reinterpret_cast<long long*>(lds_raw);
-    uint64_t* s_beg = reinterpret_cast<uint64_t*>(ring + (size_t)R * T);
-    uint32_t* s_len = reinterpret_cast<uint32_t*>(s_beg + CH);     // CH + 1
-    uint32_t* s_qof = s_len + CH + 1;                               // CH
-    uint32_t* s_spk = s_qof + CH;                                   // W * T (spikes per step of a window)
+    // s_sg[k] describes segment k of a delivery chunk: x = end of the
+    // segment in the flattened edge space, y = step offset of the spike,
+    // (z, w) = edge index of the segment's first synapse minus its flattened
+    // start (64-bit, modular), so edge = base + flattened position
+    uint4* s_sg = reinterpret_cast<uint4*>(lds_raw);                // CH
+    long long* ring = reinterpret_cast<long long*>(s_sg + CH);     // R * T
+    uint32_t* s_len = reinterpret_cast<uint32_t*>(ring + (size_t)R * T);   // CH + 1
+    uint32_t* s_spk = s_len + CH + 1;                               // W * T (spikes per step of a window)
     uint32_t* s_pc = s_spk + (size_t)a.W * T;                       // pairs_max + 1
     uint32_t* s_pid = s_pc + pairs_max + 1;                         // pairs_max * kInline
     uint32_t* s_wsum = s_pid + (size_t)pairs_max * kInline;         // 20
@@ -293,17 +297,16 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     if (bail) {
                         // the id never arrived: the kernel stops after this
                         // chunk, so the entry is only kept in range
-                        s_beg[k] = 0;
+                        s_sg[k] = make_uint4(0u, 0u, 0u, 0u);
                         s_len[k] = 0;
-                        s_qof[k] = 0;
                         continue;
                     }
                     const uint64_t rs = a.row_start[j];
                     const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
                     const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
-                    s_beg[k] = rs + o0;
+                    const uint64_t beg = rs + o0;
+                    s_sg[k] = make_uint4(0u, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
                     s_len[k] = o1 - o0;
-                    s_qof[k] = (uint32_t)qi;
                 }
                 if (bail) {
                     s_misc[1] = 1;
@@ -314,6 +317,14 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
                 if (tid == 0) s_len[cn] = EL;
                 __syncthreads();
+                for (int k = tid; k < cn; k += bs) {
+                    uint4 g = s_sg[k];
+                    const uint64_t base = (((uint64_t)g.w << 32) | g.z) - (uint64_t)s_len[k];
+                    g.x = s_len[k + 1];
+                    g.z = (uint32_t)base;
+                    g.w = (uint32_t)(base >> 32);
+                    s_sg[k] = g;
+                }
                 // The flattened edges are walked in pieces of at most 64 * kBlk;
                 // s_blk[b] is the segment holding the piece's edge 64 b, so a
                 // lane starts its segment search next to its edge
@@ -346,9 +357,10 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         wv[u] = 0.f;
                         if (fu < f_end) {
                             int seg = (int)s_blk[((fu - (uint32_t)lane) - pc0) >> 6];
-                            while (s_len[seg + 1] <= fu) ++seg;
-                            const uint64_t e = s_beg[seg] + (fu - s_len[seg]);
-                            qpk[u >> 3] |= (s_qof[seg] | 8u) << (4 * (u & 7));
+                            uint4 g = s_sg[seg];
+                            while (g.x <= fu) g = s_sg[++seg];
+                            const uint64_t e = (((uint64_t)g.w << 32) | g.z) + fu;
+                            qpk[u >> 3] |= (g.y | 8u) << (4 * (u & 7));
                             m[u] = static_cast<const META*>(a.meta)[e];
                             wv[u] = load_w(a.w, e, WBF16);
                         }
@@ -359,8 +371,12 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         if (q & 8u) {
                             int sl = base_slot + (int)(q & 7u) + (int)(m[u] >> a.tbits);
                             if (sl >= R) sl -= R;
-                            const long long iv = __float2ll_rn(wv[u] * a.fx_scale);
-                            atomicAdd(reinterpret_cast<unsigned long long*>(&ring[sl * T + (m[u] & tmask)]),
+                            // w 2^fx in 64-bit fixed point: round w 2^(fx - fx_shift)
+                            // to a 32-bit integer, then shift (exact)
+                            const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
+                            const long long iv = (long long)iw << a.fx_shift;
+                            atomicAdd(reinterpret_cast<unsigned long long*>(
+                                          &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)]),
                                       (unsigned long long)iv);
                         }
                     }
@@ -504,10 +520,9 @@ KernelFn pick_kernel(const cortex_net* n) {
 }  // namespace
 
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
-    size_t b = (size_t)R * T * 8;
-    b += (size_t)chunk * 8;                       // s_beg
+    size_t b = (size_t)chunk * 16;                // s_sg
+    b += (size_t)R * T * 8;                       // ring
     b += (size_t)(chunk + 1) * 4;                 // s_len
-    b += (size_t)chunk * 4;                       // s_qof
     b += (size_t)W * T * 4;                       // s_spk
     const size_t pairs = (size_t)W * ntiles_max;
     b += (pairs + 1) * 4;                         // s_pc
@@ -518,6 +533,20 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
     b += (size_t)16 * T;                          // s_kcb
     b += (size_t)kBlk * 4;                        // s_blk
     return (b + 15) & ~(size_t)15;
+}
+
+int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds) {
+    KernelFn f;
+    switch (model) {
+        case CORTEX_MODEL_DELTA: f = pick_fmt<CORTEX_MODEL_DELTA>(meta_bytes, w_bytes, npt); break;
+        case CORTEX_MODEL_EXP: f = pick_fmt<CORTEX_MODEL_EXP>(meta_bytes, w_bytes, npt); break;
+        default: f = pick_fmt<CORTEX_MODEL_ALPHA>(meta_bytes, w_bytes, npt); break;
+    }
+    if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, bs, lds) != hipSuccess) return 0;
+    return nb;
 }
 
 int step_max_blocks_per_cu(cortex_net* n) {
@@ -596,7 +625,8 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.Ur = (float)(n->spec.V_reset - n->spec.E_L);
     a.w_ext = (float)n->w_ext_native;
     a.E_L = (float)n->spec.E_L;
-    a.fx_scale = std::ldexp(1.0f, n->fx);
+    a.fxw_scale = std::ldexp(1.0f, n->fx - n->fx_shift);
+    a.fx_shift = n->fx_shift;
     a.fx_inv = std::ldexp(1.0, -n->fx);
     a.seed = n->seed;
     for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
