@@ -209,7 +209,8 @@ enum {
     CORTEX_Q_BLOCK_SIZE = 12,
     CORTEX_Q_LDS_BYTES = 13,      /* workgroup-local memory per workgroup */
     CORTEX_Q_OFFSET_BYTES = 14,   /* bytes of the per-(source, tile) offset table */
-    CORTEX_Q_STEPS_PER_SYNC = 15  /* FP32: time steps per spike exchange chosen at build */
+    CORTEX_Q_STEPS_PER_SYNC = 15, /* FP32: time steps per spike exchange chosen at build */
+    CORTEX_Q_RING_BYTES = 16      /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
 };
 /* Scalar facts about the network into *value.  EVENTS and SPIKES
    synchronise. */

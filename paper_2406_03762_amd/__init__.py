@@ -22,7 +22,7 @@ ABI_VERSION = 1
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
 Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
          STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
-         OFFSET_BYTES=14, STEPS_PER_SYNC=15)
+         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16)
 
 
 class CortexError(RuntimeError):

@@ -247,7 +247,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     float* sv_y1 = dev_alloc_t<float>(n, N, true);
     float* sv_y2 = dev_alloc_t<float>(n, N, true);
     int32_t* sv_r = dev_alloc_t<int32_t>(n, N, true);
-    long long* sv_ring = dev_alloc_t<long long>(n, ring_n, true);
+    unsigned char* sv_ring = dev_alloc_t<unsigned char>(n, ring_n * n->ring_bytes, true);
     uint64_t* sv_pub = dev_alloc_t<uint64_t>(n, pub_n, true);
     uint64_t* sv_ev = dev_alloc_t<uint64_t>(n, 2 * (size_t)n->n_tiles, true);
     auto d2d = [&](void* dst, const void* src, size_t bytes) {
@@ -257,7 +257,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     d2d(sv_y1, n->d_y1, N * 4);
     d2d(sv_y2, n->d_y2, N * 4);
     d2d(sv_r, n->d_r, N * 4);
-    d2d(sv_ring, n->d_ring, ring_n * 8);
+    d2d(sv_ring, n->d_ring, ring_n * n->ring_bytes);
     d2d(sv_pub, n->d_pub, pub_n * 8);
     d2d(sv_ev, n->d_events, n->n_tiles * 8);
     d2d(sv_ev + n->n_tiles, n->d_spikes, n->n_tiles * 8);
@@ -421,7 +421,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     d2d(n->d_y1, sv_y1, N * 4);
     d2d(n->d_y2, sv_y2, N * 4);
     d2d(n->d_r, sv_r, N * 4);
-    d2d(n->d_ring, sv_ring, ring_n * 8);
+    d2d(n->d_ring, sv_ring, ring_n * n->ring_bytes);
     d2d(n->d_pub, sv_pub, pub_n * 8);
     d2d(n->d_events, sv_ev, n->n_tiles * 8);
     d2d(n->d_spikes, sv_ev + n->n_tiles, n->n_tiles * 8);

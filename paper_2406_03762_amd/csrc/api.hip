@@ -385,11 +385,11 @@ static void plan_tiles(cortex_net* n) {
     };
     auto lds_for = [&](int T, int ntbm, int per_cu, int* chunk) {
         for (int c = 1024; c >= 128; c /= 2) {
-            const size_t l = step_lds_bytes(n->R, T, n->W, ntbm, c);
+            const size_t l = step_lds_bytes(n->R, T, n->W, ntbm, c, n->ring_bytes);
             if (l * per_cu <= lds_cu) { *chunk = c; return l; }
         }
         *chunk = 128;
-        return step_lds_bytes(n->R, T, n->W, ntbm, 128);
+        return step_lds_bytes(n->R, T, n->W, ntbm, 128, n->ring_bytes);
     };
     std::vector<int32_t> Tb;
     int BS = n->spec.block_size;
@@ -431,7 +431,8 @@ static void plan_tiles(cortex_net* n) {
                         int npt = (Tm + bs - 1) / bs;
                         if (npt == 3) npt = 4;
                         const int meta = bits_for(Tm) + bits_for(n->R) <= 16 ? 2 : 4;
-                        if (npt <= 4 && step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds) >= per_cu) {
+                        if (npt <= 4 &&
+                            step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds, n->ring_bytes) >= per_cu) {
                             Tb = cand;
                             BS = bs;
                             chunk = c;
@@ -487,7 +488,7 @@ static void plan_tiles(cortex_net* n) {
         n->n_tiles += nt;
     }
     n->ntb_max = ntb_max_of(Tb);
-    n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk);
+    n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk, n->ring_bytes);
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
     n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
 }
@@ -518,7 +519,7 @@ static void alloc_checkpoints(cortex_net* n) {
     n->d_ck_y1 = dev_alloc_t<float>(n, (size_t)n->n_ckpt * N);
     n->d_ck_y2 = dev_alloc_t<float>(n, (size_t)n->n_ckpt * N);
     n->d_ck_r = dev_alloc_t<int32_t>(n, (size_t)n->n_ckpt * N);
-    n->d_ck_ring = dev_alloc_t<long long>(n, (size_t)n->n_ckpt * ring_n);
+    n->d_ck_ring = dev_alloc_t<unsigned char>(n, (size_t)n->n_ckpt * ring_n * n->ring_bytes);
 }
 
 static void alloc_state_fp32(cortex_net* n) {
@@ -528,7 +529,7 @@ static void alloc_state_fp32(cortex_net* n) {
     n->d_y1 = dev_alloc_t<float>(n, N);
     n->d_y2 = dev_alloc_t<float>(n, N);
     n->d_r = dev_alloc_t<int32_t>(n, N);
-    n->d_ring = dev_alloc_t<long long>(n, (size_t)n->n_tiles * n->R * n->T);
+    n->d_ring = dev_alloc(n, (size_t)n->n_tiles * n->R * n->T * n->ring_bytes);
     // (+8 words: a reader fetches a few id words past a record without bounds checks)
     n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
@@ -552,7 +553,7 @@ static void zero_dynamic_fp32(cortex_net* n) {
     dev_zero(n, n->d_y1, N * sizeof(float));
     dev_zero(n, n->d_y2, N * sizeof(float));
     dev_zero(n, n->d_r, N * sizeof(int32_t));
-    dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * sizeof(long long));
+    dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * n->ring_bytes);
     dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
     dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
     dev_zero(n, n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles * sizeof(uint32_t));
@@ -573,7 +574,7 @@ static void alloc_state_fp64(cortex_net* n) {
     n->d_hist = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->W64);
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
     n->d_raster = dev_alloc_t<uint64_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64);
-    n->d_events = dev_alloc_t<uint64_t>(n, 1);
+    n->d_events = dev_alloc_t<uint64_t>(n, 2);   // synaptic events, spikes
     n->d_err = dev_alloc_t<int32_t>(n, 4);
 }
 
@@ -585,7 +586,7 @@ static void zero_dynamic_fp64(cortex_net* n) {
     dev_zero(n, n->d_r, N * sizeof(int32_t));
     dev_zero(n, n->d_hist, (size_t)n->H * n->W64 * sizeof(uint64_t));
     dev_zero(n, n->d_raster, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64 * sizeof(uint64_t));
-    dev_zero(n, n->d_events, sizeof(uint64_t));
+    dev_zero(n, n->d_events, 2 * sizeof(uint64_t));
     dev_zero(n, n->d_err, 4 * sizeof(int32_t));
 }
 
@@ -629,21 +630,34 @@ static void build(cortex_net* n) {
         // fit workgroup-local memory
         const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
         require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
-        for (int W = W0;; W = std::max(1, W / 2)) {
-            n->W = W;
-            n->R = dmax - dmin + n->W;
-            n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
-            try {
-                plan_tiles(n);
-                break;
-            } catch (const Error& e) {
-                if (e.status != CORTEX_EUNSUPPORTED || W == 1 || s.steps_per_sync > 0) throw;
+        // 64-bit input sums first; 32-bit sums (scaled by the largest exact
+        // input bound of any neuron) when the 64-bit rings cannot fit
+        bool planned = false;
+        for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
+            n->ring_bytes = rb;
+            for (int W = W0;; W = std::max(1, W / 2)) {
+                n->W = W;
+                n->R = dmax - dmin + n->W;
+                n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+                try {
+                    plan_tiles(n);
+                    planned = true;
+                    break;
+                } catch (const Error& e) {
+                    if (e.status != CORTEX_EUNSUPPORTED || (rb == 4 && (W == 1 || s.steps_per_sync > 0))) throw;
+                    if (W == 1 || s.steps_per_sync > 0) break;
+                }
             }
         }
         n->fx = fixed_point_bits(n);
         n->fx_shift = fixed_point_shift(n, n->fx);
         upload_tables_fp32(n);
         build_graph_fp32(n);
+        if (n->ring_bytes == 4) {
+            const double bound = max_abs_input(n) * (1.0 + 1e-4) + 1e-30;
+            n->fx = std::max(0, std::min(52, 30 - (int)std::ceil(std::log2(bound))));
+            n->fx_shift = 0;
+        }
         alloc_state_fp32(n);
         alloc_checkpoints(n);
         init_state(n);
@@ -737,7 +751,7 @@ static void save_checkpoint(cortex_net* n, int k) {
     d2d(n->d_ck_y1 + (size_t)k * N, n->d_y1, N * 4);
     d2d(n->d_ck_y2 + (size_t)k * N, n->d_y2, N * 4);
     d2d(n->d_ck_r + (size_t)k * N, n->d_r, N * 4);
-    d2d(n->d_ck_ring + (size_t)k * ring_n, n->d_ring, ring_n * 8);
+    d2d(n->d_ck_ring + (size_t)k * ring_n * n->ring_bytes, n->d_ring, ring_n * n->ring_bytes);
 }
 
 void restore_checkpoint(cortex_net* n, int k) {
@@ -750,7 +764,7 @@ void restore_checkpoint(cortex_net* n, int k) {
     d2d(n->d_y1, n->d_ck_y1 + (size_t)k * N, N * 4);
     d2d(n->d_y2, n->d_ck_y2 + (size_t)k * N, N * 4);
     d2d(n->d_r, n->d_ck_r + (size_t)k * N, N * 4);
-    d2d(n->d_ring, n->d_ck_ring + (size_t)k * ring_n, ring_n * 8);
+    d2d(n->d_ring, n->d_ck_ring + (size_t)k * ring_n * n->ring_bytes, ring_n * n->ring_bytes);
 }
 
 // Advance the FP32 network, splitting launches at checkpoint steps when the
@@ -1070,21 +1084,14 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
             break;
         }
         case CORTEX_Q_STEPS_PER_SYNC: *value = fp64 ? 1 : n->W; break;
+        case CORTEX_Q_RING_BYTES: *value = fp64 ? 8 : n->ring_bytes; break;
         case CORTEX_Q_EVENTS:
         case CORTEX_Q_SPIKES: {
             require(!n->failed, CORTEX_ESTATE, "network failed earlier");
             check_device_flag(n);
             if (fp64) {
-                if (what == CORTEX_Q_EVENTS) {
-                    auto v = download(n, n->d_events, 1);
-                    *value = (int64_t)v[0];
-                } else {
-                    auto bits = download(n, n->d_raster, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64);
-                    int64_t c = 0;
-                    const int64_t used = std::min(n->step - n->log_step0, n->log_steps);
-                    for (size_t i = 0; i < (size_t)std::max<int64_t>(0, used) * n->W64; ++i) c += __builtin_popcountll(bits[i]);
-                    *value = c;
-                }
+                auto v = download(n, n->d_events, 2);
+                *value = (int64_t)v[what == CORTEX_Q_EVENTS ? 0 : 1];
             } else {
                 auto v = download(n, what == CORTEX_Q_EVENTS ? n->d_events : n->d_spikes, n->n_tiles);
                 int64_t s = 0;

@@ -484,6 +484,60 @@ void delay_range(cortex_net* n, int* dmin, int* dmax) {
     *dmax = dm[1] == 0 ? 1 : dm[1];
 }
 
+namespace {
+
+// Per target, the sum of |w| over its stored in-synapses (the largest value
+// any of its input sums can reach).  One wave per source row walks the row's
+// segments tile by tile.  Setup only.
+__global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_start, const uint32_t* off_rel,
+                                                        const void* meta, int meta16, const void* w, int wbf16,
+                                                        int tbits, const int64_t* inst_n0,
+                                                        const uint64_t* inst_offbase, const int32_t* inst_ntiles,
+                                                        const int32_t* inst_T, int n_inst, int64_t N,
+                                                        double* sum) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t tmask = (1u << tbits) - 1u;
+    for (int64_t j = wave; j < N; j += n_waves) {
+        int lo = 0, hi = n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (inst_n0[mid] <= j) lo = mid; else hi = mid;
+        }
+        const int nt = inst_ntiles[lo];
+        const uint64_t ob = inst_offbase[lo] + (uint64_t)(j - inst_n0[lo]) * (uint64_t)(nt + 1);
+        const uint64_t rs = row_start[j];
+        for (int t = 0; t < nt; ++t) {
+            const int64_t g0 = inst_n0[lo] + (int64_t)t * inst_T[lo];
+            for (uint64_t e = rs + off_rel[ob + t] + lane; e < rs + off_rel[ob + t + 1]; e += 64) {
+                const uint32_t m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
+                const float wv = wbf16 ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16)
+                                       : static_cast<const float*>(w)[e];
+                atomicAdd(&sum[g0 + (m & tmask)], (double)fabsf(wv));
+            }
+        }
+    }
+}
+
+}  // namespace
+
+double max_abs_input(cortex_net* n) {
+    double* sum = dev_alloc_t<double>(n, std::max<int64_t>(1, n->N), true);
+    dev_zero(n, sum, (size_t)n->N * sizeof(double));
+    hipLaunchKernelGGL(abs_input_kernel, dim3(grid_for(n->N * 64, 256)), dim3(256), 0, n->stream, n->d_row_start,
+                       n->d_off_rel, n->d_meta, n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0,
+                       n->tbits, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->d_inst_T, n->n_inst, n->N,
+                       sum);
+    CX_HIP(hipGetLastError());
+    std::vector<double> h((size_t)n->N);
+    CX_HIP(hipMemcpyAsync(h.data(), sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    CX_HIP(hipStreamSynchronize(n->stream));
+    double m = 0.0;
+    for (double v : h) m = std::max(m, v);
+    return m;
+}
+
 void build_graph_fp32(cortex_net* n) {
     Tables t = upload_tables(n);
     // per-(source, tile) counts

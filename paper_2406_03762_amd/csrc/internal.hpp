@@ -128,7 +128,8 @@ struct cortex_net {
     // FP32 state
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
-    long long* d_ring = nullptr;       // [n_tiles][R][T] fixed-point input sums
+    void* d_ring = nullptr;            // [n_tiles][R][T] fixed-point input sums (ring_bytes each)
+    int ring_bytes = 8;                // 8: 64-bit sums; 4: 32-bit sums when 64-bit rings do not fit
     int fx = 32;                       // fixed-point fraction bits of the rings
     int fx_shift = 0;                  // weights are rounded at 2^(fx - fx_shift), then shifted
     uint64_t* d_pub = nullptr;         // [H][n_tiles][T + 1] tagged spike records
@@ -163,7 +164,7 @@ struct cortex_net {
     float* d_ck_y1 = nullptr;
     float* d_ck_y2 = nullptr;
     int32_t* d_ck_r = nullptr;
-    long long* d_ck_ring = nullptr;    // [n_ckpt][n_tiles][R][T]
+    unsigned char* d_ck_ring = nullptr;   // [n_ckpt][n_tiles][R][T] ring elements
 };
 
 namespace cortex {
@@ -178,6 +179,8 @@ T* dev_alloc_t(cortex_net* n, size_t count, bool scratch = false) {
 // Kernel launchers (graph.hip) -----------------------------------------------
 void delay_range(cortex_net* n, int* dmin, int* dmax);
 void build_graph_fp32(cortex_net* n);
+// Largest sum of |w| over the stored in-synapses of any neuron (after build_graph_fp32).
+double max_abs_input(cortex_net* n);
 void build_graph_fp64(cortex_net* n);
 void init_state(cortex_net* n);
 // step.hip
@@ -190,11 +193,11 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
 void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss);
 void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr,
                uint64_t n_ids);
-size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk);
+size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_bytes);
 int step_max_blocks_per_cu(cortex_net* n);
 // Resident workgroups per CU of the step kernel variant for a model, record
 // format, neurons per thread, workgroup size and LDS bytes (0 if none fit).
-int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds);
+int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds, int ring_bytes);
 // verify.hip
 void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits,
                       double* x_trace, double* v_trace);

@@ -57,7 +57,7 @@ struct StepArgs {
     float* y1;
     float* y2;
     int32_t* r;
-    long long* ring;
+    void* ring;                 // [n_tiles][R][T] of RING
     uint64_t* pub;              // [H][n_tiles][T + 1] tagged step records and spike ids
     uint32_t* log_cnt;
     uint32_t* log_ids;
@@ -112,7 +112,7 @@ __device__ __noinline__ uint64_t wait_tag(const uint64_t* p, uint64_t v, uint32_
 
 // Up to 1024 threads per workgroup with one or two neurons per thread; four
 // neurons per thread (large tiles) need the registers of a 512-thread limit.
-template <int MODEL, typename META, bool WBF16, int NPT>
+template <int MODEL, typename META, bool WBF16, int NPT, typename RING>
 __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     // (z, w) = edge index of the segment's first synapse minus its flattened
     // start (64-bit, modular), so edge = base + flattened position
     uint4* s_sg = reinterpret_cast<uint4*>(lds_raw);                // CH
-    long long* ring = reinterpret_cast<long long*>(s_sg + CH);     // R * T
+    RING* ring = reinterpret_cast<RING*>(s_sg + CH);                // R * T
     uint32_t* s_len = reinterpret_cast<uint32_t*>(ring + (size_t)R * T);   // CH + 1
     uint32_t* s_spk = s_len + CH + 1;                               // W * T (spikes per step of a window)
     uint32_t* s_pc = s_spk + (size_t)a.W * T;                       // pairs_max + 1
@@ -165,7 +165,8 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             if (MODEL == CORTEX_MODEL_ALPHA) Y2[k] = a.y2[g0 + li];
         }
     }
-    for (int i = tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
+    const RING* g_ring = static_cast<const RING*>(a.ring) + (size_t)tile * R * T;
+    for (int i = tid; i < R * T; i += bs) ring[i] = g_ring[i];
     for (int i = tid; i < T; i += bs) s_frz[i] = 0;
     if (tid == 0) { s_misc[0] = 0; s_misc[1] = 0; }
     if (tid < 8) s_cnt[tid] = 0;
@@ -374,10 +375,14 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                             // w 2^fx in 64-bit fixed point: round w 2^(fx - fx_shift)
                             // to a 32-bit integer, then shift (exact)
                             const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
-                            const long long iv = (long long)iw << a.fx_shift;
-                            atomicAdd(reinterpret_cast<unsigned long long*>(
-                                          &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)]),
-                                      (unsigned long long)iv);
+                            RING* dst = &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)];
+                            if (sizeof(RING) == 8) {
+                                const long long iv = (long long)iw << a.fx_shift;
+                                atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)iv);
+                            } else {
+                                // 32-bit rings: the scale keeps every sum below 2^31
+                                atomicAdd(reinterpret_cast<unsigned int*>(dst), (unsigned int)iw);
+                            }
                         }
                     }
                     f += 64u * U4;
@@ -484,7 +489,8 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             if (MODEL == CORTEX_MODEL_ALPHA) a.y2[g0 + li] = Y2[k];
         }
     }
-    for (int i = tid; i < R * T; i += bs) a.ring[(size_t)tile * R * T + i] = ring[i];
+    RING* g_ring_out = static_cast<RING*>(a.ring) + (size_t)tile * R * T;
+    for (int i = tid; i < R * T; i += bs) g_ring_out[i] = ring[i];
     if (tid == 0) {
         a.events[tile] += ev;
         a.spikes[tile] += nspk;
@@ -494,34 +500,44 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
 
 using KernelFn = void (*)(StepArgs);
 
-template <int MODEL, typename META, bool WBF16>
+template <int MODEL, typename META, bool WBF16, typename RING>
 KernelFn pick_npt(int npt) {
-    if (npt == 1) return step_kernel<MODEL, META, WBF16, 1>;
-    if (npt == 2) return step_kernel<MODEL, META, WBF16, 2>;
-    return step_kernel<MODEL, META, WBF16, 4>;
+    if (npt == 1) return step_kernel<MODEL, META, WBF16, 1, RING>;
+    if (npt == 2) return step_kernel<MODEL, META, WBF16, 2, RING>;
+    return step_kernel<MODEL, META, WBF16, 4, RING>;
 }
 
-template <int MODEL>
+template <int MODEL, typename RING>
 KernelFn pick_fmt(int meta_bytes, int w_bytes, int npt) {
     if (meta_bytes == 2) {
-        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true>(npt) : pick_npt<MODEL, uint16_t, false>(npt);
+        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true, RING>(npt) : pick_npt<MODEL, uint16_t, false, RING>(npt);
     }
-    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true>(npt) : pick_npt<MODEL, uint32_t, false>(npt);
+    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true, RING>(npt) : pick_npt<MODEL, uint32_t, false, RING>(npt);
+}
+
+template <typename RING>
+KernelFn pick_model(int model, int meta_bytes, int w_bytes, int npt) {
+    switch (model) {
+        case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA, RING>(meta_bytes, w_bytes, npt);
+        case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP, RING>(meta_bytes, w_bytes, npt);
+        default: return pick_fmt<CORTEX_MODEL_ALPHA, RING>(meta_bytes, w_bytes, npt);
+    }
+}
+
+KernelFn pick_variant(int model, int meta_bytes, int w_bytes, int npt, int ring_bytes) {
+    return ring_bytes == 8 ? pick_model<long long>(model, meta_bytes, w_bytes, npt)
+                           : pick_model<int>(model, meta_bytes, w_bytes, npt);
 }
 
 KernelFn pick_kernel(const cortex_net* n) {
-    switch (n->spec.model) {
-        case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA>(n->meta_bytes, n->w_bytes, n->NPT);
-        case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP>(n->meta_bytes, n->w_bytes, n->NPT);
-        default: return pick_fmt<CORTEX_MODEL_ALPHA>(n->meta_bytes, n->w_bytes, n->NPT);
-    }
+    return pick_variant(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT, n->ring_bytes);
 }
 
 }  // namespace
 
-size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
+size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_bytes) {
     size_t b = (size_t)chunk * 16;                // s_sg
-    b += (size_t)R * T * 8;                       // ring
+    b += (size_t)R * T * ring_bytes;              // ring
     b += (size_t)(chunk + 1) * 4;                 // s_len
     b += (size_t)W * T * 4;                       // s_spk
     const size_t pairs = (size_t)W * ntiles_max;
@@ -535,13 +551,8 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk) {
     return (b + 15) & ~(size_t)15;
 }
 
-int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds) {
-    KernelFn f;
-    switch (model) {
-        case CORTEX_MODEL_DELTA: f = pick_fmt<CORTEX_MODEL_DELTA>(meta_bytes, w_bytes, npt); break;
-        case CORTEX_MODEL_EXP: f = pick_fmt<CORTEX_MODEL_EXP>(meta_bytes, w_bytes, npt); break;
-        default: f = pick_fmt<CORTEX_MODEL_ALPHA>(meta_bytes, w_bytes, npt); break;
-    }
+int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds, int ring_bytes) {
+    KernelFn f = pick_variant(model, meta_bytes, w_bytes, npt, ring_bytes);
     if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int nb = 0;

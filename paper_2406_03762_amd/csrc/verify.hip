@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(256) verify_step_kernel(VerifyArgs a, int64_t 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o, 64);
     if (lane == 0 && ev) atomicAdd(a.events, ev);
+    if (lane == 0 && bits) atomicAdd(a.events + 1, (unsigned long long)__popcll(bits));
 }
 
 }  // namespace

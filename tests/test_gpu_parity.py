@@ -179,6 +179,20 @@ def test_fp32_open_loop_delivery_matches_oracle(cx, orc, model, d0, d1):
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
 
 
+def test_fp32_open_loop_with_32bit_rings(cx, orc):
+    # delays of 1..200 steps: 64-bit rings of 201 slots cannot fit the
+    # workgroup-local memory of the chip, so the planner scales 32-bit sums
+    # by the largest exact input bound of any neuron
+    spec = netspec.small_brunel(model="exp", n_e=24000, n_i=6000, c_e=80, c_i=20, delay="uniform_int",
+                                d0=1, d1=200, w_rel_sd=0.1, J=20.0)
+    case("fp32 open loop, 32-bit rings, delays 1..200")
+    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 260, 0.01, 23, 0)
+    assert g.query("RING_BYTES") == 4 and g.query("RING_SLOTS") == 200
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.abs(xo).max() > 0
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
 @pytest.mark.parametrize("steps_per_sync", [0, 1, 2])
 def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc, steps_per_sync):
     spec = netspec.small_brunel(n_e=1600, n_i=400, c_e=160, c_i=40, delay="uniform_int", d0=3, d1=17,
