@@ -22,10 +22,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per synaptic event of the step kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (calibrated against a 1 GiB copy; profiles/step_kernel_config2.md),
+# WRITE_SIZE (calibrated against a 1 GiB copy; profiles/step_kernel_brunel112k_alpha.md),
 # valid only for the kernel source it was measured on.
-TRAFFIC_BYTES_PER_EVENT = (3.0661e7 * 2.0 + 1.3077e5 * 1.0) * 1024 / 9.059842e9
-TRAFFIC_SOURCE_HASH = "4228796da84fd39d"
+TRAFFIC_BYTES_PER_EVENT = (3.1188e7 * 2.0 + 1.3128e5 * 1.0) * 1024 / 9.072019401e9
+TRAFFIC_SOURCE_HASH = "0b399482200ae1cb"
 SIM_STEPS_PER_BENCH_STEP = 10000      # 1 s of biological time at dt = 0.1 ms
 
 
@@ -96,7 +96,7 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
     instances run one after another, and the adjoint (backward) against its
     forward on the first packed group."""
     import netspec
-    spec = netspec.config4()
+    spec = netspec.batched_brunel()
     out = {"workload": "64 balanced delta-LIF instances, N log-uniform 1,250-50,000 (seeded), "
                        "in-degree 10% of each population, delay 1.5 ms, FP32",
            "sim_steps": sim_steps, "neurons": spec.n_neurons}
@@ -166,8 +166,8 @@ def secondary_configs(cx, torch, netspec):
     77,169-neuron exp-current microcircuit stand-in (FP32, 1 s) and the
     1,250-neuron delta-LIF net in the FP64 verification mode (100 ms)."""
     out = {}
-    for name, spec, seed, steps in (("microcircuit_77k_fp32", netspec.config3(), 3, 10000),
-                                    ("brunel_1250_fp64_verify", netspec.config1(), 1, 1000)):
+    for name, spec, seed, steps in (("microcircuit_77k_fp32", netspec.microcircuit_77k(), 3, 10000),
+                                    ("brunel_1250_fp64_verify", netspec.brunel_1250_fp64(), 1, 1000)):
         try:
             log(f"[bench] {name}: building")
             t0 = time.perf_counter()
@@ -233,8 +233,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    spec = netspec.config2()
-    log("[bench] building config2 network")
+    spec = netspec.brunel_112k_alpha()
+    log("[bench] building the 112,500-neuron alpha-LIF network")
     t0 = time.perf_counter()
     net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size,
                      steps_per_sync=args.steps_per_sync)

@@ -144,7 +144,7 @@ def brunel_lambda(eta: float, theta: float, J: float, tau_m: float, dt: float) -
     return eta * theta * dt / (J * tau_m)
 
 
-def config1() -> NetSpec:
+def brunel_1250_fp64() -> NetSpec:
     """1,250-neuron delta-LIF balanced net, FP64 verification (100 ms)."""
     J, g = 0.1, 5.0
     s = NetSpec(model="delta", poisson_lambda=brunel_lambda(2.0, 20.0, J, 20.0, 0.1),
@@ -153,7 +153,7 @@ def config1() -> NetSpec:
     return s
 
 
-def config2(scale_n: float = 1.0, scale_k: float = 1.0) -> NetSpec:
+def brunel_112k_alpha(scale_n: float = 1.0, scale_k: float = 1.0) -> NetSpec:
     """112,500-neuron alpha-current LIF balanced net, FP32 (1 s).
 
     In-degree 9,000 E + 2,250 I, weights Normal(J, (0.1 J)^2) given as PSP
@@ -211,7 +211,7 @@ MC_LAMBDA = 0.8
 MC_W_EXT = 87.8
 
 
-def config3(total: int = MC_TOTAL, target_synapses: float = MC_TARGET_SYNAPSES) -> NetSpec:
+def microcircuit_77k(total: int = MC_TOTAL, target_synapses: float = MC_TARGET_SYNAPSES) -> NetSpec:
     """Eight-population exp-current LIF microcircuit stand-in, FP32 (1 s)."""
     return NetSpec(model="exp", tau_syn=0.5, weight_unit="native",
                    poisson_lambda=MC_LAMBDA, w_ext=MC_W_EXT, precision="fp32",
@@ -227,7 +227,7 @@ def batch_sizes(n_instances: int = 64, lo: int = 1250, hi: int = 50000,
     return [int(max(lo, min(hi, multiple * round(v / multiple)))) for v in x]
 
 
-def config4(sizes: Optional[List[int]] = None) -> NetSpec:
+def batched_brunel(sizes: Optional[List[int]] = None) -> NetSpec:
     """Many independent delta-LIF Brunel instances with in-degree 10% of each
     population, FP32 (200 ms); the adjoint workload."""
     sizes = batch_sizes() if sizes is None else sizes
@@ -240,7 +240,7 @@ def config4(sizes: Optional[List[int]] = None) -> NetSpec:
                    w_ext=J, precision="fp32", instances=insts)
 
 
-def config5(scale_n: float = 1.0) -> NetSpec:
+def brunel_2m_bf16(scale_n: float = 1.0) -> NetSpec:
     """2M-neuron delta-LIF balanced net, bf16 weights, delays 5..30 steps."""
     J, g = 0.1, 5.0
     n_e = int(round(1_600_000 * scale_n))

@@ -111,9 +111,9 @@ def test_poisson_counts_bit_exact(cx, orc, precision):
     assert np.array_equal(v[0], vo[0])
 
 
-def test_fp64_closed_loop_raster_bit_exact_config1(cx, orc):
-    spec = netspec.config1()
-    case("config1 FP64 closed loop 1000 steps")
+def test_fp64_closed_loop_raster_bit_exact_brunel_1250(cx, orc):
+    spec = netspec.brunel_1250_fp64()
+    case("brunel 1,250 FP64 closed loop 1000 steps")
     g = cx.Network(spec, 1, record_steps=1000)
     g.step(1000)
     st, ids = g.spikes(0, 1000)
@@ -213,10 +213,10 @@ def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc, steps_per_sy
     assert g.query("EVENTS") == outdeg[ids[m]].sum()
 
 
-def test_fp32_closed_loop_statistics_scaled_config2(cx, orc):
-    spec = netspec.config2(scale_n=0.1, scale_k=0.1)
+def test_fp32_closed_loop_statistics_scaled_brunel_112k(cx, orc):
+    spec = netspec.brunel_112k_alpha(scale_n=0.1, scale_k=0.1)
     T = 10000
-    case("fp32 closed loop config2 x0.1, 1 s")
+    case("fp32 closed loop brunel 112k x0.1, 1 s")
     g = cx.Network(spec, 2, record_steps=T)
     g.step(T)
     st, ids = g.spikes(0, T)
@@ -240,7 +240,7 @@ def test_fp32_closed_loop_statistics_scaled_config2(cx, orc):
 def test_fp32_results_do_not_depend_on_the_plan(cx):
     # fixed-point input sums make the FP32 path independent of tile size,
     # spike-exchange window and workgroup size, bit for bit
-    spec = netspec.config2(scale_n=0.05, scale_k=0.05)
+    spec = netspec.brunel_112k_alpha(scale_n=0.05, scale_k=0.05)
     T = 1500
     outs = []
     for plan in (dict(), dict(tile_size=300, steps_per_sync=2), dict(tile_size=128, block_size=256,
@@ -259,13 +259,13 @@ def test_fp32_results_do_not_depend_on_the_plan(cx):
             assert np.array_equal(a, b)
 
 
-def test_full_size_config2_sampled_open_loop(cx, orc):
-    spec = netspec.config2()
+def test_full_size_brunel_112k_sampled_open_loop(cx, orc):
+    spec = netspec.brunel_112k_alpha()
     N = spec.n_neurons
     sel = np.unique(np.concatenate([[0, 439, 440, N - 1],
                                     netspec.sample_targets(N, 28, seed=5)]))
     T = 60
-    case("config2 full size sampled open loop")
+    case("brunel 112k full size sampled open loop")
     g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, T, 0.002, 2, 0, sel=sel)
     assert g.E == 112500 * 11250
     assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
@@ -295,7 +295,7 @@ BATCH_SIZES = [200, 450, 1000, 2200, 5000]
 
 
 def test_batched_instances_graph_and_tiles(cx, orc):
-    spec = netspec.config4(BATCH_SIZES)
+    spec = netspec.batched_brunel(BATCH_SIZES)
     case("batched graph, 5 instances")
     g = cx.Network(spec, 4)
     o = orc.OracleNet(spec, 4)
@@ -316,7 +316,7 @@ def test_batched_instances_graph_and_tiles(cx, orc):
 
 
 def test_batched_open_loop_matches_oracle(cx, orc):
-    spec = netspec.config4(BATCH_SIZES)
+    spec = netspec.batched_brunel(BATCH_SIZES)
     case("batched open loop")
     g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 120, 0.01, 4, 0)
     assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
@@ -325,7 +325,7 @@ def test_batched_open_loop_matches_oracle(cx, orc):
 
 def test_batched_closed_loop_rates(cx, orc):
     sizes = [1000, 2000, 4000]
-    spec = netspec.config4(sizes)
+    spec = netspec.batched_brunel(sizes)
     T = 2000
     case("batched closed loop rates")
     g = cx.Network(spec, 5, record_steps=T)
@@ -374,7 +374,7 @@ def test_adjoint_matches_oracle_on_frozen_raster(cx, orc, model):
 
 
 def test_adjoint_batched_instances(cx, orc):
-    spec = netspec.config4([300, 700, 1500])
+    spec = netspec.batched_brunel([300, 700, 1500])
     case("adjoint batched")
     g, o, gr, loss, gro, loss_o = _adjoint_case(cx, orc, spec, 230, 100, 41)
     assert loss == pytest.approx(loss_o, rel=1e-5)
@@ -383,7 +383,7 @@ def test_adjoint_batched_instances(cx, orc):
 
 def test_adjoint_closed_loop_is_repeatable_and_restores_state(cx):
     import torch
-    spec = netspec.config4([1000, 2000])
+    spec = netspec.batched_brunel([1000, 2000])
     T = 300
     case("adjoint closed loop")
     g = cx.Network(spec, 6, ckpt_every=100, adjoint_steps=T)
