@@ -39,7 +39,6 @@ namespace {
 
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
 constexpr int kInline = 1;        // spike ids fetched together with a tile's step record
-constexpr int kBlk = 512;         // 64-edge blocks per piece of a delivery chunk
 
 struct StepArgs {
     const int32_t* inst_tile0;
@@ -133,10 +132,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     const size_t pub_slot = (size_t)a.n_tiles * pub_tile;
     const int pairs_max = a.W * a.ntb_max;
 
-    // s_sg[k] describes segment k of a delivery chunk: x = end of the
-    // segment in the flattened edge space, y = step offset of the spike,
-    // (z, w) = edge index of the segment's first synapse minus its flattened
-    // start (64-bit, modular), so edge = base + flattened position
+    // s_sg[k] describes segment k of a delivery chunk: x = its number of
+    // synapses, y = step offset of the spike within the delivered steps,
+    // (z, w) = index of its first synapse (64-bit)
     uint4* s_sg = reinterpret_cast<uint4*>(lds_raw);                // CH
     RING* ring = reinterpret_cast<RING*>(s_sg + CH);                // R * T
     uint32_t* s_len = reinterpret_cast<uint32_t*>(ring + (size_t)R * T);   // CH + 1
@@ -149,7 +147,6 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_cnt + 8);      // T (bit si: frozen spike at step si)
     uint32_t* s_thr = s_frz + T;                                    // kMaxThr Poisson thresholds
     unsigned char* s_kcb = reinterpret_cast<unsigned char*>(s_thr + kMaxThr);  // 2 x 8 x T Poisson counts
-    uint32_t* s_blk = reinterpret_cast<uint32_t*>(s_kcb + (size_t)16 * T);        // kBlk
 
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
@@ -306,7 +303,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
                     const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
                     const uint64_t beg = rs + o0;
-                    s_sg[k] = make_uint4(0u, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
+                    s_sg[k] = make_uint4(o1 - o0, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
                     s_len[k] = o1 - o0;
                 }
                 if (bail) {
@@ -318,76 +315,65 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
                 if (tid == 0) s_len[cn] = EL;
                 __syncthreads();
-                for (int k = tid; k < cn; k += bs) {
-                    uint4 g = s_sg[k];
-                    const uint64_t base = (((uint64_t)g.w << 32) | g.z) - (uint64_t)s_len[k];
-                    g.x = s_len[k + 1];
-                    g.z = (uint32_t)base;
-                    g.w = (uint32_t)(base >> 32);
-                    s_sg[k] = g;
-                }
-                // The flattened edges are walked in pieces of at most 64 * kBlk;
-                // s_blk[b] is the segment holding the piece's edge 64 b, so a
-                // lane starts its segment search next to its edge
-                for (uint32_t pc0 = 0; pc0 < EL; pc0 += 64u * kBlk) {
-                const uint32_t pc1 = min(EL, pc0 + 64u * kBlk);
-                for (int k = tid; k < cn; k += bs) {
-                    const uint32_t lo = max(s_len[k], pc0), hi = min(s_len[k + 1], pc1);
-                    for (uint32_t bb = (lo + 63u) >> 6; (bb << 6) < hi; ++bb) s_blk[bb - (pc0 >> 6)] = (uint32_t)k;
-                }
-                __syncthreads();
-                // each wave walks a contiguous range of the flattened
-                // (spike, synapse) space; a lane advances its segment index
-                const uint32_t per = ((pc1 - pc0 + n_waves - 1) / n_waves + 63) & ~63u;
-                const uint32_t f_beg = pc0 + min(pc1 - pc0, (uint32_t)wave * per);
-                const uint32_t f_end = min(pc1, f_beg + per);
-                uint32_t f = f_beg + lane;
-                while (f < f_end) {
-                    // all loads of a batch are issued before any is used; the
-                    // step offset of each edge (< 8) is kept in 4-bit fields
-                    constexpr int U4 = 16;
-                    uint32_t m[U4];
-                    float wv[U4];
-                    uint32_t qpk[U4 / 8];
-#pragma unroll
-                    for (int h = 0; h < U4 / 8; ++h) qpk[h] = 0;
-#pragma unroll
-                    for (int u = 0; u < U4; ++u) {
-                        const uint32_t fu = f + 64u * u;
-                        m[u] = 0;
-                        wv[u] = 0.f;
-                        if (fu < f_end) {
-                            int seg = (int)s_blk[((fu - (uint32_t)lane) - pc0) >> 6];
-                            uint4 g = s_sg[seg];
-                            while (g.x <= fu) g = s_sg[++seg];
-                            const uint64_t e = (((uint64_t)g.w << 32) | g.z) + fu;
-                            qpk[u >> 3] |= (g.y | 8u) << (4 * (u & 7));
-                            m[u] = static_cast<const META*>(a.meta)[e];
-                            wv[u] = load_w(a.w, e, WBF16);
-                        }
+                // Each wave takes a contiguous run of whole segments holding
+                // about EL / n_waves synapses (a segment belongs to the wave
+                // whose share contains its first synapse).  It reads the
+                // descriptors of 8 segments at once; lane l handles synapses
+                // l, l + 64, ... of each, so the loads of a segment are
+                // contiguous and the spike's step offset is the same for the
+                // whole wave.
+                const uint32_t share = (EL + n_waves - 1) / n_waves;
+                auto first_seg = [&](uint32_t fpos) {
+                    int lo = 0, hi = cn;          // first k with s_len[k] >= fpos
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_len[mid] < fpos) lo = mid + 1; else hi = mid;
                     }
+                    return lo;
+                };
+                const int kw0 = first_seg(min(EL, (uint32_t)wave * share));
+                const int kw1 = first_seg(min(EL, (uint32_t)(wave + 1) * share));
+                for (int k0 = kw0; k0 < kw1; k0 += 8) {
+                    constexpr int U8 = 8;
+                    uint4 g[U8];
+                    uint32_t len_max = 0;
 #pragma unroll
-                    for (int u = 0; u < U4; ++u) {
-                        const uint32_t q = (qpk[u >> 3] >> (4 * (u & 7))) & 15u;
-                        if (q & 8u) {
-                            int sl = base_slot + (int)(q & 7u) + (int)(m[u] >> a.tbits);
-                            if (sl >= R) sl -= R;
-                            // w 2^fx in 64-bit fixed point: round w 2^(fx - fx_shift)
-                            // to a 32-bit integer, then shift (exact)
-                            const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
-                            RING* dst = &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)];
-                            if (sizeof(RING) == 8) {
-                                const long long iv = (long long)iw << a.fx_shift;
-                                atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)iv);
-                            } else {
-                                // 32-bit rings: the scale keeps every sum below 2^31
-                                atomicAdd(reinterpret_cast<unsigned int*>(dst), (unsigned int)iw);
+                    for (int u = 0; u < U8; ++u) {
+                        g[u] = (k0 + u < kw1) ? s_sg[k0 + u] : make_uint4(0u, 0u, 0u, 0u);
+                        len_max = max(len_max, g[u].x);
+                    }
+                    for (uint32_t o = lane; o < len_max + lane; o += 64u) {
+                        uint32_t m[U8];
+                        float wv[U8];
+#pragma unroll
+                        for (int u = 0; u < U8; ++u) {
+                            m[u] = 0;
+                            wv[u] = 0.f;
+                            if (o < g[u].x) {
+                                const uint64_t e = (((uint64_t)g[u].w << 32) | g[u].z) + o;
+                                m[u] = static_cast<const META*>(a.meta)[e];
+                                wv[u] = load_w(a.w, e, WBF16);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < U8; ++u) {
+                            if (o < g[u].x) {
+                                int sl = base_slot + (int)g[u].y + (int)(m[u] >> a.tbits);
+                                if (sl >= R) sl -= R;
+                                // w 2^fx in fixed point: round w 2^(fx - fx_shift) to a
+                                // 32-bit integer, then shift (exact)
+                                const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
+                                RING* dst = &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)];
+                                if (sizeof(RING) == 8) {
+                                    const long long iv = (long long)iw << a.fx_shift;
+                                    atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)iv);
+                                } else {
+                                    // 32-bit rings: the scale keeps every sum below 2^31
+                                    atomicAdd(reinterpret_cast<unsigned int*>(dst), (unsigned int)iw);
+                                }
                             }
                         }
                     }
-                    f += 64u * U4;
-                }
-                __syncthreads();   // s_blk is refilled for the next piece
                 }
                 ev += EL;
                 __syncthreads();
@@ -547,7 +533,6 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_b
     b += (size_t)T * 4;                           // s_frz
     b += (size_t)kMaxThr * 4;                     // s_thr
     b += (size_t)16 * T;                          // s_kcb
-    b += (size_t)kBlk * 4;                        // s_blk
     return (b + 15) & ~(size_t)15;
 }
 
