@@ -172,6 +172,17 @@ int cortex_run_frozen(cortex_net* net, const uint32_t* r_steps, const uint32_t* 
    Synchronising.  Errors: ESTATE (adjoint not enabled / window too long). */
 int cortex_backward(cortex_net* net, const float* vstar, float* grad_w, double* loss);
 
+/* Replace every stored synaptic weight (native units; FP32 networks with
+   spec.ckpt_every > 0, at step 0, i.e. after the build or cortex_reset):
+   w_canonical is a device float [E] in canonical synapse order (caller
+   owned, read only).  Weights are stored in the network's weight format and
+   the input rings' fixed-point scale is recomputed from the new weights, so
+   the sums stay exact for any weights.  This and cortex_backward let a caller
+   run the adjoint on weights it chooses (e.g. a training loop).  Errors:
+   ESTATE (not at step 0, or no canonical order without ckpt_every),
+   EUNSUPPORTED (FP64 networks), EINVAL (NULL). */
+int cortex_set_weights(cortex_net* net, const float* w_canonical);
+
 /* Back to the build-time state (step 0, empty input rings, empty log). */
 int cortex_reset(cortex_net* net);
 

@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
         L.cortex_clear_spikes.argtypes = [P]
         L.cortex_run_frozen.argtypes = [P, P, P, i64, i64, P, P]
         L.cortex_backward.argtypes = [P, P, P, C.POINTER(C.c_double)]
+        L.cortex_set_weights.argtypes = [P, P]
         L.cortex_reset.argtypes = [P]
         L.cortex_get_state.argtypes = [P, P, P, P, P]
         L.cortex_export_graph.argtypes = [P, P, P, P, P]
@@ -226,6 +227,10 @@ def cortex_run_frozen(h, steps, ids, n_steps: int, x_trace=None, v_trace=None) -
                                    _ptr(x_trace), _ptr(v_trace)))
 
 
+def cortex_set_weights(h, w_canonical) -> None:
+    _check(lib().cortex_set_weights(h, _ptr(w_canonical)))
+
+
 def cortex_backward(h, vstar, grad_w) -> float:
     loss = C.c_double()
     _check(lib().cortex_backward(h, _ptr(vstar), _ptr(grad_w), C.byref(loss)))
@@ -327,6 +332,19 @@ class Network:
         loss = cortex_backward(self._h, vstar, grad)
         return grad, loss
 
+    def set_weights(self, w_canonical) -> None:
+        """Replace all weights (device float tensor [E], canonical order); at step 0."""
+        w = w_canonical.detach().to(dtype=self.torch.float32).contiguous()
+        cortex_set_weights(self._h, w)
+        self.torch.cuda.current_stream().synchronize()
+
+    def canonical_weights(self):
+        """The stored weights as a float64 numpy array in canonical synapse order."""
+        _, _, w, _ = self.graph()
+        out = np.empty_like(w)
+        out[self.canonical()] = w
+        return out
+
     def reset(self) -> None:
         cortex_reset(self._h)
 
@@ -344,6 +362,82 @@ class Network:
 
     def tiles(self):
         return cortex_export_tiles(self._h, self.query("TILES"))
+
+
+def autotune(net, seed: int, steps: int = 500, warmup: int = 100, tile_sizes=(0,), **plan):
+    """Pick the launch plan of an FP32 network by measurement: build it with
+    every steps-per-exchange window from its minimum delay down to 1 (and the
+    given tile sizes, 0 = the planner's balanced tiles), time ``steps``
+    closed-loop steps after ``warmup`` and return (best plan dict, timings).
+    Candidates that cannot be planned on this device are skipped."""
+    import time
+    import torch
+    probe = Network(net, seed, **plan)
+    w_max = probe.query("STEPS_PER_SYNC")
+    d_min = probe.query("MIN_DELAY")
+    probe.close()
+    results = []
+    for T in tile_sizes:
+        for W in range(min(8, d_min), 0, -1):
+            cand = dict(plan, tile_size=T, steps_per_sync=W)
+            try:
+                g = Network(net, seed, **cand)
+            except CortexError as e:
+                if e.status in (EUNSUPPORTED, EINVAL):
+                    continue
+                raise
+            g.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            results.append((time.perf_counter() - t0, cand))
+            g.close()
+            if W < w_max and len(results) >= 2 and results[-1][0] > 1.5 * min(r[0] for r in results):
+                break   # shorter windows only add exchanges from here on
+    if not results:
+        raise CortexError(EUNSUPPORTED, "no candidate plan fits this device")
+    best = min(results, key=lambda r: r[0])[1]
+    return best, [(c, t) for t, c in results]
+
+
+class VoltageLoss:
+    """Membrane-voltage loss of a network as a function of its weights, for
+    torch.autograd: ``VoltageLoss.apply(w, net, vstar, n_steps, raster)``
+    resets ``net``, sets the weights ``w`` (canonical order), runs
+    ``n_steps`` (closed loop, or open loop on ``raster = (steps, ids)``),
+    and returns L = sum_b 1/(N_b T) sum (V - V*)^2; its gradient with respect
+    to ``w`` is the adjoint's, with every spike held at the time it occurred
+    in this run.  ``net`` must be built with ckpt_every > 0 and
+    adjoint_steps >= n_steps."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, w, net, vstar, n_steps: int, raster=None):
+        import torch
+
+        if cls._fn is None:
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, w_, net_, vstar_, n_steps_, raster_):
+                    net_.reset()
+                    net_.set_weights(w_)
+                    if raster_ is None:
+                        net_.step(n_steps_)
+                    else:
+                        net_.run_frozen(raster_[0], raster_[1], n_steps_, traces=False)
+                    grad, loss = net_.backward(vstar_)
+                    ctx.save_for_backward(grad)
+                    return torch.tensor(loss, dtype=torch.float64, device=w_.device)
+
+                @staticmethod
+                def backward(ctx, g_out):
+                    (grad,) = ctx.saved_tensors
+                    return (g_out.to(grad.dtype) * grad).to(dtype=torch.float32), None, None, None, None
+
+            cls._fn = _Fn
+        return cls._fn.apply(w, net, vstar, n_steps, raster)
 
 
 def header_functions(path: str = HEADER):

@@ -942,6 +942,32 @@ int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* lo
     CX_API_END
 }
 
+int cortex_set_weights(cortex_net* n, const float* w_canonical) {
+    CX_API_BEGIN
+    require_net(n);
+    require(w_canonical != nullptr, CORTEX_EINVAL, "w_canonical is NULL");
+    require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "weights are set in FP32 mode");
+    require(n->d_canon != nullptr, CORTEX_ESTATE, "setting weights needs ckpt_every > 0 (canonical order)");
+    require(n->step == 0, CORTEX_ESTATE, "weights are set at step 0 (after the build or cortex_reset)");
+    check_device_flag(n);
+    set_weights_fp32(n, w_canonical);
+    // fixed-point scale from the exact bound of the new weights
+    double wmax = 0.0;
+    const double bound = max_abs_input(n, &wmax) * (1.0 + 1e-4) + 1e-30;
+    const int lg = (int)std::ceil(std::log2(bound));
+    if (n->ring_bytes == 8) {
+        n->fx = std::max(0, std::min(52, 61 - lg));
+        const int fxw = 30 - (int)std::ceil(std::log2(wmax * (1.0 + 1e-6) + 1e-30));
+        n->fx_shift = std::max(0, n->fx - std::max(0, fxw));
+    } else {
+        n->fx = std::max(0, std::min(52, 30 - lg));
+        n->fx_shift = 0;
+    }
+    free_scratch(n);
+    return CORTEX_OK;
+    CX_API_END
+}
+
 int cortex_reset(cortex_net* n) {
     CX_API_BEGIN
     require_net(n);

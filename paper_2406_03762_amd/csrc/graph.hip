@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_star
                                                         int tbits, const int64_t* inst_n0,
                                                         const uint64_t* inst_offbase, const int32_t* inst_ntiles,
                                                         const int32_t* inst_T, int n_inst, int64_t N,
-                                                        double* sum) {
+                                                        double* sum, unsigned int* wmax_bits) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -515,6 +515,7 @@ __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_star
                 const float wv = wbf16 ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16)
                                        : static_cast<const float*>(w)[e];
                 atomicAdd(&sum[g0 + (m & tmask)], (double)fabsf(wv));
+                atomicMax(wmax_bits, __float_as_uint(fabsf(wv)));   // non-negative floats order as integers
             }
         }
     }
@@ -522,20 +523,47 @@ __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_star
 
 }  // namespace
 
-double max_abs_input(cortex_net* n) {
+double max_abs_input(cortex_net* n, double* wmax) {
     double* sum = dev_alloc_t<double>(n, std::max<int64_t>(1, n->N), true);
+    unsigned int* wbits = dev_alloc_t<unsigned int>(n, 1, true);
     dev_zero(n, sum, (size_t)n->N * sizeof(double));
+    dev_zero(n, wbits, sizeof(unsigned int));
     hipLaunchKernelGGL(abs_input_kernel, dim3(grid_for(n->N * 64, 256)), dim3(256), 0, n->stream, n->d_row_start,
                        n->d_off_rel, n->d_meta, n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0,
                        n->tbits, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->d_inst_T, n->n_inst, n->N,
-                       sum);
+                       sum, wbits);
     CX_HIP(hipGetLastError());
     std::vector<double> h((size_t)n->N);
+    unsigned int wb = 0;
     CX_HIP(hipMemcpyAsync(h.data(), sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    CX_HIP(hipMemcpyAsync(&wb, wbits, sizeof wb, hipMemcpyDeviceToHost, n->stream));
     CX_HIP(hipStreamSynchronize(n->stream));
     double m = 0.0;
     for (double v : h) m = std::max(m, v);
+    if (wmax) {
+        float wf;
+        std::memcpy(&wf, &wb, sizeof wf);
+        *wmax = wf;
+    }
     return m;
+}
+
+namespace {
+// Stored weight of every synapse from a canonical-order array (setup).
+__global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, void* w, int wbf16, int64_t E) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = w_canon[canon[e]];
+        if (wbf16) static_cast<uint16_t*>(w)[e] = to_bf16((double)v);
+        else static_cast<float*>(w)[e] = v;
+    }
+}
+}  // namespace
+
+void set_weights_fp32(cortex_net* n, const float* w_canonical) {
+    if (n->E == 0) return;
+    hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(n->E, 256)), dim3(256), 0, n->stream, w_canonical,
+                       n->d_canon, n->d_w, n->w_bytes == 2 ? 1 : 0, n->E);
+    CX_HIP(hipGetLastError());
 }
 
 void build_graph_fp32(cortex_net* n) {

@@ -179,8 +179,11 @@ T* dev_alloc_t(cortex_net* n, size_t count, bool scratch = false) {
 // Kernel launchers (graph.hip) -----------------------------------------------
 void delay_range(cortex_net* n, int* dmin, int* dmax);
 void build_graph_fp32(cortex_net* n);
-// Largest sum of |w| over the stored in-synapses of any neuron (after build_graph_fp32).
-double max_abs_input(cortex_net* n);
+// Largest sum of |w| over the stored in-synapses of any neuron (after
+// build_graph_fp32); *wmax (if not NULL) gets the largest single |w|.
+double max_abs_input(cortex_net* n, double* wmax = nullptr);
+// Stored weights from a device array in canonical synapse order.
+void set_weights_fp32(cortex_net* n, const float* w_canonical);
 void build_graph_fp64(cortex_net* n);
 void init_state(cortex_net* n);
 // step.hip

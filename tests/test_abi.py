@@ -96,6 +96,7 @@ def test_null_handles_return_einval(L):
     assert L.cortex_reset(None) == cx.EINVAL
     assert L.cortex_get_spikes(None, 0, 1, None, None, 0, C.byref(v)) == cx.EINVAL
     assert L.cortex_backward(None, None, None, None) == cx.EINVAL
+    assert L.cortex_set_weights(None, None) == cx.EINVAL
     L.cortex_destroy(None)
 
 

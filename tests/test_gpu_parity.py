@@ -373,6 +373,57 @@ def test_adjoint_matches_oracle_on_frozen_raster(cx, orc, model):
     assert np.array_equal(os_[canon], src) and np.array_equal(ot[canon], tgt) and np.array_equal(od[canon], d)
 
 
+def test_set_weights_gradient_matches_oracle_and_finite_differences(cx, orc):
+    import torch
+    spec = netspec.small_brunel(model="exp", n_e=400, n_i=100, c_e=40, c_i=10, delay="uniform_int",
+                                d0=2, d1=9, w_rel_sd=0.1, J=20.0)
+    T, seed = 200, 37
+    N = spec.n_neurons
+    steps, ids = netspec.refractory_raster(N, T, 0.02, seed=seed, n_ref=20)
+    vstar = netspec.target_trace(N, T, 10.0, 20.0, seed=seed + 1)
+    case("set weights: gradient vs oracle and finite differences")
+    g = cx.Network(spec, seed, ckpt_every=50, adjoint_steps=T)
+    w0 = g.canonical_weights()
+    rng = np.random.default_rng(seed + 2)
+    w1 = (w0 * (1.0 + 0.3 * rng.standard_normal(w0.size))).astype(np.float32)
+    vs = torch.tensor(vstar, dtype=torch.float32, device="cuda")
+    w = torch.tensor(w1, device="cuda", requires_grad=True)
+    raster = (steps, ids)
+    loss = cx.VoltageLoss.apply(w, g, vs, T, raster)
+    loss.backward()
+    gr = w.grad.detach().cpu().numpy().astype(np.float64)
+    # the stored weights are the new ones
+    assert np.array_equal(g.canonical_weights(), w1.astype(np.float64))
+    # oracle with the same weights (canonical order is shared)
+    o = orc.OracleNet(spec, seed)
+    for e in range(o.E):
+        o.set_weight(e, float(w1[e]))
+    gro, loss_o = o.backward(steps, ids, T, vstar.astype(np.float32).astype(np.float64))
+    assert float(loss) == pytest.approx(loss_o, rel=1e-5)
+    assert np.allclose(gr, gro, rtol=1e-3, atol=1e-4 * np.abs(gro).max())
+    # central differences of the GPU loss (quadratic in w with frozen spikes)
+    for e in np.argsort(-np.abs(gr))[:4]:
+        h = 0.2 * abs(float(w1[e]))
+        lp = float(cx.VoltageLoss.apply(torch.tensor(np.where(np.arange(w1.size) == e, w1 + h, w1)
+                                                     .astype(np.float32), device="cuda"), g, vs, T, raster))
+        lm = float(cx.VoltageLoss.apply(torch.tensor(np.where(np.arange(w1.size) == e, w1 - h, w1)
+                                                     .astype(np.float32), device="cuda"), g, vs, T, raster))
+        h_eff = float(np.float32(w1[e] + h)) - float(np.float32(w1[e] - h))
+        assert (lp - lm) / h_eff == pytest.approx(gr[e], rel=2e-2)
+
+
+def test_autotune_returns_the_fastest_valid_plan(cx):
+    spec = netspec.batched_brunel([600, 1200, 2400])
+    case("autotune on 3 batched instances")
+    best, timings = cx.autotune(spec, 9, steps=300, warmup=50)
+    assert timings and all(t > 0 for _, t in timings)
+    assert best == min(timings, key=lambda ct: ct[1])[0]
+    g = cx.Network(spec, 9, **best)
+    assert g.query("STEPS_PER_SYNC") == best["steps_per_sync"]
+    g.step(100)
+    assert g.query("SPIKES") > 0
+
+
 def test_adjoint_batched_instances(cx, orc):
     spec = netspec.batched_brunel([300, 700, 1500])
     case("adjoint batched")
