@@ -151,7 +151,7 @@ struct WgradArgs {
     const uint32_t* off_rel;
     const void* meta;
     int meta16;
-    int tbits, dmin;
+    int T, dmin;                // record = (delay - dmin) T + target in tile
     const uint64_t* src_ptr;    // [n_inst + 1] into src_id
     const uint32_t* src_id;     // spiking sources, grouped by instance
     const uint64_t* spk_ptr;    // [n_src + 1] into spk_step
@@ -170,7 +170,6 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
     const int ntb = a.inst_ntiles[b];
     const int64_t n0b = a.inst_n0[b];
     const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
-    const uint32_t tmask = (1u << a.tbits) - 1u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
     for (uint64_t s = a.src_ptr[b] + wave; s < a.src_ptr[b + 1]; s += n_waves) {
         const uint32_t j = a.src_id[s];
@@ -180,8 +179,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
         for (uint64_t e = e0 + lane; e < e1; e += 64) {
             const uint32_t m = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
                                         : static_cast<const uint32_t*>(a.meta)[e];
-            const int64_t d = a.dmin + (int64_t)(m >> a.tbits);
-            const int64_t tgt = g0 + (m & tmask);
+            const int64_t d = a.dmin + (int64_t)(m / (uint32_t)a.T);
+            const int64_t tgt = g0 + (m % (uint32_t)a.T);
             float acc = 0.f;
             for (uint64_t p = p0; p < p1; ++p) {
                 const int64_t tau = a.spk_step[p] + d;
@@ -397,7 +396,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 wa.tile_inst = n->d_tile_inst; wa.inst_tile0 = n->d_inst_tile0; wa.inst_ntiles = n->d_inst_ntiles;
                 wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0; wa.inst_offbase = n->d_inst_offbase;
                 wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
-                wa.meta16 = n->meta_bytes == 2; wa.tbits = n->tbits; wa.dmin = n->dmin;
+                wa.meta16 = n->meta_bytes == 2; wa.T = n->T; wa.dmin = n->dmin;
                 wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
                 wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
                 hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(256), 0, n->stream, wa);

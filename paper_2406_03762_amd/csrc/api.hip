@@ -1041,7 +1041,7 @@ int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, in
         auto m = download(n, static_cast<const float*>(n->d_w), n->E);
         for (int64_t e = 0; e < n->E; ++e) wv[e] = m[e];
     }
-    const uint32_t tmask = (1u << n->tbits) - 1u;
+    const uint32_t ts = (uint32_t)n->T;   // record = (delay - dmin) T + target in tile
     for (int b = 0; b < n->n_inst; ++b) {
         const int nt = n->inst_ntiles[b];
         for (int64_t jl = 0; jl < n->inst_N[b]; ++jl) {
@@ -1050,9 +1050,9 @@ int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, in
             for (int t = 0; t < nt; ++t) {
                 for (uint64_t e = rs[j] + off[ob + t]; e < rs[j] + off[ob + t + 1]; ++e) {
                     if (src) src[e] = j;
-                    if (tgt) tgt[e] = n->inst_n0[b] + (int64_t)t * n->inst_T[b] + (meta[e] & tmask);
+                    if (tgt) tgt[e] = n->inst_n0[b] + (int64_t)t * n->inst_T[b] + (meta[e] % ts);
                     if (w) w[e] = wv[e];
-                    if (d) d[e] = n->dmin + (int32_t)(meta[e] >> n->tbits);
+                    if (d) d[e] = n->dmin + (int32_t)(meta[e] / ts);
                 }
             }
         }

@@ -47,14 +47,18 @@ __device__ __forceinline__ uint64_t uniform_below(uint64_t u, uint64_t n) { retu
 __device__ __forceinline__ double unit_closed0(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
 __device__ __forceinline__ double unit_open0(uint64_t u) { return (double)((u >> 11) + 1) * 0x1.0p-53; }
 
-// Wave (64 lanes) inclusive scan of 32-bit values.
+// Wave (64 lanes) inclusive scan of 32-bit values with DPP lane moves:
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from
+// outside the row read 0), then the last lane of row 0 is added to row 1 and
+// that of row 2 to row 3 (row_bcast:15), then the last lane of row 1 to rows
+// 2 and 3 (row_bcast:31).  Lanes a row mask leaves out keep `old` = 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return x;
 }
 
@@ -67,20 +71,22 @@ __device__ inline uint32_t block_excl_scan(uint32_t* data, int n, uint32_t* wsum
     const int beg = min(n, tid * per), end = min(n, beg + per);
     uint32_t local = 0;
     for (int i = beg; i < end; ++i) local += data[i];
-    uint32_t inc = wave_incl_scan(local);
+    const uint32_t inc = wave_incl_scan(local);
     const int wave = tid >> 6, lane = tid & 63;
+    const int nw = (bs + 63) >> 6;
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        const int nw = (bs + 63) >> 6;
-        for (int w = 0; w < nw; ++w) { uint32_t t = wsum[w]; wsum[w] = acc; acc += t; }
-        wsum[nw] = acc;
+    if (wave == 0) {
+        // exclusive offsets of the waves (nw <= 16), and the total
+        const uint32_t v = lane < nw ? wsum[lane] : 0u;
+        const uint32_t vi = wave_incl_scan(v);
+        if (lane < nw) wsum[lane] = vi - v;
+        if (lane == nw - 1) wsum[nw] = vi;
     }
     __syncthreads();
     uint32_t run = wsum[wave] + inc - local;
     for (int i = beg; i < end; ++i) { uint32_t t = data[i]; data[i] = run; run += t; }
-    const uint32_t total = wsum[(bs + 63) >> 6];
+    const uint32_t total = wsum[nw];
     __syncthreads();
     return total;
 }

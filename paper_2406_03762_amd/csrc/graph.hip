@@ -53,7 +53,7 @@ struct GenArgs {
     const uint32_t* off_rel;
     void* meta;
     void* w;
-    int tbits;
+    int T;          // ring row stride: a record is (delay - dmin) T + target in tile
     int dmin;
     int meta16;
     int wbf16;
@@ -163,8 +163,7 @@ __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_
         } else {
             const uint32_t k = atomicAdd(&a.cnt[key], 1u);
             const uint64_t pos = a.row_start[src_global] + a.off_rel[key] + k;
-            const uint32_t m = (uint32_t)(tl - tile_local * Tb) |
-                               ((uint32_t)(dr.d - a.dmin) << a.tbits);
+            const uint32_t m = (uint32_t)(tl - tile_local * Tb) + (uint32_t)(dr.d - a.dmin) * (uint32_t)a.T;
             if (a.meta16) static_cast<uint16_t*>(a.meta)[pos] = (uint16_t)m;
             else static_cast<uint32_t*>(a.meta)[pos] = m;
             if (a.wbf16) static_cast<uint16_t*>(a.w)[pos] = to_bf16(w);
@@ -491,14 +490,13 @@ namespace {
 // segments tile by tile.  Setup only.
 __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_start, const uint32_t* off_rel,
                                                         const void* meta, int meta16, const void* w, int wbf16,
-                                                        int tbits, const int64_t* inst_n0,
+                                                        int T, const int64_t* inst_n0,
                                                         const uint64_t* inst_offbase, const int32_t* inst_ntiles,
                                                         const int32_t* inst_T, int n_inst, int64_t N,
                                                         double* sum, unsigned int* wmax_bits) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t tmask = (1u << tbits) - 1u;
     for (int64_t j = wave; j < N; j += n_waves) {
         int lo = 0, hi = n_inst;
         while (hi - lo > 1) {
@@ -514,7 +512,7 @@ __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_star
                 const uint32_t m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
                 const float wv = wbf16 ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16)
                                        : static_cast<const float*>(w)[e];
-                atomicAdd(&sum[g0 + (m & tmask)], (double)fabsf(wv));
+                atomicAdd(&sum[g0 + (m % (uint32_t)T)], (double)fabsf(wv));
                 atomicMax(wmax_bits, __float_as_uint(fabsf(wv)));   // non-negative floats order as integers
             }
         }
@@ -530,7 +528,7 @@ double max_abs_input(cortex_net* n, double* wmax) {
     dev_zero(n, wbits, sizeof(unsigned int));
     hipLaunchKernelGGL(abs_input_kernel, dim3(grid_for(n->N * 64, 256)), dim3(256), 0, n->stream, n->d_row_start,
                        n->d_off_rel, n->d_meta, n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0,
-                       n->tbits, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->d_inst_T, n->n_inst, n->N,
+                       n->T, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->d_inst_T, n->n_inst, n->N,
                        sum, wbits);
     CX_HIP(hipGetLastError());
     std::vector<double> h((size_t)n->N);
@@ -604,13 +602,10 @@ void build_graph_fp32(cortex_net* n) {
     CX_HIP(hipStreamSynchronize(n->stream));
     n->E = (int64_t)E;
     // record format
-    int tb = 0;
-    while ((1 << tb) < n->T) ++tb;
-    int db = 0;
-    while ((1 << db) < n->R) ++db;
-    n->tbits = tb;
-    require(tb + db <= 32, CORTEX_EUNSUPPORTED, "tile size and delay range too large for 32-bit records");
-    n->meta_bytes = (tb + db <= 16) ? 2 : 4;
+    // a record is (delay - dmin) T + target: every record is below R T
+    const uint64_t rt = (uint64_t)n->R * (uint64_t)n->T;
+    require(rt <= 0xFFFFFFFFull, CORTEX_EUNSUPPORTED, "tile size and delay range too large for 32-bit records");
+    n->meta_bytes = (rt <= 65536) ? 2 : 4;
     n->w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
     n->d_meta = dev_alloc(n, (size_t)n->E * n->meta_bytes + 16);
     n->d_w = dev_alloc(n, (size_t)n->E * n->w_bytes + 16);
@@ -629,7 +624,7 @@ void build_graph_fp32(cortex_net* n) {
     a.off_rel = n->d_off_rel;
     a.meta = n->d_meta;
     a.w = n->d_w;
-    a.tbits = n->tbits;
+    a.T = n->T;
     a.dmin = n->dmin;
     a.meta16 = n->meta_bytes == 2;
     a.wbf16 = n->w_bytes == 2;

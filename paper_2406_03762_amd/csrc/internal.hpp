@@ -97,7 +97,7 @@ struct cortex_net {
     std::vector<int32_t> tile_size, tile_inst;
     int dmin = 1, dmax = 1, R = 1, H = 64;
     int W = 1, chunk = 1024, ntb_max = 1;   // steps per spike exchange, staged spikes, tiles per instance
-    int tbits = 0, meta_bytes = 2, w_bytes = 4;
+    int meta_bytes = 2, w_bytes = 4;    // record: (delay - dmin) T + target in tile
     size_t lds_bytes = 0;
     int xcd_map = 0;
     int64_t step = 0;

@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
 constexpr int kInline = 1;        // spike ids fetched together with a tile's step record
+constexpr int kBlk = 512;         // 64-synapse blocks per piece of a delivery chunk (short segments)
 
 struct StepArgs {
     const int32_t* inst_tile0;
@@ -72,11 +73,10 @@ struct StepArgs {
     float* v_trace;
     uint8_t* m_trace;           // 1 where a neuron integrated and did not spike (adjoint)
     int64_t n0, n1, log_step0, log_steps, N;
-    int n_tiles, T, R, dmin, H, W, chunk, tbits, n_ref, n_thr, xcd, spin_log2, ntb_max;
+    int n_tiles, T, R, dmin, H, W, chunk, n_ref, n_thr, xcd, spin_log2, ntb_max;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
-    float fxw_scale;            // 2^(fx - fx_shift): synaptic weight to 32-bit fixed point
-    int fx_shift;               // left shift from the 32-bit weight scale to the ring's 2^fx
-    double fx_inv;              // 2^-fx
+    float fxw_scale;            // 2^fw: synaptic weight to its 32-bit fixed-point value
+    double fx_inv;              // 2^-fw: ring sum to input
     uint64_t seed;
     uint32_t thr[kMaxThr];
 };
@@ -97,13 +97,15 @@ __device__ __forceinline__ void coherent_store(uint64_t* p, uint64_t v) {
 __device__ __noinline__ uint64_t wait_tag(const uint64_t* p, uint64_t v, uint32_t tag, int64_t spin_max,
                                           int32_t* err, bool* bail) {
     int64_t spins = 0;
+    int32_t e = 0;
     while ((uint32_t)(v >> 32) != tag) {
-        if (++spins > spin_max ||
-            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (++spins > spin_max || e != 0) {
             *bail = true;
             return 0;
         }
         __builtin_amdgcn_s_sleep(1);
+        // the error flag is read with the word, so one round trip per try
+        e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         v = coherent_load(p);
     }
     return v;
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     const int tsz = a.tile_size[tile];
     const uint64_t offb = a.inst_offbase[b];
     const int T = a.T, R = a.R, H = a.H, CH = a.chunk;
-    const uint32_t tmask = (1u << a.tbits) - 1u;
+    const uint32_t RT = (uint32_t)R * (uint32_t)T;
     const size_t pub_tile = (size_t)T + 1;
     const size_t pub_slot = (size_t)a.n_tiles * pub_tile;
     const int pairs_max = a.W * a.ntb_max;
@@ -144,9 +146,11 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     uint32_t* s_wsum = s_pid + (size_t)pairs_max * kInline;         // 20
     int* s_misc = reinterpret_cast<int*>(s_wsum + 20);              // 4
     int* s_cnt = s_misc + 4;                                        // 8 (spike count per step of a window)
-    uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_cnt + 8);      // T (bit si: frozen spike at step si)
+    int* s_kw = s_cnt + 8;                                          // 20 (first segment of each wave's run)
+    uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_kw + 20);      // T (bit si: frozen spike at step si)
     uint32_t* s_thr = s_frz + T;                                    // kMaxThr Poisson thresholds
     unsigned char* s_kcb = reinterpret_cast<unsigned char*>(s_thr + kMaxThr);  // 2 x 8 x T Poisson counts
+    uint32_t* s_blk = reinterpret_cast<uint32_t*>(s_kcb + (size_t)16 * T);        // kBlk
 
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
@@ -211,11 +215,13 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     for (int sub = 0; sub < 8; ++sub) {
                         const uint64_t word = p.v[sub >> 1];
                         const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-                        // inversion: the count is the number of thresholds at
-                        // or below u (the table is increasing; unused entries
-                        // are 2^32 - 1 and end the scan)
+                        // inversion: the count is the number of the n_thr
+                        // (increasing) thresholds at or below u, found by a
+                        // binary search over the table
                         int kc = 0;
-                        while (kc < kMaxThr && s_thr[kc] != 0xFFFFFFFFu && u >= s_thr[kc]) ++kc;
+#pragma unroll
+                        for (int h = kMaxThr; h > 0; h >>= 1)
+                            if (kc + h <= a.n_thr && s_thr[kc + h - 1] <= u) kc += h;
                         dst[sub * T + li] = (unsigned char)kc;
                     }
                 }
@@ -250,20 +256,54 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 }
                 if (!marked) mark_frozen();
                 if (!prepared) prepare();
+                // every stale word of the thread's pairs is re-read in the
+                // same round (one round trip per try, the error flag with
+                // them) until all carry their step's tag
+                uint32_t tag[kP];
 #pragma unroll
-                for (int u = 0; u < kP; ++u) {
-                    const int p = p0 + tid + u * bs;
-                    if (p < pairs && !bail) {
-                        const uint32_t tag = (uint32_t)(q_lo + p / ntb + 1);
-                        const uint64_t r = wait_tag(base[u], rec[u], tag, spin_max, a.err, &bail);
-                        const uint32_t c = (uint32_t)r;
-                        s_pc[p] = c;
+                for (int u = 0; u < kP; ++u) tag[u] = (uint32_t)(q_lo + (p0 + tid + u * bs) / ntb + 1);
+                int64_t spins = 0;
+                int32_t e = 0;
+                while (!bail) {
+                    bool stale[kP], pending = false;
 #pragma unroll
-                        for (int k = 0; k < kInline; ++k) {
-                            if ((uint32_t)k < c) {
-                                const uint64_t v = wait_tag(base[u] + 1 + k, idw[u][k], tag, spin_max, a.err, &bail);
-                                s_pid[p * kInline + k] = (uint32_t)v;
-                            }
+                    for (int u = 0; u < kP; ++u) {
+                        stale[u] = false;
+                        if (base[u]) {
+                            bool st = (uint32_t)(rec[u] >> 32) != tag[u];
+#pragma unroll
+                            for (int k = 0; k < kInline; ++k)
+                                st |= (uint32_t)k < (uint32_t)rec[u] && (uint32_t)(idw[u][k] >> 32) != tag[u];
+                            stale[u] = st;
+                            pending |= st;
+                        }
+                    }
+                    if (!pending) break;
+                    if (++spins > spin_max || e != 0) {
+                        bail = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    e = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int u = 0; u < kP; ++u) {
+                        if (stale[u]) {
+                            rec[u] = coherent_load(base[u]);
+#pragma unroll
+                            for (int k = 0; k < kInline; ++k) idw[u][k] = coherent_load(base[u] + 1 + k);
+                        }
+                    }
+                }
+                if (!bail) {
+#pragma unroll
+                    for (int u = 0; u < kP; ++u) {
+                        const int p = p0 + tid + u * bs;
+                        if (base[u]) {
+                            const uint32_t c = (uint32_t)rec[u];
+                            s_pc[p] = c;
+#pragma unroll
+                            for (int k = 0; k < kInline; ++k)
+                                if ((uint32_t)k < c) s_pid[p * kInline + k] = (uint32_t)idw[u][k];
                         }
                     }
                 }
@@ -278,9 +318,19 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             const int base_slot = (int)((q_lo + a.dmin) % R);
             for (uint32_t c0 = 0; c0 < S; c0 += CH) {
                 const int cn = (int)min((uint32_t)CH, S - c0);
+                // spike kk of the window belongs to the (step, tile) pair p
+                // with s_pc[p] <= kk < s_pc[p + 1]: each pair writes its
+                // spikes' pair index (s_len is reused, each entry is read and
+                // then overwritten by the same thread below)
+                for (int p = tid; p < pairs; p += bs) {
+                    const uint32_t lo = max(s_pc[p], c0);
+                    const uint32_t hi = min(p + 1 < pairs ? s_pc[p + 1] : S, c0 + (uint32_t)cn);
+                    for (uint32_t kk = lo; kk < hi; ++kk) s_len[kk - c0] = (uint32_t)p;
+                }
+                __syncthreads();
                 for (int k = tid; k < cn; k += bs) {
                     const uint32_t kk = c0 + k;
-                    const int p = seg_of(s_pc, pairs, kk);
+                    const int p = (int)s_len[k];
                     const uint32_t rnk = kk - s_pc[p];
                     const int qi = p / ntb, tt = p - qi * ntb;
                     uint32_t j;
@@ -313,6 +363,17 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 __syncthreads();
                 if (s_misc[1]) break;
                 const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
+                const uint32_t share = (EL + n_waves - 1) / n_waves;
+                // s_kw[w] = first segment k with s_len[k] >= min(EL, w share):
+                // segment k owns the share boundaries in (s_len[k - 1], s_len[k]]
+                for (int k = tid; k <= cn; k += bs) {
+                    const int64_t lo = k == 0 ? -1 : (int64_t)s_len[k - 1];
+                    const uint32_t hi = k < cn ? s_len[k] : EL;
+                    for (int w = 0; w <= n_waves; ++w) {
+                        const uint32_t tw = min(EL, (uint32_t)w * share);
+                        if ((int64_t)tw > lo && tw <= hi) s_kw[w] = k;
+                    }
+                }
                 if (tid == 0) s_len[cn] = EL;
                 __syncthreads();
                 // Each wave takes a contiguous run of whole segments holding
@@ -322,57 +383,111 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 // l, l + 64, ... of each, so the loads of a segment are
                 // contiguous and the spike's step offset is the same for the
                 // whole wave.
-                const uint32_t share = (EL + n_waves - 1) / n_waves;
-                auto first_seg = [&](uint32_t fpos) {
-                    int lo = 0, hi = cn;          // first k with s_len[k] >= fpos
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_len[mid] < fpos) lo = mid + 1; else hi = mid;
-                    }
-                    return lo;
-                };
-                const int kw0 = first_seg(min(EL, (uint32_t)wave * share));
-                const int kw1 = first_seg(min(EL, (uint32_t)(wave + 1) * share));
-                for (int k0 = kw0; k0 < kw1; k0 += 8) {
-                    constexpr int U8 = 8;
-                    uint4 g[U8];
-                    uint32_t len_max = 0;
-#pragma unroll
-                    for (int u = 0; u < U8; ++u) {
-                        g[u] = (k0 + u < kw1) ? s_sg[k0 + u] : make_uint4(0u, 0u, 0u, 0u);
-                        len_max = max(len_max, g[u].x);
-                    }
-                    for (uint32_t o = lane; o < len_max + lane; o += 64u) {
-                        uint32_t m[U8];
-                        float wv[U8];
+                const int kw0 = s_kw[wave], kw1 = s_kw[wave + 1];
+                if (EL >= 32u * (uint32_t)cn) {
+                    // Long segments.  A segment's descriptor is the same for
+                    // the whole wave, so its first synapse, length and ring
+                    // row offset live in scalar registers and each lane only
+                    // adds its 32-bit position.  A record r = delta T + target
+                    // lands at (r + (base_slot + y) T) mod R T.
+                    const int kb = __builtin_amdgcn_readfirstlane(kw0);
+                    const int ke = __builtin_amdgcn_readfirstlane(kw1);
+                    for (int k0 = kb; k0 < ke; k0 += 8) {
+                        constexpr int U8 = 8;
+                        const unsigned char* mp[U8];
+                        const unsigned char* wp[U8];
+                        uint32_t len[U8], roff[U8];
+                        uint32_t len_max = 0;
 #pragma unroll
                         for (int u = 0; u < U8; ++u) {
-                            m[u] = 0;
-                            wv[u] = 0.f;
-                            if (o < g[u].x) {
-                                const uint64_t e = (((uint64_t)g[u].w << 32) | g[u].z) + o;
-                                m[u] = static_cast<const META*>(a.meta)[e];
-                                wv[u] = load_w(a.w, e, WBF16);
-                            }
+                            uint4 g = make_uint4(0u, 0u, 0u, 0u);
+                            if (k0 + u < ke) g = s_sg[k0 + u];
+                            len[u] = __builtin_amdgcn_readfirstlane(g.x);
+                            const uint32_t y = __builtin_amdgcn_readfirstlane(g.y);
+                            const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane(g.w) << 32) |
+                                                __builtin_amdgcn_readfirstlane(g.z);
+                            mp[u] = static_cast<const unsigned char*>(a.meta) + e0 * sizeof(META);
+                            wp[u] = static_cast<const unsigned char*>(a.w) + e0 * (WBF16 ? 2 : 4);
+                            roff[u] = (uint32_t)(base_slot + (int)y) * (uint32_t)T;
+                            len_max = max(len_max, len[u]);
                         }
+                        for (uint32_t o0 = 0; o0 < len_max; o0 += 64u) {
+                            const uint32_t o = o0 + (uint32_t)lane;
+                            uint32_t m[U8];
+                            float wv[U8];
 #pragma unroll
-                        for (int u = 0; u < U8; ++u) {
-                            if (o < g[u].x) {
-                                int sl = base_slot + (int)g[u].y + (int)(m[u] >> a.tbits);
-                                if (sl >= R) sl -= R;
-                                // w 2^fx in fixed point: round w 2^(fx - fx_shift) to a
-                                // 32-bit integer, then shift (exact)
-                                const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
-                                RING* dst = &ring[__umul24((unsigned)sl, (unsigned)T) + (m[u] & tmask)];
-                                if (sizeof(RING) == 8) {
-                                    const long long iv = (long long)iw << a.fx_shift;
-                                    atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)iv);
-                                } else {
-                                    // 32-bit rings: the scale keeps every sum below 2^31
-                                    atomicAdd(reinterpret_cast<unsigned int*>(dst), (unsigned int)iw);
+                            for (int u = 0; u < U8; ++u) {
+                                // m[u] and wv[u] are read below under the same condition
+                                if (o < len[u]) {
+                                    m[u] = *reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META));
+                                    wv[u] = WBF16 ? __uint_as_float((uint32_t)*reinterpret_cast<const uint16_t*>(wp[u] + o * 2u) << 16)
+                                                  : *reinterpret_cast<const float*>(wp[u] + o * 4u);
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < U8; ++u) {
+                                if (o < len[u]) {
+                                    uint32_t x = m[u] + roff[u];
+                                    x = min(x, x - RT);
+                                    // the weight rounded to a 32-bit fixed-point value
+                                    const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
+                                    if (sizeof(RING) == 8)
+                                        atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), (unsigned long long)(long long)iw);
+                                    else
+                                        atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
                                 }
                             }
                         }
+                    }
+                } else {
+                    // short segments: lanes take consecutive synapses of the
+                    // flattened space (stride 64); s_blk[b] is the segment
+                    // holding synapse 64 b, from which a lane walks forward
+                    for (uint32_t pc0 = 0; pc0 < EL; pc0 += 64u * kBlk) {
+                        const uint32_t pc1 = min(EL, pc0 + 64u * kBlk);
+                        for (int k = tid; k < cn; k += bs) {
+                            const uint32_t lo = max(s_len[k], pc0), hi = min(s_len[k + 1], pc1);
+                            for (uint32_t bb = (lo + 63u) >> 6; (bb << 6) < hi; ++bb)
+                                s_blk[bb - (pc0 >> 6)] = (uint32_t)k;
+                        }
+                        __syncthreads();
+                        const uint32_t per = ((pc1 - pc0 + n_waves - 1) / n_waves + 63) & ~63u;
+                        const uint32_t f_beg = pc0 + min(pc1 - pc0, (uint32_t)wave * per);
+                        const uint32_t f_end = min(pc1, f_beg + per);
+                        for (uint32_t f = f_beg + lane; f < f_end; f += 64u * 8u) {
+                            constexpr int U8 = 8;
+                            uint32_t m[U8], q[U8];
+                            float wv[U8];
+#pragma unroll
+                            for (int u = 0; u < U8; ++u) {
+                                const uint32_t fu = f + 64u * u;
+                                m[u] = 0;
+                                wv[u] = 0.f;
+                                q[u] = 0;
+                                if (fu < f_end) {
+                                    int seg = (int)s_blk[((fu - (uint32_t)lane) - pc0) >> 6];
+                                    while (s_len[seg + 1] <= fu) ++seg;
+                                    const uint4 g = s_sg[seg];
+                                    const uint64_t e = (((uint64_t)g.w << 32) | g.z) + (fu - s_len[seg]);
+                                    q[u] = g.y | 8u;
+                                    m[u] = static_cast<const META*>(a.meta)[e];
+                                    wv[u] = load_w(a.w, e, WBF16);
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < U8; ++u) {
+                                if (q[u] & 8u) {
+                                    uint32_t x = m[u] + (uint32_t)(base_slot + (int)(q[u] & 7u)) * (uint32_t)T;
+                                    x = min(x, x - RT);
+                                    const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
+                                    if (sizeof(RING) == 8)
+                                        atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), (unsigned long long)(long long)iw);
+                                    else
+                                        atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
+                                }
+                            }
+                        }
+                        __syncthreads();   // s_blk is refilled for the next piece
                     }
                 }
                 ev += EL;
@@ -529,10 +644,11 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_b
     const size_t pairs = (size_t)W * ntiles_max;
     b += (pairs + 1) * 4;                         // s_pc
     b += pairs * kInline * 4;                     // s_pid
-    b += 20 * 4 + 4 * 4 + 8 * 4;                  // s_wsum, s_misc, s_cnt
+    b += 20 * 4 + 4 * 4 + 8 * 4 + 20 * 4;         // s_wsum, s_misc, s_cnt, s_kw
     b += (size_t)T * 4;                           // s_frz
     b += (size_t)kMaxThr * 4;                     // s_thr
     b += (size_t)16 * T;                          // s_kcb
+    b += (size_t)kBlk * 4;                        // s_blk
     return (b + 15) & ~(size_t)15;
 }
 
@@ -602,7 +718,6 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.H = n->H;
     a.W = n->W;
     a.chunk = n->chunk;
-    a.tbits = n->tbits;
     a.n_ref = n->k.n_ref;
     a.n_thr = n->n_thr;
     a.xcd = n->xcd_map;
@@ -621,9 +736,9 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.Ur = (float)(n->spec.V_reset - n->spec.E_L);
     a.w_ext = (float)n->w_ext_native;
     a.E_L = (float)n->spec.E_L;
+    // weights are rounded at 2^(fx - fx_shift) and summed in those units
     a.fxw_scale = std::ldexp(1.0f, n->fx - n->fx_shift);
-    a.fx_shift = n->fx_shift;
-    a.fx_inv = std::ldexp(1.0, -n->fx);
+    a.fx_inv = std::ldexp(1.0, n->fx_shift - n->fx);
     a.seed = n->seed;
     for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
     KernelFn f = pick_kernel(n);
