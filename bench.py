@@ -106,6 +106,9 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
     out["instances_per_launch"] = [len(g.instances) for g, _ in groups]
     out["synapses"] = int(sum(net.E for _, net in groups))
     log(f"[bench] batched: {len(groups)} launches of {out['instances_per_launch']} instances")
+    for i, (_, net) in enumerate(groups):
+        log(f"[bench] batched launch {i}: tiles={net.query('TILES')} T={net.query('TILE_SIZE')} "
+            f"BS={net.query('BLOCK_SIZE')} W={net.query('STEPS_PER_SYNC')} ring={net.query('RING_BYTES')}B")
     for _, net in groups:
         net.step(200)
     torch.cuda.synchronize()

@@ -107,7 +107,8 @@ typedef struct {
     const cortex_pop* pops;   /* host, n_pops */
     int32_t n_projs;
     const cortex_proj* projs; /* host, n_projs */
-    int32_t tile_size;        /* targets per tile; 0 = automatic */
+    int32_t tile_size;        /* targets per tile; 0 = automatic; at most 2 x block_size
+                                 (4 x with block_size 512) */
     int32_t block_size;       /* threads per workgroup: 0 (auto), 256, 512, 1024 */
     int64_t record_steps;     /* steps of spike log kept (0 = none) */
     int32_t ckpt_every;       /* adjoint checkpoint interval in steps; 0 = no adjoint */

@@ -401,7 +401,6 @@ static void plan_tiles(cortex_net* n) {
         lds_for(T, ntb_max_of(Tb), 1, &chunk);
     } else {
         bool found = false;
-        auto bits_for = [](int64_t x) { int t = 0; while ((int64_t)1 << t < x) ++t; return t; };
         const int w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
         for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
             const int64_t cap = (int64_t)n_cu * per_cu;
@@ -430,8 +429,10 @@ static void plan_tiles(cortex_net* n) {
                         // workgroups of bs threads
                         int npt = (Tm + bs - 1) / bs;
                         if (npt == 3) npt = 4;
-                        const int meta = bits_for(Tm) + bits_for(n->R) <= 16 ? 2 : 4;
-                        if (npt <= 4 &&
+                        // the record width the graph build will choose
+                        const int meta = (uint64_t)Tm * (uint64_t)n->R <= 65536 ? 2 : 4;
+                        // four neurons per thread only in 512-thread workgroups
+                        if ((npt <= 2 || (npt == 4 && bs == 512)) &&
                             step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds, n->ring_bytes) >= per_cu) {
                             Tb = cand;
                             BS = bs;
@@ -459,8 +460,8 @@ static void plan_tiles(cortex_net* n) {
     const int T = *std::max_element(Tb.begin(), Tb.end());
     n->NPT = (T + BS - 1) / BS;
     if (n->NPT == 3) n->NPT = 4;
-    require(n->NPT <= 2 || (n->NPT == 4 && BS <= 512), CORTEX_EINVAL,
-            "tile_size must be at most 2 x block_size (4 x for block_size <= 512)");
+    require(n->NPT <= 2 || (n->NPT == 4 && BS == 512), CORTEX_EINVAL,
+            "tile_size must be at most 2 x block_size (4 x for block_size 512)");
     n->T = T;
     n->inst_T = Tb;
     n->BS = BS;

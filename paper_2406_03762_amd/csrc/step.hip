@@ -398,11 +398,16 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         const unsigned char* wp[U8];
                         uint32_t len[U8], roff[U8];
                         uint32_t len_max = 0;
+                        // all eight descriptors are read before any is used
+                        // (past the run's end the last one is re-read and
+                        // given length 0)
+                        uint4 gd[U8];
+#pragma unroll
+                        for (int u = 0; u < U8; ++u) gd[u] = s_sg[min(k0 + u, ke - 1)];
 #pragma unroll
                         for (int u = 0; u < U8; ++u) {
-                            uint4 g = make_uint4(0u, 0u, 0u, 0u);
-                            if (k0 + u < ke) g = s_sg[k0 + u];
-                            len[u] = __builtin_amdgcn_readfirstlane(g.x);
+                            const uint4 g = gd[u];
+                            len[u] = k0 + u < ke ? __builtin_amdgcn_readfirstlane(g.x) : 0u;
                             const uint32_t y = __builtin_amdgcn_readfirstlane(g.y);
                             const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane(g.w) << 32) |
                                                 __builtin_amdgcn_readfirstlane(g.z);
