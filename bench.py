@@ -24,8 +24,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per synaptic event of the step kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (calibrated against a 1 GiB copy; profiles/step_kernel_brunel112k_alpha.md),
 # valid only for the kernel source it was measured on.
-TRAFFIC_BYTES_PER_EVENT = (3.1188e7 * 2.0 + 1.3128e5 * 1.0) * 1024 / 9.072019401e9
-TRAFFIC_SOURCE_HASH = "0b399482200ae1cb"
+TRAFFIC_BYTES_PER_EVENT = (3.0703e7 * 2.0 + 1.8482e6 * 1.0) * 1024 / 9.072019401e9
+TRAFFIC_SOURCE_HASH = "4b542c1b14690f92"
 SIM_STEPS_PER_BENCH_STEP = 10000      # 1 s of biological time at dt = 0.1 ms
 
 
