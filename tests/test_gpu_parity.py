@@ -166,14 +166,17 @@ def _fp32_open_loop(cx, orc, spec, T, p, seed, tile_size, sel=None):
     return g, xg, vg, xo, vo, B, steps, ids
 
 
-@pytest.mark.parametrize("model,d0,d1", [("delta", 5, 30), ("exp", 1, 12), ("alpha", 5, 30),
-                                         ("alpha", 1, 1)])
-def test_fp32_open_loop_delivery_matches_oracle(cx, orc, model, d0, d1):
+# tile 256: segments of ~26 synapses (lanes over the flattened synapses);
+# tiles 1024 and 2048 (two neurons per thread): ~102 and ~205 (waves over
+# whole segments)
+@pytest.mark.parametrize("model,d0,d1,tile", [("delta", 5, 30, 256), ("exp", 1, 12, 256), ("alpha", 5, 30, 256),
+                                              ("alpha", 1, 1, 256), ("alpha", 5, 5, 1024), ("exp", 1, 12, 2048)])
+def test_fp32_open_loop_delivery_matches_oracle(cx, orc, model, d0, d1, tile):
     spec = netspec.small_brunel(model=model, n_e=2400, n_i=600, c_e=240, c_i=60, delay="uniform_int",
                                 d0=d0, d1=d1, w_rel_sd=0.1, weight_unit="psp_mV")
-    case(f"fp32 open loop {model} delays {d0}..{d1}")
-    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 200, 0.01, 13, 256)
-    assert g.query("TILES") == 12
+    case(f"fp32 open loop {model} delays {d0}..{d1} tile {tile}")
+    g, xg, vg, xo, vo, B, _, _ = _fp32_open_loop(cx, orc, spec, 200, 0.01, 13, tile)
+    assert g.query("TILES") == -(-3000 // tile)
     assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
     assert np.abs(xo).max() > 0
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
@@ -193,14 +196,16 @@ def test_fp32_open_loop_with_32bit_rings(cx, orc):
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
 
 
-@pytest.mark.parametrize("steps_per_sync", [0, 1, 2])
-def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc, steps_per_sync):
+# tile 192: segments of ~19 synapses (lanes over the flattened synapses);
+# tile 1024: ~102 (waves over whole segments)
+@pytest.mark.parametrize("steps_per_sync,tile", [(0, 192), (1, 192), (2, 192), (0, 1024), (3, 1024)])
+def test_fp32_integer_weights_give_exact_sums_across_calls(cx, orc, steps_per_sync, tile):
     spec = netspec.small_brunel(n_e=1600, n_i=400, c_e=160, c_i=40, delay="uniform_int", d0=3, d1=17,
                                 w_rel_sd=0.0, J=1.0, g=2.0)
     T = 160
     steps, ids = netspec.synthetic_raster(2000, T, 0.02, seed=21)
-    case(f"fp32 integer weights, split calls, steps_per_sync={steps_per_sync}")
-    g = cx.Network(spec, 17, tile_size=192, steps_per_sync=steps_per_sync)
+    case(f"fp32 integer weights, split calls, steps_per_sync={steps_per_sync}, tile {tile}")
+    g = cx.Network(spec, 17, tile_size=tile, steps_per_sync=steps_per_sync)
     o = orc.OracleNet(spec, 17)
     xo, _ = o.run_frozen(steps, ids, T)
     parts = [g.run_frozen(steps, ids, k)[0].cpu().numpy() for k in (1, 63, 16, 80)]
