@@ -364,15 +364,15 @@ class Network:
         return cortex_export_tiles(self._h, self.query("TILES"))
 
 
-def autotune(net, seed: int, steps: int = 500, warmup: int = 100, tile_sizes=(0,), **plan):
-    """Pick the launch plan of an FP32 network by measurement: build it with
+def autotune(spec, seed: int, steps: int = 500, warmup: int = 100, tile_sizes=(0,), **plan):
+    """Pick the launch plan of an FP32 network spec by measurement: build it with
     every steps-per-exchange window from its minimum delay down to 1 (and the
     given tile sizes, 0 = the planner's balanced tiles), time ``steps``
     closed-loop steps after ``warmup`` and return (best plan dict, timings).
     Candidates that cannot be planned on this device are skipped."""
     import time
     import torch
-    probe = Network(net, seed, **plan)
+    probe = Network(spec, seed, **plan)
     w_max = probe.query("STEPS_PER_SYNC")
     d_min = probe.query("MIN_DELAY")
     probe.close()
@@ -381,7 +381,7 @@ def autotune(net, seed: int, steps: int = 500, warmup: int = 100, tile_sizes=(0,
         for W in range(min(8, d_min), 0, -1):
             cand = dict(plan, tile_size=T, steps_per_sync=W)
             try:
-                g = Network(net, seed, **cand)
+                g = Network(spec, seed, **cand)
             except CortexError as e:
                 if e.status in (EUNSUPPORTED, EINVAL):
                     continue

@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(256) loss_sum_kernel(const double* part, int n
 
 struct WgradArgs {
     const int32_t* tile_inst;
+    const int32_t* tile_size;
     const int32_t* inst_tile0;
     const int32_t* inst_ntiles;
     const int32_t* inst_T;
@@ -152,41 +153,59 @@ struct WgradArgs {
     const void* meta;
     int meta16;
     int T, dmin;                // record = (delay - dmin) T + target in tile
-    const uint64_t* src_ptr;    // [n_inst + 1] into src_id
-    const uint32_t* src_id;     // spiking sources, grouped by instance
-    const uint64_t* spk_ptr;    // [n_src + 1] into spk_step
+    int sw, n_sub;              // steps per sub-window, sub-windows of the segment
+    int n_inst;
+    const uint64_t* src_ptr;    // [n_sub][n_inst + 1] into src_id
+    const uint32_t* src_id;     // per sub-window, spiking sources grouped by instance
+    const uint64_t* spk_ptr;    // [sources + 1] into spk_step
     const int64_t* spk_step;
     const float* gtr;           // [len][N]
     float* grad;                // [E] storage order
     int64_t N, s0, s1;
 };
 
-// One workgroup per tile, one wave per spiking source, lanes over the
-// source's segment into the tile.
+// One workgroup per tile.  The segment's steps are taken in sub-windows of
+// sw steps; for each, the tile's dL/dx values of those steps are staged in
+// LDS ([sw][tile size]), then one wave per source whose spikes can arrive in
+// the sub-window walks the source's segment into the tile (lanes over its
+// synapses) and adds, per synapse, the staged values at the arrival steps.
 __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
+    extern __shared__ float s_g[];
     const int tile = blockIdx.x;
     const int b = a.tile_inst[tile];
     const int tl = tile - a.inst_tile0[b];
     const int ntb = a.inst_ntiles[b];
+    const int tsz = a.tile_size[tile];
     const int64_t n0b = a.inst_n0[b];
     const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    for (uint64_t s = a.src_ptr[b] + wave; s < a.src_ptr[b + 1]; s += n_waves) {
-        const uint32_t j = a.src_id[s];
-        const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-        const uint64_t e0 = a.row_start[j] + a.off_rel[ob], e1 = a.row_start[j] + a.off_rel[ob + 1];
-        const uint64_t p0 = a.spk_ptr[s], p1 = a.spk_ptr[s + 1];
-        for (uint64_t e = e0 + lane; e < e1; e += 64) {
-            const uint32_t m = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                        : static_cast<const uint32_t*>(a.meta)[e];
-            const int64_t d = a.dmin + (int64_t)(m / (uint32_t)a.T);
-            const int64_t tgt = g0 + (m % (uint32_t)a.T);
-            float acc = 0.f;
-            for (uint64_t p = p0; p < p1; ++p) {
-                const int64_t tau = a.spk_step[p] + d;
-                if (tau >= a.s0 && tau < a.s1) acc += a.gtr[(tau - a.s0) * a.N + tgt];
+    for (int w = 0; w < a.n_sub; ++w) {
+        const int64_t t = a.s0 + (int64_t)w * a.sw;
+        const int nw = (int)min((int64_t)a.sw, a.s1 - t);
+        __syncthreads();   // the previous sub-window's readers are done
+        for (int i = threadIdx.x; i < nw * tsz; i += blockDim.x) {
+            const int k = i / tsz, li = i - k * tsz;
+            s_g[i] = a.gtr[(t - a.s0 + k) * a.N + g0 + li];
+        }
+        __syncthreads();
+        const uint64_t* sp = a.src_ptr + (size_t)w * (a.n_inst + 1);
+        for (uint64_t s = sp[b] + wave; s < sp[b + 1]; s += n_waves) {
+            const uint32_t j = a.src_id[s];
+            const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+            const uint64_t e0 = a.row_start[j] + a.off_rel[ob], e1 = a.row_start[j] + a.off_rel[ob + 1];
+            const uint64_t p0 = a.spk_ptr[s], p1 = a.spk_ptr[s + 1];
+            for (uint64_t e = e0 + lane; e < e1; e += 64) {
+                const uint32_t m = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                            : static_cast<const uint32_t*>(a.meta)[e];
+                const int64_t d = a.dmin + (int64_t)(m / (uint32_t)a.T);
+                const int li = (int)(m % (uint32_t)a.T);
+                float acc = 0.f;
+                for (uint64_t p = p0; p < p1; ++p) {
+                    const int64_t tau = a.spk_step[p] + d;
+                    if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+                }
+                if (acc != 0.f) a.grad[e] += acc;
             }
-            if (acc != 0.f) a.grad[e] += acc;
         }
     }
 }
@@ -273,6 +292,11 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     double* dloss_part = dev_alloc_t<double>(n, rev_grid, true);
     float* grad = dev_alloc_t<float>(n, n->E, true);
     int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
+    // weight-gradient sub-windows: sw steps of a tile's dL/dx in 128 KB of LDS
+    const int sw = (int)std::max<int64_t>(1, std::min<int64_t>(C, 32768 / std::max(1, n->T)));
+    const size_t wgrad_lds = (size_t)sw * n->T * sizeof(float);
+    CX_HIP(hipFuncSetAttribute((const void*)wgrad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)wgrad_lds));
     CX_HIP(hipMemcpyAsync(inst_N, n->inst_N.data(), n->n_inst * 8, hipMemcpyHostToDevice, n->stream));
     dev_zero(n, aU, N * 8);
     dev_zero(n, a1, N * 8);
@@ -354,33 +378,44 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             CX_HIP(hipGetLastError());
             hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, n->stream, dloss_part, rev_grid, dloss);
             CX_HIP(hipGetLastError());
-            // sources whose arrivals may land in [s0, s1), grouped by instance
+            // per sub-window of sw steps, the sources whose arrivals may land
+            // in it (a spike at q arrives in [q + d_min, q + d_max]), grouped
+            // by instance, each with its spike steps
+            const int n_sub = (int)((len + sw - 1) / sw);
             const auto spk = slice(s0 - n->dmax, s1 - n->dmin);
-            std::vector<std::vector<std::pair<uint32_t, int64_t>>> per_inst(n->n_inst);
+            std::vector<std::vector<std::pair<uint32_t, int64_t>>> bucket((size_t)n_sub * n->n_inst);
             for (const auto& sp : spk) {
                 int lo = 0, hi = n->n_inst;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) / 2;
                     if (n->inst_n0[mid] <= (int64_t)sp.second) lo = mid; else hi = mid;
                 }
-                per_inst[lo].emplace_back(sp.second, (int64_t)sp.first);
+                const int64_t q = (int64_t)sp.first;
+                const int64_t a0 = q + n->dmin - s0, a1 = q + n->dmax - s0;   // arrivals, relative to s0
+                if (a1 < 0 || a0 >= len) continue;
+                const int w0 = (int)(std::max<int64_t>(0, a0) / sw);
+                const int w1 = (int)(std::min<int64_t>(len - 1, a1) / sw);
+                for (int w = w0; w <= w1; ++w) bucket[(size_t)w * n->n_inst + lo].emplace_back(sp.second, q);
             }
-            // CSR: instance -> distinct sources -> their spike steps
-            src_ptr.assign(n->n_inst + 1, 0);
+            // CSR: sub-window -> instance -> distinct sources -> their spike steps
+            src_ptr.assign((size_t)n_sub * (n->n_inst + 1), 0);
             spk_ptr.clear();
             src_id.clear();
             spk_step.clear();
-            for (int b = 0; b < n->n_inst; ++b) {
-                auto& v = per_inst[b];
-                std::sort(v.begin(), v.end());
-                for (size_t q = 0; q < v.size(); ++q) {
-                    if (q == 0 || v[q].first != v[q - 1].first) {
-                        src_id.push_back(v[q].first);
-                        spk_ptr.push_back(spk_step.size());
+            for (int w = 0; w < n_sub; ++w) {
+                src_ptr[(size_t)w * (n->n_inst + 1)] = src_id.size();
+                for (int b = 0; b < n->n_inst; ++b) {
+                    auto& v = bucket[(size_t)w * n->n_inst + b];
+                    std::sort(v.begin(), v.end());
+                    for (size_t q = 0; q < v.size(); ++q) {
+                        if (q == 0 || v[q].first != v[q - 1].first) {
+                            src_id.push_back(v[q].first);
+                            spk_ptr.push_back(spk_step.size());
+                        }
+                        spk_step.push_back(v[q].second);
                     }
-                    spk_step.push_back(v[q].second);
+                    src_ptr[(size_t)w * (n->n_inst + 1) + b + 1] = src_id.size();
                 }
-                src_ptr[b + 1] = src_id.size();
             }
             spk_ptr.push_back(spk_step.size());
             if (!src_id.empty()) {
@@ -393,13 +428,15 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 CX_HIP(hipMemcpyAsync(d_pp, spk_ptr.data(), spk_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
                 CX_HIP(hipMemcpyAsync(d_ss, spk_step.data(), spk_step.size() * 8, hipMemcpyHostToDevice, n->stream));
                 WgradArgs wa{};
-                wa.tile_inst = n->d_tile_inst; wa.inst_tile0 = n->d_inst_tile0; wa.inst_ntiles = n->d_inst_ntiles;
-                wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0; wa.inst_offbase = n->d_inst_offbase;
+                wa.tile_inst = n->d_tile_inst; wa.tile_size = n->d_tile_size; wa.inst_tile0 = n->d_inst_tile0;
+                wa.inst_ntiles = n->d_inst_ntiles; wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0;
+                wa.inst_offbase = n->d_inst_offbase;
                 wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
                 wa.meta16 = n->meta_bytes == 2; wa.T = n->T; wa.dmin = n->dmin;
+                wa.sw = sw; wa.n_sub = n_sub; wa.n_inst = n->n_inst;
                 wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
                 wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
-                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(256), 0, n->stream, wa);
+                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(256), wgrad_lds, n->stream, wa);
                 CX_HIP(hipGetLastError());
             }
             CX_HIP(hipStreamSynchronize(n->stream));
