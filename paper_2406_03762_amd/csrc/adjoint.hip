@@ -164,12 +164,13 @@ struct WgradArgs {
     int64_t N, s0, s1;
 };
 
-// One workgroup per tile.  The segment's steps are taken in sub-windows of
-// sw steps; for each, the tile's dL/dx values of those steps are staged in
-// LDS ([sw][tile size]), then one wave per source whose spikes can arrive in
-// the sub-window walks the source's segment into the tile (lanes over its
-// synapses) and adds, per synapse, the staged values at the arrival steps.
-__global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
+// One workgroup (16 waves) per tile.  The segment's steps are taken in
+// sub-windows of sw steps; for each, the tile's dL/dx values of those steps
+// are staged in LDS ([sw][tile size]), then one wave per source whose spikes
+// can arrive in the sub-window walks the source's segment into the tile
+// (lanes over its synapses) and adds, per synapse, the staged values at the
+// arrival steps.
+__global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
     extern __shared__ float s_g[];
     const int tile = blockIdx.x;
     const int b = a.tile_inst[tile];
@@ -436,7 +437,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 wa.sw = sw; wa.n_sub = n_sub; wa.n_inst = n->n_inst;
                 wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
                 wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
-                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(256), wgrad_lds, n->stream, wa);
+                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(1024), wgrad_lds, n->stream, wa);
                 CX_HIP(hipGetLastError());
             }
             CX_HIP(hipStreamSynchronize(n->stream));
