@@ -725,18 +725,31 @@ std::vector<std::pair<uint32_t, uint32_t>> collect_spikes(cortex_net* n, int64_t
     auto cnt = download(n, n->d_log_cnt, (size_t)(s1 - w0) * n->n_tiles);
     auto pos = download(n, n->d_log_pos, n->n_tiles);
     auto base = download(n, n->d_log_base, n->n_tiles + 1);
-    for (int t = 0; t < n->n_tiles; ++t) {
-        auto tid = download(n, n->d_log_ids + base[t], (size_t)pos[t]);
-        uint64_t p = 0;
-        for (int64_t s = w0; s < s1; ++s) {
+    std::vector<std::vector<uint32_t>> tid(n->n_tiles);
+    for (int t = 0; t < n->n_tiles; ++t) tid[t] = download(n, n->d_log_ids + base[t], (size_t)pos[t]);
+    // Each tile's log lists its spikes step by step; tiles hold increasing
+    // id ranges, so walking the steps and, within a step, the tiles in
+    // order, with each (step, tile) group sorted, yields (step, id) order.
+    // A tile's log ends at its first overflow mark.
+    std::vector<uint64_t> p(n->n_tiles, 0);
+    std::vector<char> ended(n->n_tiles, 0);
+    for (int64_t s = w0; s < s1; ++s) {
+        for (int t = 0; t < n->n_tiles; ++t) {
+            if (ended[t]) continue;
             const uint32_t c = cnt[(size_t)(s - w0) * n->n_tiles + t];
-            if (c == 0xFFFFFFFFu) { *trunc = true; break; }
-            if (s >= s0)
-                for (uint32_t k = 0; k < c; ++k) out.emplace_back((uint32_t)s, tid[p + k]);
-            p += c;
+            if (c == 0xFFFFFFFFu || p[t] + c > tid[t].size()) {
+                *trunc = true;
+                ended[t] = 1;
+                continue;
+            }
+            if (s >= s0) {
+                const size_t o = out.size();
+                for (uint32_t k = 0; k < c; ++k) out.emplace_back((uint32_t)s, tid[t][p[t] + k]);
+                std::sort(out.begin() + o, out.end());
+            }
+            p[t] += c;
         }
     }
-    std::sort(out.begin(), out.end());
     return out;
 }
 
