@@ -214,7 +214,7 @@ def main():
                     help="time steps per spike exchange (0 = the planner's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=6000)
-    ap.add_argument("--cpu-steps", type=int, default=8000)
+    ap.add_argument("--cpu-steps", type=int, default=12000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
