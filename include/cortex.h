@@ -47,7 +47,7 @@ typedef enum {
     CORTEX_ENOMEM = -2,       /* allocation failed */
     CORTEX_EDEVICE = -3,      /* HIP runtime error */
     CORTEX_ESTATE = -4,       /* call not valid in the network's state */
-    CORTEX_EUNSUPPORTED = -5, /* valid request this build cannot serve */
+    CORTEX_EUNSUPPORTED = -5, /* valid request the library cannot serve */
     CORTEX_ETIMEOUT = -6,     /* a device-side wait exceeded its spin limit */
     CORTEX_ETRUNC = -7        /* output truncated (buffer or log capacity) */
 } cortex_status;
