@@ -358,14 +358,11 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                     CX_HIP(hipMemcpyAsync(d_ids, fr_ids.data(), fr_ids.size() * 4, hipMemcpyHostToDevice,
                                           n->stream));
                 CX_HIP(hipMemcpyAsync(d_ptr, fr_ptr.data(), fr_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
+                // no wait here: the host builds the segment's gradient lists
+                // while the replay runs; its error flag is read at the end of
+                // the segment (the kernels in between index only by lists and
+                // records, so a failed replay leaves them in bounds)
                 launch_step_fp32(n, len, d_ids, d_ptr, fr_ids.size(), nullptr, vtr, mtr);
-                CX_HIP(hipStreamSynchronize(n->stream));
-                int32_t e = 0;
-                CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
-                if (e != 0) {
-                    n->failed = true;
-                    throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
-                }
             }
             // reverse recursion over the segment
             ReverseArgs ra{};
@@ -441,6 +438,14 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 CX_HIP(hipGetLastError());
             }
             CX_HIP(hipStreamSynchronize(n->stream));
+            {
+                int32_t e = 0;
+                CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
+                if (e != 0) {
+                    n->failed = true;
+                    throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
+                }
+            }
             // per-segment scratch (lists) is released; large buffers stay
         }
         hipLaunchKernelGGL(scatter_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad, n->d_canon,
