@@ -211,10 +211,11 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
     }
 }
 
-__global__ void scatter_kernel(const float* src, const uint32_t* canon, float* dst, int64_t E) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-         e += (int64_t)gridDim.x * blockDim.x)
-        dst[canon[e]] = src[e];
+// dst in canonical order from src in storage order: dst[c] = src[inv[c]].
+__global__ void gather_kernel(const float* src, const uint32_t* inv, float* dst, int64_t E) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < E;
+         c += (int64_t)gridDim.x * blockDim.x)
+        dst[c] = src[inv[c]];
 }
 
 int grid_of(int64_t work, int bs) {
@@ -448,8 +449,8 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             }
             // per-segment scratch (lists) is released; large buffers stay
         }
-        hipLaunchKernelGGL(scatter_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad, n->d_canon,
-                           grad_w, n->E);
+        hipLaunchKernelGGL(gather_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad,
+                           n->d_canon_inv, grad_w, n->E);
         CX_HIP(hipGetLastError());
         CX_HIP(hipMemcpyAsync(loss_out, dloss, 8, hipMemcpyDeviceToHost, n->stream));
     } catch (...) {

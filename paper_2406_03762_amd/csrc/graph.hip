@@ -547,6 +547,12 @@ double max_abs_input(cortex_net* n, double* wmax) {
 }
 
 namespace {
+// inv[canon[e]] = e (setup).
+__global__ void invert_kernel(const uint32_t* canon, uint32_t* inv, int64_t E) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
+        inv[canon[e]] = (uint32_t)e;
+}
+
 // Stored weight of every synapse from a canonical-order array (setup).
 __global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, void* w, int wbf16, int64_t E) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
@@ -633,6 +639,15 @@ void build_graph_fp32(cortex_net* n) {
     a.cin = cin;
     a.canon_out = n->d_canon;
     run_gen<kFillTiles>(n, a);
+    if (need_canon && n->E > 0) {
+        // the inverse permutation, so that canonical-order outputs are
+        // written in order (gathered) rather than scattered
+        n->d_canon_inv = dev_alloc_t<uint32_t>(n, n->E);
+        dev_zero(n, n->d_canon_inv, (size_t)n->E * sizeof(uint32_t));   // in range even if not a permutation
+        hipLaunchKernelGGL(invert_kernel, dim3(grid_for(n->E, 256)), dim3(256), 0, n->stream, n->d_canon,
+                           n->d_canon_inv, n->E);
+        CX_HIP(hipGetLastError());
+    }
     CX_HIP(hipStreamSynchronize(n->stream));
 }
 

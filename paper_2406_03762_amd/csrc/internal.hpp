@@ -125,6 +125,7 @@ struct cortex_net {
     void* d_meta = nullptr;            // u16/u32 [E]
     void* d_w = nullptr;               // f32/bf16 [E]
     uint32_t* d_canon = nullptr;       // [E] canonical index of each stored synapse (adjoint)
+    uint32_t* d_canon_inv = nullptr;   // [E] stored index of each canonical synapse (adjoint)
     // FP32 state
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
