@@ -320,16 +320,69 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
         return v;
     };
     const int K = (int)((T + C - 1) / C);
-    // Host staging of every asynchronous upload of a segment.  The copies
-    // read these vectors when the stream reaches them, so they live at
-    // function scope and are refilled only after the stream has drained
-    // (end of each segment, or the error path below).
-    std::vector<uint32_t> rp_ids, fr_ids, src_id;
-    std::vector<uint64_t> rp_ptr, fr_ptr, src_ptr, spk_ptr;
-    std::vector<int64_t> spk_step;
+    // Host lists of a segment: the pending spikes to republish, the frozen
+    // raster of the replay and, per sub-window of sw steps, the sources
+    // whose arrivals may land in it (a spike at q arrives in [q + d_min,
+    // q + d_max]), grouped by instance, each with its spike steps.  They
+    // depend only on the raster, so the lists of segment k - 1 are built
+    // while the device works on segment k.  Two sets alternate; a set is
+    // refilled only after the stream has drained the uploads that read it.
+    struct SegLists {
+        std::vector<uint32_t> rp_ids, fr_ids, src_id;
+        std::vector<uint64_t> rp_ptr, fr_ptr, src_ptr, spk_ptr;
+        std::vector<int64_t> spk_step;
+    };
+    SegLists lists[2];
+    auto build_lists = [&](int k, SegLists& L) {
+        const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
+        const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
+        L.rp_ids.clear();
+        L.rp_ptr.clear();
+        if (s0 > r0) frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, L.rp_ids, L.rp_ptr);
+        frozen_lists_at(n, s0, slice(s0, s1), len, L.fr_ids, L.fr_ptr);
+        const int n_sub = (int)((len + sw - 1) / sw);
+        const auto spk = slice(s0 - n->dmax, s1 - n->dmin);
+        std::vector<std::vector<std::pair<uint32_t, int64_t>>> bucket((size_t)n_sub * n->n_inst);
+        for (const auto& sp : spk) {
+            int lo = 0, hi = n->n_inst;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (n->inst_n0[mid] <= (int64_t)sp.second) lo = mid; else hi = mid;
+            }
+            const int64_t q = (int64_t)sp.first;
+            const int64_t a0 = q + n->dmin - s0, a1 = q + n->dmax - s0;   // arrivals, relative to s0
+            if (a1 < 0 || a0 >= len) continue;
+            const int w0 = (int)(std::max<int64_t>(0, a0) / sw);
+            const int w1 = (int)(std::min<int64_t>(len - 1, a1) / sw);
+            for (int w = w0; w <= w1; ++w) bucket[(size_t)w * n->n_inst + lo].emplace_back(sp.second, q);
+        }
+        // CSR: sub-window -> instance -> distinct sources -> their spike steps
+        L.src_ptr.assign((size_t)n_sub * (n->n_inst + 1), 0);
+        L.spk_ptr.clear();
+        L.src_id.clear();
+        L.spk_step.clear();
+        for (int w = 0; w < n_sub; ++w) {
+            L.src_ptr[(size_t)w * (n->n_inst + 1)] = L.src_id.size();
+            for (int b = 0; b < n->n_inst; ++b) {
+                auto& v = bucket[(size_t)w * n->n_inst + b];
+                std::sort(v.begin(), v.end());
+                for (size_t q = 0; q < v.size(); ++q) {
+                    if (q == 0 || v[q].first != v[q - 1].first) {
+                        L.src_id.push_back(v[q].first);
+                        L.spk_ptr.push_back(L.spk_step.size());
+                    }
+                    L.spk_step.push_back(v[q].second);
+                }
+                L.src_ptr[(size_t)w * (n->n_inst + 1) + b + 1] = L.src_id.size();
+            }
+        }
+        L.spk_ptr.push_back(L.spk_step.size());
+    };
     try {
+        if (K > 0) build_lists(K - 1, lists[(K - 1) & 1]);
         for (int k = K - 1; k >= 0; --k) {
             const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
+            SegLists& L = lists[k & 1];
             restore_checkpoint(n, k);
             n->step = s0;
             // Records left in the publication buffer by the forward run or a
@@ -341,29 +394,28 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             // spikes of [s0 - d_min, s0) are published but not yet delivered at s0
             const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
             if (s0 > r0) {
-                frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, rp_ids, rp_ptr);
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, rp_ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, rp_ptr.size(), true);
-                if (!rp_ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, rp_ids.data(), rp_ids.size() * 4, hipMemcpyHostToDevice,
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, L.rp_ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, L.rp_ptr.size(), true);
+                if (!L.rp_ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, L.rp_ids.data(), L.rp_ids.size() * 4, hipMemcpyHostToDevice,
                                           n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, rp_ptr.data(), rp_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                republish(n, r0, s0, d_ids, d_ptr, rp_ids.size());
+                CX_HIP(hipMemcpyAsync(d_ptr, L.rp_ptr.data(), L.rp_ptr.size() * 8, hipMemcpyHostToDevice,
+                                      n->stream));
+                republish(n, r0, s0, d_ids, d_ptr, L.rp_ids.size());
             }
-            // bit-exact replay of the segment on the frozen raster
+            // bit-exact replay of the segment on the frozen raster; its error
+            // flag is read at the end of the segment (the kernels in between
+            // index only by lists and records, so a failed replay leaves them
+            // in bounds)
             {
-                frozen_lists_at(n, s0, slice(s0, s1), len, fr_ids, fr_ptr);
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, fr_ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, fr_ptr.size(), true);
-                if (!fr_ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, fr_ids.data(), fr_ids.size() * 4, hipMemcpyHostToDevice,
+                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, L.fr_ids.size()), true);
+                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, L.fr_ptr.size(), true);
+                if (!L.fr_ids.empty())
+                    CX_HIP(hipMemcpyAsync(d_ids, L.fr_ids.data(), L.fr_ids.size() * 4, hipMemcpyHostToDevice,
                                           n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, fr_ptr.data(), fr_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                // no wait here: the host builds the segment's gradient lists
-                // while the replay runs; its error flag is read at the end of
-                // the segment (the kernels in between index only by lists and
-                // records, so a failed replay leaves them in bounds)
-                launch_step_fp32(n, len, d_ids, d_ptr, fr_ids.size(), nullptr, vtr, mtr);
+                CX_HIP(hipMemcpyAsync(d_ptr, L.fr_ptr.data(), L.fr_ptr.size() * 8, hipMemcpyHostToDevice,
+                                      n->stream));
+                launch_step_fp32(n, len, d_ids, d_ptr, L.fr_ids.size(), nullptr, vtr, mtr);
             }
             // reverse recursion over the segment
             ReverseArgs ra{};
@@ -377,55 +429,21 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             CX_HIP(hipGetLastError());
             hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, n->stream, dloss_part, rev_grid, dloss);
             CX_HIP(hipGetLastError());
-            // per sub-window of sw steps, the sources whose arrivals may land
-            // in it (a spike at q arrives in [q + d_min, q + d_max]), grouped
-            // by instance, each with its spike steps
-            const int n_sub = (int)((len + sw - 1) / sw);
-            const auto spk = slice(s0 - n->dmax, s1 - n->dmin);
-            std::vector<std::vector<std::pair<uint32_t, int64_t>>> bucket((size_t)n_sub * n->n_inst);
-            for (const auto& sp : spk) {
-                int lo = 0, hi = n->n_inst;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) / 2;
-                    if (n->inst_n0[mid] <= (int64_t)sp.second) lo = mid; else hi = mid;
-                }
-                const int64_t q = (int64_t)sp.first;
-                const int64_t a0 = q + n->dmin - s0, a1 = q + n->dmax - s0;   // arrivals, relative to s0
-                if (a1 < 0 || a0 >= len) continue;
-                const int w0 = (int)(std::max<int64_t>(0, a0) / sw);
-                const int w1 = (int)(std::min<int64_t>(len - 1, a1) / sw);
-                for (int w = w0; w <= w1; ++w) bucket[(size_t)w * n->n_inst + lo].emplace_back(sp.second, q);
-            }
-            // CSR: sub-window -> instance -> distinct sources -> their spike steps
-            src_ptr.assign((size_t)n_sub * (n->n_inst + 1), 0);
-            spk_ptr.clear();
-            src_id.clear();
-            spk_step.clear();
-            for (int w = 0; w < n_sub; ++w) {
-                src_ptr[(size_t)w * (n->n_inst + 1)] = src_id.size();
-                for (int b = 0; b < n->n_inst; ++b) {
-                    auto& v = bucket[(size_t)w * n->n_inst + b];
-                    std::sort(v.begin(), v.end());
-                    for (size_t q = 0; q < v.size(); ++q) {
-                        if (q == 0 || v[q].first != v[q - 1].first) {
-                            src_id.push_back(v[q].first);
-                            spk_ptr.push_back(spk_step.size());
-                        }
-                        spk_step.push_back(v[q].second);
-                    }
-                    src_ptr[(size_t)w * (n->n_inst + 1) + b + 1] = src_id.size();
-                }
-            }
-            spk_ptr.push_back(spk_step.size());
-            if (!src_id.empty()) {
-                uint64_t* d_sp = dev_alloc_t<uint64_t>(n, src_ptr.size(), true);
-                uint32_t* d_si = dev_alloc_t<uint32_t>(n, src_id.size(), true);
-                uint64_t* d_pp = dev_alloc_t<uint64_t>(n, spk_ptr.size(), true);
-                int64_t* d_ss = dev_alloc_t<int64_t>(n, spk_step.size(), true);
-                CX_HIP(hipMemcpyAsync(d_sp, src_ptr.data(), src_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                CX_HIP(hipMemcpyAsync(d_si, src_id.data(), src_id.size() * 4, hipMemcpyHostToDevice, n->stream));
-                CX_HIP(hipMemcpyAsync(d_pp, spk_ptr.data(), spk_ptr.size() * 8, hipMemcpyHostToDevice, n->stream));
-                CX_HIP(hipMemcpyAsync(d_ss, spk_step.data(), spk_step.size() * 8, hipMemcpyHostToDevice, n->stream));
+            // weight gradient of the synapses whose arrivals land in the segment
+            if (!L.src_id.empty()) {
+                const int n_sub = (int)((len + sw - 1) / sw);
+                uint64_t* d_sp = dev_alloc_t<uint64_t>(n, L.src_ptr.size(), true);
+                uint32_t* d_si = dev_alloc_t<uint32_t>(n, L.src_id.size(), true);
+                uint64_t* d_pp = dev_alloc_t<uint64_t>(n, L.spk_ptr.size(), true);
+                int64_t* d_ss = dev_alloc_t<int64_t>(n, L.spk_step.size(), true);
+                CX_HIP(hipMemcpyAsync(d_sp, L.src_ptr.data(), L.src_ptr.size() * 8, hipMemcpyHostToDevice,
+                                      n->stream));
+                CX_HIP(hipMemcpyAsync(d_si, L.src_id.data(), L.src_id.size() * 4, hipMemcpyHostToDevice,
+                                      n->stream));
+                CX_HIP(hipMemcpyAsync(d_pp, L.spk_ptr.data(), L.spk_ptr.size() * 8, hipMemcpyHostToDevice,
+                                      n->stream));
+                CX_HIP(hipMemcpyAsync(d_ss, L.spk_step.data(), L.spk_step.size() * 8, hipMemcpyHostToDevice,
+                                      n->stream));
                 WgradArgs wa{};
                 wa.tile_inst = n->d_tile_inst; wa.tile_size = n->d_tile_size; wa.inst_tile0 = n->d_inst_tile0;
                 wa.inst_ntiles = n->d_inst_ntiles; wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0;
@@ -438,6 +456,9 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(1024), wgrad_lds, n->stream, wa);
                 CX_HIP(hipGetLastError());
             }
+            // the previous segment's lists, into the other set, while the
+            // device runs this one
+            if (k > 0) build_lists(k - 1, lists[(k - 1) & 1]);
             CX_HIP(hipStreamSynchronize(n->stream));
             {
                 int32_t e = 0;
