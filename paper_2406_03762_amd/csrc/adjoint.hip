@@ -195,17 +195,36 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
             const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
             const uint64_t e0 = a.row_start[j] + a.off_rel[ob], e1 = a.row_start[j] + a.off_rel[ob + 1];
             const uint64_t p0 = a.spk_ptr[s], p1 = a.spk_ptr[s + 1];
-            for (uint64_t e = e0 + lane; e < e1; e += 64) {
-                const uint32_t m = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                            : static_cast<const uint32_t*>(a.meta)[e];
-                const int64_t d = a.dmin + (int64_t)(m / (uint32_t)a.T);
-                const int li = (int)(m % (uint32_t)a.T);
-                float acc = 0.f;
-                for (uint64_t p = p0; p < p1; ++p) {
-                    const int64_t tau = a.spk_step[p] + d;
-                    if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+            // four synapses per lane at a time; a synapse's record and its
+            // gradient so far are loaded together (this wave is the only
+            // writer of the segment's gradients in this sub-window)
+            for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
+                uint32_t m[4];
+                float g[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t e = eb + 64u * u;
+                    m[u] = 0;
+                    g[u] = 0.f;
+                    if (e < e1) {
+                        m[u] = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                        : static_cast<const uint32_t*>(a.meta)[e];
+                        g[u] = a.grad[e];
+                    }
                 }
-                if (acc != 0.f) a.grad[e] += acc;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t e = eb + 64u * u;
+                    if (e >= e1) continue;
+                    const int64_t d = a.dmin + (int64_t)(m[u] / (uint32_t)a.T);
+                    const int li = (int)(m[u] % (uint32_t)a.T);
+                    float acc = 0.f;
+                    for (uint64_t p = p0; p < p1; ++p) {
+                        const int64_t tau = a.spk_step[p] + d;
+                        if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+                    }
+                    if (acc != 0.f) a.grad[e] = g[u] + acc;
+                }
             }
         }
     }
