@@ -164,6 +164,13 @@ struct WgradArgs {
     int64_t N, s0, s1;
 };
 
+// Lane i's value of v, for a wave-uniform i.
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int i) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // One workgroup (16 waves) per tile.  The segment's steps are taken in
 // sub-windows of sw steps; for each, the tile's dL/dx values of those steps
 // are staged in LDS ([sw][tile size]), then one wave per source whose spikes
@@ -190,40 +197,56 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
         }
         __syncthreads();
         const uint64_t* sp = a.src_ptr + (size_t)w * (a.n_inst + 1);
-        for (uint64_t s = sp[b] + wave; s < sp[b + 1]; s += n_waves) {
-            const uint32_t j = a.src_id[s];
-            const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-            const uint64_t e0 = a.row_start[j] + a.off_rel[ob], e1 = a.row_start[j] + a.off_rel[ob + 1];
-            const uint64_t p0 = a.spk_ptr[s], p1 = a.spk_ptr[s + 1];
-            // four synapses per lane at a time; a synapse's record and its
-            // gradient so far are loaded together (this wave is the only
-            // writer of the segment's gradients in this sub-window)
-            for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
-                uint32_t m[4];
-                float g[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint64_t e = eb + 64u * u;
-                    m[u] = 0;
-                    g[u] = 0.f;
-                    if (e < e1) {
-                        m[u] = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                        : static_cast<const uint32_t*>(a.meta)[e];
-                        g[u] = a.grad[e];
+        // a wave takes 16 consecutive sources at a time: lanes 0-15 load
+        // their segment bounds and spike ranges together, then the wave
+        // walks the 16 segments one after the other
+        constexpr int kSB = 16;
+        for (uint64_t sb = sp[b] + (uint64_t)wave * kSB; sb < sp[b + 1]; sb += (uint64_t)n_waves * kSB) {
+            const int cnt = (int)min<uint64_t>(kSB, sp[b + 1] - sb);
+            uint64_t e0l = 0, e1l = 0, p0l = 0, p1l = 0;
+            if (lane < cnt) {
+                const uint64_t s = sb + lane;
+                const uint32_t j = a.src_id[s];
+                const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+                const uint64_t rs = a.row_start[j];
+                e0l = rs + a.off_rel[ob];
+                e1l = rs + a.off_rel[ob + 1];
+                p0l = a.spk_ptr[s];
+                p1l = a.spk_ptr[s + 1];
+            }
+            for (int i = 0; i < cnt; ++i) {
+                const uint64_t e0 = lane_u64(e0l, i), e1 = lane_u64(e1l, i);
+                const uint64_t p0 = lane_u64(p0l, i), p1 = lane_u64(p1l, i);
+                // four synapses per lane at a time; a synapse's record and its
+                // gradient so far are loaded together (this wave is the only
+                // writer of the segment's gradients in this sub-window)
+                for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
+                    uint32_t m[4];
+                    float g[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint64_t e = eb + 64u * u;
+                        m[u] = 0;
+                        g[u] = 0.f;
+                        if (e < e1) {
+                            m[u] = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                            : static_cast<const uint32_t*>(a.meta)[e];
+                            g[u] = a.grad[e];
+                        }
                     }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint64_t e = eb + 64u * u;
-                    if (e >= e1) continue;
-                    const int64_t d = a.dmin + (int64_t)(m[u] / (uint32_t)a.T);
-                    const int li = (int)(m[u] % (uint32_t)a.T);
-                    float acc = 0.f;
-                    for (uint64_t p = p0; p < p1; ++p) {
-                        const int64_t tau = a.spk_step[p] + d;
-                        if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint64_t e = eb + 64u * u;
+                        if (e >= e1) continue;
+                        const int64_t d = a.dmin + (int64_t)(m[u] / (uint32_t)a.T);
+                        const int li = (int)(m[u] % (uint32_t)a.T);
+                        float acc = 0.f;
+                        for (uint64_t p = p0; p < p1; ++p) {
+                            const int64_t tau = a.spk_step[p] + d;
+                            if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+                        }
+                        if (acc != 0.f) a.grad[e] = g[u] + acc;
                     }
-                    if (acc != 0.f) a.grad[e] = g[u] + acc;
                 }
             }
         }
