@@ -130,7 +130,12 @@ typedef struct {
 
 typedef struct cortex_net cortex_net;
 
-/* Build a network from `spec` with Philox key (seed, instance): generates
+/* Passage: the graph G = (V, E) of Sec. II-A with its indegree sub-graphs
+   (Eq. 5) over a partition of the neurons (Eq. 9-10), bound to their owners
+   as in Sec. III-B (Fig. v_e_map_thread) and balanced by edge count
+   (Sec. III-A, load balance); the populations, projections and neuron
+   parameters are the problem description of Sec. II-B.
+   Build a network from `spec` with Philox key (seed, instance): generates
    every synapse on the device, lays the graph out in indegree tiles and sets
    the initial state (step 0).  Synchronising.  *out receives the handle.
    Errors: EINVAL (bad spec), ENOMEM, EDEVICE, EUNSUPPORTED (e.g. input rings
@@ -138,24 +143,37 @@ typedef struct cortex_net cortex_net;
 int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_device* dev,
                          cortex_net** out);
 
-/* Advance the simulation by n_steps (closed loop: spikes from threshold
+/* Passage: the simulation step of Sec. II-B (Fig.
+   brain_simulation_procedure (d)): synapses of spiking sources act on their
+   targets after each synapse's delay, then every neuron advances by the LIF
+   dynamics of Eq. 1 with threshold, reset and refractory period (Eq. 2);
+   only the spiking sub-graph (Eq. 11) of each owner is read.  Spikes are
+   exchanged once per window of steps no longer than the smallest delay, the
+   buffered-spike overlap of Sec. III-C.
+   Advance the simulation by n_steps (closed loop: spikes from threshold
    crossings).  Asynchronous on the network's stream.  FP32 networks run one
    persistent launch; the spike log keeps steps inside the record window.
    Errors: EINVAL (n_steps < 0), ESTATE (network failed earlier), EDEVICE,
    ETIMEOUT (reported by the next synchronising call). */
 int cortex_step(cortex_net* net, int64_t n_steps);
 
-/* Spikes with step in [step0, step1) from the log, sorted by (step, id),
+/* Passage: the spike buffer of Sec. III-C (spikes broadcast and buffer),
+   read back as (step, neuron) pairs.
+   Spikes with step in [step0, step1) from the log, sorted by (step, id),
    into host arrays of `capacity` entries; *count = number of spikes in the
    range.  Returns ETRUNC if capacity < *count (the first `capacity` are
    written) or if the range leaves the record window.  Synchronising. */
 int cortex_get_spikes(cortex_net* net, int64_t step0, int64_t step1, uint32_t* steps,
                       uint32_t* ids, int64_t capacity, int64_t* count);
 
-/* Restart the spike log window at the current step. */
+/* Passage: the spike buffer of Sec. III-C.
+   Restart the spike log window at the current step. */
 int cortex_clear_spikes(cortex_net* net);
 
-/* Open loop with spikes frozen to a raster (host arrays, sorted by (step,
+/* Passage: the step of Sec. II-B with the spiking set of each step given
+   instead of computed (the spiking sub-graph of Eq. 11 taken from a
+   raster), so that delivery is a linear function of the weights.
+   Open loop with spikes frozen to a raster (host arrays, sorted by (step,
    id), absolute steps): advance n_steps; a neuron spikes and resets exactly at
    its raster entries, thresholds are not evaluated, and delivery uses the
    raster.  Optional device traces [n_steps][N] (float in FP32 mode, double in
@@ -164,7 +182,12 @@ int cortex_clear_spikes(cortex_net* net);
 int cortex_run_frozen(cortex_net* net, const uint32_t* r_steps, const uint32_t* r_ids,
                       int64_t n_spikes, int64_t n_steps, void* x_trace, void* v_trace);
 
-/* Gradient of L = sum_b 1/(N_b T) sum_{i in b, n < T} (V_i(n) - V*_i(n))^2
+/* Passage: the exact integration of Eq. 1 between spikes (linear in the
+   synaptic input) and the delivery of Sec. II-B over the indegree
+   sub-graphs of Eq. 5: with spikes frozen, V is affine in the weights, and
+   the gradient is the transpose of delivery over the same spiking
+   sub-graph (Eq. 11), one writer per synapse as in Sec. III-B.
+   Gradient of L = sum_b 1/(N_b T) sum_{i in b, n < T} (V_i(n) - V*_i(n))^2
    over the T steps simulated since the build (or the last cortex_reset),
    with every neuron's spikes frozen to the ones it emitted, with respect to
    all stored synaptic weights (native units).  Requires spec.ckpt_every > 0
@@ -173,7 +196,9 @@ int cortex_run_frozen(cortex_net* net, const uint32_t* r_steps, const uint32_t* 
    Synchronising.  Errors: ESTATE (adjoint not enabled / window too long). */
 int cortex_backward(cortex_net* net, const float* vstar, float* grad_w, double* loss);
 
-/* Replace every stored synaptic weight (native units; FP32 networks with
+/* Passage: the synaptic weights W of Eq. 3 (current form), one per edge of
+   G (Sec. II-A), stored inside their target's indegree sub-graph (Eq. 5).
+   Replace every stored synaptic weight (native units; FP32 networks with
    spec.ckpt_every > 0, at step 0, i.e. after the build or cortex_reset):
    w_canonical is a device float [E] in canonical synapse order (caller
    owned, read only).  Weights are stored in the network's weight format and
@@ -184,24 +209,34 @@ int cortex_backward(cortex_net* net, const float* vstar, float* grad_w, double* 
    EUNSUPPORTED (FP64 networks), EINVAL (NULL). */
 int cortex_set_weights(cortex_net* net, const float* w_canonical);
 
-/* Back to the build-time state (step 0, empty input rings, empty log). */
+/* Passage: the initial state of the simulation of Sec. II-B.
+   Back to the build-time state (step 0, empty input rings, empty log). */
 int cortex_reset(cortex_net* net);
 
-/* Neuron state into host arrays of N entries (V in mV; r = refractory steps
+/* Passage: the state of the LIF neuron of Eq. 1-2 (membrane potential,
+   refractory clock) and of its current synapse (Eq. 3, current form).
+   Neuron state into host arrays of N entries (V in mV; r = refractory steps
    left; y1/y2 synaptic state as in the oracle: exp y1 = current; alpha y1 =
    auxiliary, y2 = current); NULL skips an array.  Synchronising. */
 int cortex_get_state(cortex_net* net, double* V, int32_t* r, double* y1, double* y2);
 
-/* All synapses into host arrays of E entries, in the library's storage
+/* Passage: the edges E of Sec. II-A as triplets (source, target, weight)
+   plus the delay, stored per source and per owning tile (the segments of
+   the spiking sub-graph, Eq. 11; Sec. III-B, Fig. data_ins).
+   All synapses into host arrays of E entries, in the library's storage
    order (grouped by source, then tile).  Global ids; delay in steps; weight
    as stored, widened to double.  Synchronising. */
 int cortex_export_graph(cortex_net* net, int64_t* src, int64_t* tgt, double* w, int32_t* d);
 
-/* Canonical index of every stored synapse (host int64[E], storage order),
+/* Passage: the bijection between stored and canonical edges that makes
+   the indegree sub-graphs a partition of E (Eq. 8).
+   Canonical index of every stored synapse (host int64[E], storage order),
    so export order can be mapped to canonical order. Synchronising. */
 int cortex_export_canonical(cortex_net* net, int64_t* canon);
 
-/* Tile table into host arrays of n_tiles entries: first global target,
+/* Passage: the partition of V into disjoint parts V_1 ... V_n (Eq. 9-10),
+   one per owner.
+   Tile table into host arrays of n_tiles entries: first global target,
    number of targets, instance.  Synchronising. */
 int cortex_export_tiles(cortex_net* net, int64_t* start, int32_t* size, int32_t* instance);
 
@@ -224,14 +259,18 @@ enum {
     CORTEX_Q_STEPS_PER_SYNC = 15, /* FP32: time steps per spike exchange chosen at build */
     CORTEX_Q_RING_BYTES = 16      /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
 };
-/* Scalar facts about the network into *value.  EVENTS and SPIKES
+/* Passage: the sizes of G (Sec. II-A) and of its decomposition (Eq. 9-10);
+   EVENTS counts the edges of the spiking sub-graphs (Eq. 11) delivered.
+   Scalar facts about the network into *value.  EVENTS and SPIKES
    synchronise. */
 int cortex_query(cortex_net* net, int what, int64_t* value);
 
-/* Release the network and its device memory.  NULL is ignored. */
+/* Passage: none (resource management).
+   Release the network and its device memory.  NULL is ignored. */
 void cortex_destroy(cortex_net* net);
 
-/* Message of the last failure on the calling thread (never NULL). */
+/* Passage: none (error reporting).
+   Message of the last failure on the calling thread (never NULL). */
 const char* cortex_last_error(void);
 
 #ifdef __cplusplus

@@ -111,6 +111,29 @@ def _ptr(a) -> Optional[int]:
     return a.data_ptr()
 
 
+def _dev_ptr(t, name: str, dtype, numel: int, device=None) -> Optional[int]:
+    """Address of a device buffer the library reads or writes, after checking
+    that it is a contiguous torch tensor of `dtype` with `numel` elements on
+    the network's GPU (host memory or a wrong type would be read through a
+    wrong pointer on the device)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise CortexError(EINVAL, f"{name} must be a torch tensor on the GPU, not {type(t).__name__}")
+    if not t.is_cuda:
+        raise CortexError(EINVAL, f"{name} must be on the GPU (got {t.device})")
+    if device is not None and t.device != torch.device(device):
+        raise CortexError(EINVAL, f"{name} is on {t.device}, the network on {device}")
+    if t.dtype != dtype:
+        raise CortexError(EINVAL, f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise CortexError(EINVAL, f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise CortexError(EINVAL, f"{name} must have {numel} elements (got {t.numel()})")
+    return t.data_ptr()
+
+
 _MODEL = {"delta": 0, "exp": 1, "alpha": 2}
 _RULE = {"fixed_indegree": 0, "pairwise": 1}
 _DELAY = {"const": 0, "uniform_int": 1, "normal": 2}
@@ -219,21 +242,55 @@ def cortex_get_spikes(h, step0: int, step1: int):
     return st[:n], ids[:n]
 
 
-def cortex_run_frozen(h, steps, ids, n_steps: int, x_trace=None, v_trace=None) -> None:
+def _net_facts(h):
+    """(N, E, step, fp64) of a network handle."""
+    v = C.c_int64()
+    out = []
+    for q in ("NEURONS", "SYNAPSES", "STEP"):
+        _check(lib().cortex_query(h, Q[q], C.byref(v)))
+        out.append(v.value)
+    return out
+
+
+def _raster(steps, ids):
     st = np.ascontiguousarray(steps, np.uint32)
     ii = np.ascontiguousarray(ids, np.uint32)
+    if st.shape != ii.shape or st.ndim != 1:
+        raise CortexError(EINVAL, "raster steps and ids must be 1-D arrays of one length")
+    return st, ii
+
+
+def cortex_run_frozen(h, steps, ids, n_steps: int, x_trace=None, v_trace=None, fp64: bool = False,
+                      device=None) -> None:
+    """x_trace / v_trace: device tensors [n_steps, N] (float64 for FP64
+    networks, float32 otherwise) or None."""
+    import torch
+    st, ii = _raster(steps, ids)
+    N = _net_facts(h)[0]
+    dt = torch.float64 if fp64 else torch.float32
+    xp = _dev_ptr(x_trace, "x_trace", dt, n_steps * N, device)
+    vp = _dev_ptr(v_trace, "v_trace", dt, n_steps * N, device)
     _check(lib().cortex_run_frozen(h, st.ctypes.data if len(st) else None,
-                                   ii.ctypes.data if len(ii) else None, len(st), n_steps,
-                                   _ptr(x_trace), _ptr(v_trace)))
+                                   ii.ctypes.data if len(ii) else None, len(st), n_steps, xp, vp))
 
 
-def cortex_set_weights(h, w_canonical) -> None:
-    _check(lib().cortex_set_weights(h, _ptr(w_canonical)))
+def cortex_set_weights(h, w_canonical, device=None) -> None:
+    import torch
+    E = _net_facts(h)[1]
+    _check(lib().cortex_set_weights(h, _dev_ptr(w_canonical, "w_canonical", torch.float32, E, device)))
 
 
-def cortex_backward(h, vstar, grad_w) -> float:
+def cortex_backward(h, vstar, grad_w, device=None) -> float:
+    """vstar: device float32 [T, N] with T = steps simulated since the build
+    or reset; grad_w: device float32 [E] (written)."""
+    import torch
+    N, E, T = _net_facts(h)
+    if vstar is None or grad_w is None:
+        # let the library report its own state errors (adjoint not enabled)
+        _check(lib().cortex_backward(h, None, None, None))
     loss = C.c_double()
-    _check(lib().cortex_backward(h, _ptr(vstar), _ptr(grad_w), C.byref(loss)))
+    _check(lib().cortex_backward(h, _dev_ptr(vstar, "vstar", torch.float32, T * N, device),
+                                 _dev_ptr(grad_w, "grad_w", torch.float32, E, device), C.byref(loss)))
     return loss.value
 
 
@@ -288,6 +345,7 @@ class Network:
         import torch
         self.spec = net
         self._h, self._keep = cortex_build_network(net, seed, **plan)
+        self.device = self._keep[0].device
         self.N = cortex_query(self._h, "NEURONS")
         self.E = cortex_query(self._h, "SYNAPSES")
         self.fp64 = net.precision == "fp64"
@@ -321,22 +379,28 @@ class Network:
             cortex_run_frozen(self._h, steps, ids, n_steps)
             return None, None
         dt = self.torch.float64 if self.fp64 else self.torch.float32
-        x = self.torch.empty((n_steps, self.N), dtype=dt, device="cuda")
-        v = self.torch.empty((n_steps, self.N), dtype=dt, device="cuda")
-        cortex_run_frozen(self._h, steps, ids, n_steps, x, v)
+        x = self.torch.empty((n_steps, self.N), dtype=dt, device=self.device)
+        v = self.torch.empty((n_steps, self.N), dtype=dt, device=self.device)
+        cortex_run_frozen(self._h, steps, ids, n_steps, x, v, fp64=self.fp64, device=self.device)
         return x, v
 
     def backward(self, vstar, grad=None):
+        """vstar: target voltages [T, N] (numpy or torch; converted to a
+        float32 device tensor); returns (grad [E] float32 on the device, loss)."""
+        if isinstance(vstar, np.ndarray):
+            vstar = self.torch.as_tensor(vstar, dtype=self.torch.float32, device=self.device)
         if grad is None:
-            grad = self.torch.empty(self.E, dtype=self.torch.float32, device="cuda")
-        loss = cortex_backward(self._h, vstar, grad)
+            grad = self.torch.empty(self.E, dtype=self.torch.float32, device=self.device)
+        loss = cortex_backward(self._h, vstar, grad, device=self.device)
         return grad, loss
 
     def set_weights(self, w_canonical) -> None:
-        """Replace all weights (device float tensor [E], canonical order); at step 0."""
-        w = w_canonical.detach().to(dtype=self.torch.float32).contiguous()
-        cortex_set_weights(self._h, w)
-        self.torch.cuda.current_stream().synchronize()
+        """Replace all weights (float tensor or array [E], canonical order); at step 0."""
+        if isinstance(w_canonical, np.ndarray):
+            w_canonical = self.torch.as_tensor(w_canonical)
+        w = w_canonical.detach().to(device=self.device, dtype=self.torch.float32).contiguous()
+        cortex_set_weights(self._h, w, device=self.device)
+        self.torch.cuda.current_stream(self.device).synchronize()
 
     def canonical_weights(self):
         """The stored weights as a float64 numpy array in canonical synapse order."""

@@ -425,6 +425,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
         for (int k = K - 1; k >= 0; --k) {
             const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
             SegLists& L = lists[k & 1];
+            const size_t seg_mark = n->scratch.size();
             restore_checkpoint(n, k);
             n->step = s0;
             // Records left in the publication buffer by the forward run or a
@@ -510,7 +511,9 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                     throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
                 }
             }
-            // per-segment scratch (lists) is released; large buffers stay
+            // the segment's device lists go back to the allocator (the stream
+            // has drained); the large buffers above stay for the whole pass
+            free_scratch_from(n, seg_mark);
         }
         hipLaunchKernelGGL(gather_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad,
                            n->d_canon_inv, grad_w, n->E);

@@ -150,6 +150,14 @@ void free_scratch(cortex_net* n) {
     release(n, n->scratch);
 }
 
+void free_scratch_from(cortex_net* n, size_t mark) {
+    if (mark >= n->scratch.size()) return;
+    (void)hipStreamSynchronize(n->stream);
+    std::vector<DevBuf> tail(n->scratch.begin() + (std::ptrdiff_t)mark, n->scratch.end());
+    n->scratch.resize(mark);
+    release(n, tail);
+}
+
 void dev_zero(cortex_net* n, void* p, size_t bytes) {
     if (bytes) CX_HIP(hipMemsetAsync(p, 0, bytes, n->stream));
 }
@@ -949,6 +957,8 @@ int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* lo
     require_net(n);
     require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "the adjoint runs in FP32 mode");
     require(n->ckpt > 0, CORTEX_ESTATE, "adjoint not enabled (ckpt_every = 0 at build)");
+    require(vstar != nullptr && grad_w != nullptr && loss != nullptr, CORTEX_EINVAL,
+            "vstar, grad_w and loss must not be NULL");
     check_device_flag(n);
     adjoint_backward(n, vstar, grad_w, loss);
     free_scratch(n);

@@ -171,6 +171,9 @@ struct cortex_net {
 namespace cortex {
 void* dev_alloc(cortex_net* n, size_t bytes, bool scratch = false);
 void free_scratch(cortex_net* n);
+// Release the scratch buffers allocated after the first `mark` ones (waits
+// for the stream first).
+void free_scratch_from(cortex_net* n, size_t mark);
 void dev_zero(cortex_net* n, void* p, size_t bytes);
 template <class T>
 T* dev_alloc_t(cortex_net* n, size_t count, bool scratch = false) {
