@@ -1,14 +1,21 @@
 """Throughput of the LIF + delayed delivery step on one MI355X.
 
-Workload: the 112,500-neuron balanced network with alpha-current LIF neurons,
-in-degree 9,000 E + 2,250 I (1.27e9 synapses), delays uniform on 5..30 steps,
-FP32, dt = 0.1 ms.  One benchmark step simulates 1 s (10,000 time steps) in
-one persistent launch; inputs (graph, state) are resident in HBM before the
-timed region.  Prints one JSON line.
+Headline workload: the largest single-GPU network, a balanced random network
+of 2,000,000 delta-current LIF neurons (1.6 M E / 0.4 M I) with in-degree
+9,000 E + 2,250 I (2.25e10 synapses, 16-bit records and bf16 weights, FP32
+accumulation), delays uniform on 5..30 steps, dt = 0.1 ms.  Its input rings
+(240 MB) exceed the chip's workgroup-local memory, so it runs the streamed
+plan: one kernel launch per window of 5 steps over all tiles, replayed from a
+captured HIP graph.  One benchmark step simulates 1 s (10,000 time steps);
+inputs (graph, state) are resident in HBM before the timed region.  Prints
+one JSON line; secondary workloads (the 112,500-neuron alpha net on the
+resident persistent plan, the microcircuit stand-in, the FP64 verification
+net, the batched instances and the adjoint) are reported beside it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,28 +28,97 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per synaptic event of the step kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (calibrated against a 1 GiB copy; profiles/step_kernel_brunel112k_alpha.md),
-# valid only for the kernel source it was measured on.
-TRAFFIC_BYTES_PER_EVENT = (3.0703e7 * 2.0 + 1.8482e6 * 1.0) * 1024 / 9.072019401e9
-TRAFFIC_SOURCE_HASH = "4b542c1b14690f92"
 SIM_STEPS_PER_BENCH_STEP = 10000      # 1 s of biological time at dt = 0.1 ms
+CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
+
+# HBM bytes per synaptic event of a kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (each scaled by its reading for a plain device copy of known
+# size, as the summaries under profiles/ state), valid only for the sources
+# they were measured on: {kernel: (bytes per event, source hash)}.
+TRAFFIC = {
+    "step_kernel": ((3.0703e7 * 2.0 + 1.8482e6 * 1.0) * 1024 / 9.072019401e9, "4b542c1b14690f92"),
+}
 
 
-def step_source_hash():
-    import hashlib
-    p = os.path.join(ROOT, "paper_2406_03762_amd", "csrc", "step.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+def source_hash(kernel: str) -> str:
+    files = {"step_kernel": ["step.hip"], "stream_kernel": ["stream.hip", "deliver.hpp"]}[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_event(kernel: str):
+    t = TRAFFIC.get(kernel)
+    if t is None or source_hash(kernel) != t[1]:
+        return None
+    return t[0]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def timed_run(net, torch, steps, warmup, sim_steps, name):
+    """`warmup` untimed, then `steps` timed calls of cortex_step(sim_steps),
+    bracketed by synchronisations; HIP events on the caller's stream around
+    each call (the library orders its own graph stream inside them)."""
+    for w in range(warmup):
+        net.step(sim_steps)
+        torch.cuda.synchronize()
+        log(f"[bench] {name}: warmup {w + 1}/{warmup} done")
+    stream = torch.cuda.current_stream()
+    ev0, sp0 = net.query("EVENTS"), net.query("SPIKES")
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        net.step(sim_steps)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    events = net.query("EVENTS") - ev0
+    spikes = net.query("SPIKES") - sp0
+    sim_s = steps * sim_steps * net.spec.dt * 1e-3
+    out = {"wall_s": wall, "events": events, "spikes": spikes, "sim_s": sim_s,
+           "events_per_s": events / wall, "rtf": wall / sim_s,
+           "firing_rate_hz": spikes / (net.N * sim_s), "gpu_ms_per_step": float(np.mean(kern_ms))}
+    log(f"[bench] {name}: {steps} x {sim_steps} steps in {wall:.3f} s, {out['events_per_s']:.3e} events/s, "
+        f"rate {out['firing_rate_hz']:.2f} Hz, rtf {out['rtf']:.3f}")
+    return out
+
+
+def roofline(net, run, steps, sim_steps):
+    """Roofline of the dominant kernel: algorithmic record bytes of one launch
+    over the launch's average duration (event-timed calls divided by their
+    launches: one persistent launch per call, or one per window)."""
+    streamed = net.query("PLAN") == 2
+    kernel = "stream_kernel" if streamed else "step_kernel"
+    W = net.query("STEPS_PER_SYNC")
+    launches = -(-sim_steps // W) if streamed else 1
+    B_rec = net.query("EDGE_BYTES")
+    events_per_launch = run["events"] / steps / launches
+    avg_launch_s = run["gpu_ms_per_step"] * 1e-3 / launches
+    achieved = events_per_launch * B_rec / avg_launch_s / 1e9
+    tpe = traffic_per_event(kernel)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if tpe is None else tpe * events_per_launch,
+            "kernel": kernel, "launches_per_step": launches, "record_bytes": B_rec,
+            "algorithmic_bytes_per_launch": events_per_launch * B_rec,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "offset_bytes_per_launch": run["spikes"] / steps / launches * net.query("TILES") * 8}
+
+
 def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
     """The CPU oracle on a bounded sample of the same workload: every synapse
-    into `n_targets` sampled neurons, those neurons' updates, driven for
-    `n_steps` by a replayed raster of all sources at the measured rate."""
+    into `n_targets` sampled neurons (weights as the network stores them),
+    those neurons' updates, driven for `n_steps` by a replayed raster of all
+    sources at the measured rate.  Events/s is a per-event rate, so it scales
+    to the whole network."""
     import oracle
     import netspec
     N = spec.n_neurons
@@ -67,18 +143,34 @@ def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
     }
 
 
+def brunel_112k(cx, torch, netspec, args):
+    """The 112,500-neuron alpha-current net on the resident persistent plan."""
+    spec = netspec.brunel_112k_alpha()
+    log("[bench] brunel_112k: building")
+    t0 = time.perf_counter()
+    net = cx.Network(spec, 2)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    run = timed_run(net, torch, args.steps, args.warmup, SIM_STEPS_PER_BENCH_STEP, "brunel_112k")
+    out = dict(run, neurons=net.N, synapses=net.E, graph_build_s=t_build, tiles=net.query("TILES"),
+               tile_size=net.query("TILE_SIZE"), block_size=net.query("BLOCK_SIZE"),
+               steps_per_sync=net.query("STEPS_PER_SYNC"), plan="resident",
+               roofline=roofline(net, run, args.steps, SIM_STEPS_PER_BENCH_STEP))
+    net.close()
+    return out
+
+
 def _pack_instances(cx, netspec, spec, seed):
     """Greedy packing of the instances into as few co-resident launches as the
     device allows: each group is the longest prefix of the remaining
-    instances whose plan fits (a plan that does not fit fails before the graph
-    is generated)."""
+    instances whose resident plan fits."""
     groups, rest = [], list(spec.instances)
     while rest:
         k = len(rest)
         while True:
             sub = netspec.NetSpec(**{**spec.__dict__, "instances": rest[:k]})
             try:
-                net = cx.Network(sub, seed + len(groups))
+                net = cx.Network(sub, seed, plan="resident")
                 break
             except cx.CortexError as e:
                 if e.status != cx.EUNSUPPORTED or k == 1:
@@ -91,57 +183,64 @@ def _pack_instances(cx, netspec, spec, seed):
 
 def batched_and_adjoint(cx, torch, seed, sim_steps):
     """Secondary figures on the batched workload (64 Brunel instances of
-    log-uniform size 1,250-50,000, delta LIF, 1.5 ms delays): the instances
-    packed into as few persistent launches as fit the device vs the same
-    instances run one after another, and the adjoint (backward) against its
-    forward on the first packed group."""
+    log-uniform size 1,250-50,000, delta LIF, 1.5 ms delays): all instances in
+    one launch per window (streamed plan, captured graph), the resident
+    persistent plan packed into as few co-resident launches as fit, and the
+    instances one after another; then the adjoint against its forward."""
     import netspec
     spec = netspec.batched_brunel()
     out = {"workload": "64 balanced delta-LIF instances, N log-uniform 1,250-50,000 (seeded), "
                        "in-degree 10% of each population, delay 1.5 ms, FP32",
            "sim_steps": sim_steps, "neurons": spec.n_neurons}
-    log("[bench] batched: packing 64 instances into co-resident launches")
+
+    def timed(nets):
+        for net in nets:
+            net.step(200)
+        torch.cuda.synchronize()
+        e0 = [net.query("EVENTS") for net in nets]
+        t0 = time.perf_counter()
+        for net in nets:
+            net.step(sim_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return sum(net.query("EVENTS") - e for net, e in zip(nets, e0)) / dt, dt
+
+    log("[bench] batched: all 64 instances, streamed plan")
+    net = cx.Network(spec, seed, plan="streamed")
+    out["streamed"] = {"tiles": net.query("TILES"), "tile_size": net.query("TILE_SIZE"),
+                       "steps_per_sync": net.query("STEPS_PER_SYNC"), "synapses": net.E}
+    eps, dt = timed([net])
+    out["streamed"].update(events_per_s=eps, wall_s=dt, launches_per_window=1)
+    net.close()
+    log(f"[bench] batched streamed: {eps:.3e} events/s")
+    log("[bench] batched: resident plan, packed")
     groups = _pack_instances(cx, netspec, spec, seed)
-    out["launches"] = len(groups)
-    out["instances_per_launch"] = [len(g.instances) for g, _ in groups]
-    out["synapses"] = int(sum(net.E for _, net in groups))
-    log(f"[bench] batched: {len(groups)} launches of {out['instances_per_launch']} instances")
-    for i, (_, net) in enumerate(groups):
-        log(f"[bench] batched launch {i}: tiles={net.query('TILES')} T={net.query('TILE_SIZE')} "
-            f"BS={net.query('BLOCK_SIZE')} W={net.query('STEPS_PER_SYNC')} ring={net.query('RING_BYTES')}B")
+    out["resident"] = {"launches": len(groups), "instances_per_launch": [len(g.instances) for g, _ in groups]}
+    eps_r, dt_r = timed([net for _, net in groups])
+    out["resident"].update(events_per_s=eps_r, wall_s=dt_r)
     for _, net in groups:
-        net.step(200)
-    torch.cuda.synchronize()
-    e0 = [net.query("EVENTS") for _, net in groups]
-    t0 = time.perf_counter()
-    for _, net in groups:
-        net.step(sim_steps)
-    torch.cuda.synchronize()
-    dt_b = time.perf_counter() - t0
-    ev_b = sum(net.query("EVENTS") - e for (_, net), e in zip(groups, e0))
-    log(f"[bench] batched: {ev_b / dt_b:.3e} events/s")
+        net.close()
+    del groups
+    log(f"[bench] batched resident: {eps_r:.3e} events/s")
+    ev_s, dt_s = 0, 0.0
+    for b, inst in enumerate(spec.instances):
+        one = netspec.NetSpec(**{**spec.__dict__, "instances": [inst]})
+        g = cx.Network(one, seed, plan="resident")
+        e, d = timed([g])
+        ev_s += e * d
+        dt_s += d
+        g.close()
+    out["sequential_events_per_s"] = ev_s / dt_s
+    out["speedup_streamed_vs_sequential"] = eps / (ev_s / dt_s)
+    out["speedup_resident_vs_sequential"] = eps_r / (ev_s / dt_s)
+    log(f"[bench] one instance per launch: {ev_s / dt_s:.3e} events/s")
+    # adjoint: checkpointed forward, then the gradient of the voltage loss
+    log("[bench] adjoint: forward with checkpoints")
+    groups = _pack_instances(cx, netspec, spec, seed)
     adj_spec = groups[0][0]
     for _, net in groups:
         net.close()
     del groups
-    ev_s, dt_s = 0, 0.0
-    for b, inst in enumerate(spec.instances):
-        one = netspec.NetSpec(**{**spec.__dict__, "instances": [inst]})
-        g = cx.Network(one, seed + 1000 + b)
-        g.step(200)
-        torch.cuda.synchronize()
-        e0 = g.query("EVENTS")
-        t0 = time.perf_counter()
-        g.step(sim_steps)
-        torch.cuda.synchronize()
-        dt_s += time.perf_counter() - t0
-        ev_s += g.query("EVENTS") - e0
-        g.close()
-    log(f"[bench] one instance per launch: {ev_s / dt_s:.3e} events/s")
-    out.update(events_per_s=ev_b / dt_b, sequential_events_per_s=ev_s / dt_s,
-               speedup=(ev_b / dt_b) / (ev_s / dt_s), batched_wall_s=dt_b, sequential_wall_s=dt_s)
-    # adjoint: checkpointed forward, then the gradient of the voltage loss
-    log("[bench] adjoint: forward with checkpoints")
     net = cx.Network(adj_spec, seed, ckpt_every=100, adjoint_steps=sim_steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -149,7 +248,8 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     ev_f = net.query("EVENTS")
-    vstar = torch.empty((sim_steps, net.N), dtype=torch.float32, device="cuda").uniform_(10.0, 20.0)
+    vstar = torch.as_tensor(netspec.target_trace(net.N, sim_steps, 10.0, 20.0, seed=seed + 7),
+                            dtype=torch.float32, device="cuda")
     grad = torch.empty(net.E, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -165,9 +265,9 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
 
 
 def secondary_configs(cx, torch, netspec):
-    """Events/s and real-time factor of the other single-GPU workloads: the
-    77,169-neuron exp-current microcircuit stand-in (FP32, 1 s) and the
-    1,250-neuron delta-LIF net in the FP64 verification mode (100 ms)."""
+    """Events/s and real-time factor of the 77,169-neuron exp-current
+    microcircuit stand-in (FP32, 1 s) and the 1,250-neuron delta-LIF net in
+    the FP64 verification mode (100 ms)."""
     out = {}
     for name, spec, seed, steps in (("microcircuit_77k_fp32", netspec.microcircuit_77k(), 3, 10000),
                                     ("brunel_1250_fp64_verify", netspec.brunel_1250_fp64(), 1, 1000)):
@@ -177,23 +277,13 @@ def secondary_configs(cx, torch, netspec):
             net = cx.Network(spec, seed)
             torch.cuda.synchronize()
             t_build = time.perf_counter() - t0
-            net.step(min(1000, steps))
-            torch.cuda.synchronize()
-            e0, s0 = net.query("EVENTS"), net.query("SPIKES")
-            t0 = time.perf_counter()
-            net.step(steps)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            ev, sp = net.query("EVENTS") - e0, net.query("SPIKES") - s0
-            sim_s = steps * spec.dt * 1e-3
-            out[name] = {"neurons": net.N, "synapses": net.E, "sim_steps": steps,
-                         "events_per_s": ev / wall, "rtf": wall / sim_s,
-                         "firing_rate_hz": sp / (net.N * sim_s), "graph_build_s": t_build}
+            run = timed_run(net, torch, 1, 1, steps, name)
+            out[name] = dict(run, neurons=net.N, synapses=net.E, sim_steps=steps, graph_build_s=t_build)
             if spec.precision != "fp64":
                 out[name].update(tiles=net.query("TILES"), tile_size=net.query("TILE_SIZE"),
                                  steps_per_sync=net.query("STEPS_PER_SYNC"),
-                                 ring_slots=net.query("RING_SLOTS"), record_bytes=net.query("EDGE_BYTES"))
-            log(f"[bench] {name}: {ev / wall:.3e} events/s, rtf {wall / sim_s:.3f}")
+                                 ring_slots=net.query("RING_SLOTS"), record_bytes=net.query("EDGE_BYTES"),
+                                 roofline=roofline(net, run, 1, steps))
             net.close()
         except cx.CortexError as e:
             log(f"[bench] {name} failed: {e}")
@@ -204,17 +294,18 @@ def secondary_configs(cx, torch, netspec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sim-steps", type=int, default=SIM_STEPS_PER_BENCH_STEP)
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="neuron-count scale of the headline network (1.0 = 2,000,000; smaller only for trials)")
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
-    ap.add_argument("--steps-per-sync", type=int, default=0,
-                    help="time steps per spike exchange (0 = the planner's choice)")
+    ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=6000)
-    ap.add_argument("--cpu-steps", type=int, default=12000)
+    ap.add_argument("--cpu-targets", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
@@ -236,21 +327,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    spec = netspec.brunel_112k_alpha()
-    log("[bench] building the 112,500-neuron alpha-LIF network")
+    spec = netspec.brunel_2m_bf16(scale_n=args.scale)
+    log(f"[bench] building the {spec.n_neurons:,}-neuron delta-LIF network (bf16 weights)")
     t0 = time.perf_counter()
     net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size,
-                     steps_per_sync=args.steps_per_sync)
+                     wg_per_cu=args.wg_per_cu)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
-    E = net.E
-    B_rec = net.query("EDGE_BYTES")
-    n_tiles = net.query("TILES")
-    tile_size = net.query("TILE_SIZE")
-    block_size = net.query("BLOCK_SIZE")
-    log(f"[bench] built: N={net.N} E={E} tiles={n_tiles} T={net.query('TILE_SIZE')} "
-        f"R={net.query('RING_SLOTS')} W={net.query('STEPS_PER_SYNC')} BS={net.query('BLOCK_SIZE')} rec={B_rec}B "
-        f"in {t_build:.1f}s")
+    log(f"[bench] built: N={net.N} E={net.E} plan={'streamed' if net.query('PLAN') == 2 else 'resident'} "
+        f"tiles={net.query('TILES')} T={net.query('TILE_SIZE')} R={net.query('RING_SLOTS')} "
+        f"W={net.query('STEPS_PER_SYNC')} BS={net.query('BLOCK_SIZE')} rec={net.query('EDGE_BYTES')}B "
+        f"device={net.query('DEVICE_BYTES') / 2**30:.1f} GiB in {t_build:.1f}s")
 
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
@@ -262,50 +349,37 @@ def main():
         log(f"[bench] calibration copy of {nb} bytes done")
         del src, dst
 
-    for w in range(args.warmup):
-        net.step(args.sim_steps)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
-
-    stream = torch.cuda.current_stream()
-    ev0 = net.query("EVENTS")
-    sp0 = net.query("SPIKES")
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        net.step(args.sim_steps)
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev1 = net.query("EVENTS")
-    sp1 = net.query("SPIKES")
-    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    events = ev1 - ev0
-    spikes = sp1 - sp0
-    sim_s = args.steps * args.sim_steps * spec.dt * 1e-3
-    rate_hz = spikes / (net.N * sim_s)
-    ev_per_s = events / wall
-    avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
-    bytes_per_launch = events / args.steps * B_rec
-    achieved = bytes_per_launch / avg_kernel_s / 1e9
-    offset_bytes = spikes / args.steps * n_tiles * 8
-    log(f"[bench] timed {args.steps} x {args.sim_steps} steps: wall {wall:.3f}s, "
-        f"kernel avg {avg_kernel_s * 1e3:.2f} ms, rate {rate_hz:.2f} Hz, {ev_per_s:.3e} events/s")
+    run = timed_run(net, torch, args.steps, args.warmup, args.sim_steps, "headline")
+    roof = roofline(net, run, args.steps, args.sim_steps)
+    cfg = {
+        "workload": (f"balanced random net, delta-current LIF, {spec.n_neurons:,} neurons "
+                     f"({spec.instances[0].pops[0].size:,} E / {spec.instances[0].pops[1].size:,} I), "
+                     "in-degree 9,000 E + 2,250 I, "
+                     f"{net.E:.3e} synapses (16-bit record + bf16 weight, FP32 accumulation), "
+                     "weights Normal(J, (0.1J)^2), J = 0.1 mV, g = 5, delays uniform 0.5-3.0 ms, "
+                     f"Poisson drive eta = 2, dt 0.1 ms; one step = {args.sim_steps} time steps "
+                     f"({args.sim_steps * spec.dt:.0f} ms)"),
+        "neurons": net.N, "synapses": net.E, "plan": "streamed" if net.query("PLAN") == 2 else "resident",
+        "tiles": net.query("TILES"), "tile_size": net.query("TILE_SIZE"),
+        "block_size": net.query("BLOCK_SIZE"), "steps_per_sync": net.query("STEPS_PER_SYNC"),
+        "record_bytes": net.query("EDGE_BYTES"),
+    }
+    net.close()
+    del net
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(spec, rate_hz, args.seed, args.cpu_targets, args.cpu_steps)
+        cpu = cpu_baseline(spec, run["firing_rate_hz"], args.seed, args.cpu_targets, args.cpu_steps)
         log(f"[bench] cpu baseline {cpu['value']:.3e} events/s")
 
-    net.close()
-    del net
-    secondary = None
+    secondary = {}
     if not args.no_secondary:
-        secondary = secondary_configs(cx, torch, netspec)
+        secondary["brunel_112k_alpha_fp32"] = brunel_112k(cx, torch, netspec, args)
+        torch.cuda.empty_cache()
+        secondary.update(secondary_configs(cx, torch, netspec))
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         try:
@@ -316,45 +390,22 @@ def main():
 
     out = {
         "metric": "synaptic events/s (1 GPU)",
-        "value": ev_per_s,
+        "value": run["events_per_s"],
         "unit": "synaptic events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": run["wall_s"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic (network and Poisson drive generated on device from Philox seeds)",
-        "config": {
-            "workload": "balanced random net, alpha-current LIF, 112,500 neurons (90,000 E / 22,500 I), "
-                        "in-degree 9,000 E + 2,250 I, 1.27e9 synapses, weights Normal(J, (0.1J)^2) "
-                        "as PSP peaks, delays uniform 0.5-3.0 ms, dt 0.1 ms, FP32; "
-                        f"one step = {args.sim_steps} time steps ({args.sim_steps * spec.dt:.0f} ms)",
-            "neurons": spec.n_neurons,
-            "synapses": E,
-            "tiles": n_tiles,
-            "tile_size": tile_size,
-            "block_size": block_size,
-            "record_bytes": B_rec,
-        },
-        "rtf": wall / sim_s,
-        "firing_rate_hz": rate_hz,
-        "events_per_launch": events / args.steps,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (TRAFFIC_BYTES_PER_EVENT * events / args.steps
-                        if step_source_hash() == TRAFFIC_SOURCE_HASH else None),
-            "kernel": "step_kernel",
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "offset_bytes_per_launch": offset_bytes,
-            "avg_launch_ms": avg_kernel_s * 1e3,
-        },
+        "config": cfg,
+        "rtf": run["rtf"],
+        "firing_rate_hz": run["firing_rate_hz"],
+        "events_per_step": run["events"] / args.steps,
+        "roofline": roof,
         "cpu_baseline": cpu,
         "graph_build_s": t_build,
         "other_workloads": secondary,

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CORTEX_ABI_VERSION 1
+#define CORTEX_ABI_VERSION 2
 
 typedef enum {
     CORTEX_OK = 0,
@@ -58,6 +58,12 @@ enum { CORTEX_DELAY_CONST = 0, CORTEX_DELAY_UNIFORM_INT = 1, CORTEX_DELAY_NORMAL
 enum { CORTEX_UNIT_NATIVE = 0, CORTEX_UNIT_PSP_MV = 1 };
 enum { CORTEX_FP32 = 0, CORTEX_FP64_VERIFY = 1 };
 enum { CORTEX_W_FP32 = 0, CORTEX_W_BF16 = 1 };
+/* FP32 launch plans: RESIDENT keeps every tile's input ring in workgroup-local
+   memory for a whole persistent launch; STREAMED launches one kernel per
+   window of steps and stages each tile's ring through HBM (networks whose
+   rings do not fit the chip's workgroup-local memory); AUTO takes RESIDENT
+   when it fits. */
+enum { CORTEX_PLAN_AUTO = 0, CORTEX_PLAN_RESIDENT = 1, CORTEX_PLAN_STREAMED = 2 };
 
 /* A population: `size` consecutive neurons of instance `instance`.
    Populations must be listed grouped by instance, instances ascending. */
@@ -115,6 +121,8 @@ typedef struct {
     int64_t adjoint_steps;    /* longest forward window the adjoint covers */
     int32_t spin_limit_log2;  /* device wait limit, 2^k polls (0 = default 22) */
     int32_t steps_per_sync;   /* FP32: time steps per exchange of spikes, 1..min(d_min, 8) (0 = auto) */
+    int32_t plan_kind;        /* FP32: CORTEX_PLAN_* */
+    int32_t wg_per_cu;        /* FP32 resident plan: workgroups per compute unit, 1, 2, 4, 8 (0 = auto) */
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device
@@ -257,7 +265,9 @@ enum {
     CORTEX_Q_LDS_BYTES = 13,      /* workgroup-local memory per workgroup */
     CORTEX_Q_OFFSET_BYTES = 14,   /* bytes of the per-(source, tile) offset table */
     CORTEX_Q_STEPS_PER_SYNC = 15, /* FP32: time steps per spike exchange chosen at build */
-    CORTEX_Q_RING_BYTES = 16      /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
+    CORTEX_Q_RING_BYTES = 16,     /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
+    CORTEX_Q_PLAN = 17,           /* FP32: CORTEX_PLAN_RESIDENT or CORTEX_PLAN_STREAMED */
+    CORTEX_Q_NPT = 18             /* FP32: neurons per thread */
 };
 /* Passage: the sizes of G (Sec. II-A) and of its decomposition (Eq. 9-10);
    EVENTS counts the edges of the spiking sub-graphs (Eq. 11) delivered.

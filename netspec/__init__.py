@@ -178,11 +178,26 @@ def brunel_112k_alpha(scale_n: float = 1.0, scale_k: float = 1.0) -> NetSpec:
 MC_LAYER_SHARE = (0.3, 0.3, 0.1, 0.3)
 MC_TOTAL = 77169
 MC_TARGET_SYNAPSES = 3.0e8
+MC_INH_RATIO = 1.5
+MC_P_SPREAD = 1.3
 
 
 def microcircuit_instance(total: int = MC_TOTAL, seed: int = 3,
                           target_synapses: float = MC_TARGET_SYNAPSES,
-                          w_mean: float = 87.8, g: float = -4.0) -> Instance:
+                          w_mean: float = 87.8, g: float = -4.0,
+                          inh_ratio: float = MC_INH_RATIO,
+                          p_spread: float = MC_P_SPREAD) -> Instance:
+    """Eight populations (four layers x {E, I}) with a seeded random table of
+    pairwise connection probabilities p[target, source], log-uniform over a
+    range of ratio ``p_spread`` before scaling.  Every target population's row is then
+    scaled so that it expects the same excitatory in-degree K_E, and its
+    inhibitory columns so that |g| K_I = inh_ratio K_E (every population
+    sees the same inhibition-dominated balance, as in the asynchronous
+    irregular state of balanced networks; which population connects to
+    which stays random).  K_E follows from ``target_synapses`` expected
+    synapses in all.  ``total`` scales the populations; keep
+    target_synapses / total fixed for a same-in-degree copy of another
+    size."""
     sizes = []
     for share in MC_LAYER_SHARE:
         n = int(round(total * share))
@@ -190,10 +205,15 @@ def microcircuit_instance(total: int = MC_TOTAL, seed: int = 3,
     sizes[-2] += total - sum(sizes)
     names = ["L23E", "L23I", "L4E", "L4I", "L5E", "L5I", "L6E", "L6I"]
     rng = np.random.default_rng(seed)
-    p = np.exp(rng.uniform(np.log(0.01), np.log(0.3), size=(8, 8)))
+    p = np.exp(rng.uniform(0.0, np.log(p_spread), size=(8, 8)))
     n = np.asarray(sizes, dtype=np.float64)
-    expected = float((p * n[:, None] * n[None, :]).sum())   # p[tgt, src]
-    p = np.clip(p * (target_synapses / expected), 1e-4, 1.0)
+    exc = np.array([s % 2 == 0 for s in range(8)])
+    k_e = target_synapses / (float(n.sum()) * (1.0 + inh_ratio / abs(g)))
+    k_i = inh_ratio * k_e / abs(g)
+    for t in range(8):
+        p[t, exc] *= k_e / float((p[t, exc] * n[exc]).sum())
+        p[t, ~exc] *= k_i / float((p[t, ~exc] * n[~exc]).sum())
+    p = np.clip(p, 0.0, 1.0)
     pops = [Population(nm, sz) for nm, sz in zip(names, sizes)]
     projs = []
     for t in range(8):
@@ -205,16 +225,26 @@ def microcircuit_instance(total: int = MC_TOTAL, seed: int = 3,
     return Instance(pops, projs)
 
 
-# Background Poisson count per step for the microcircuit stand-in, chosen so
-# that the network fires at a few Hz (weights in pA, exp currents).
+# Background Poisson count per neuron and step (weight MC_W_EXT pA, exp
+# currents) of the microcircuit stand-in.  The drive alone would hold the
+# free membrane at lambda/dt * w_ext * tau_syn * tau_m / C = 28 mV, above
+# threshold; the inhibition-dominated recurrence brings every population
+# down to about 3.5 Hz (CV about 0.45) in the CPU reference (a
+# same-in-degree quarter-size copy, 0.5 s), within the 1-10 Hz asked of the
+# stand-in.
 MC_LAMBDA = 0.8
 MC_W_EXT = 87.8
 
 
-def microcircuit_77k(total: int = MC_TOTAL, target_synapses: float = MC_TARGET_SYNAPSES) -> NetSpec:
-    """Eight-population exp-current LIF microcircuit stand-in, FP32 (1 s)."""
+def microcircuit_77k(total: int = MC_TOTAL, target_synapses: Optional[float] = None,
+                     lam: float = MC_LAMBDA) -> NetSpec:
+    """Eight-population exp-current LIF microcircuit stand-in, FP32 (1 s).
+    With ``total`` below 77,169 and no ``target_synapses``, a copy with the
+    same mean in-degree (about 3,900)."""
+    if target_synapses is None:
+        target_synapses = MC_TARGET_SYNAPSES * total / MC_TOTAL
     return NetSpec(model="exp", tau_syn=0.5, weight_unit="native",
-                   poisson_lambda=MC_LAMBDA, w_ext=MC_W_EXT, precision="fp32",
+                   poisson_lambda=lam, w_ext=MC_W_EXT, precision="fp32",
                    v0_lo=0.0, v0_hi=20.0,
                    instances=[microcircuit_instance(total, target_synapses=target_synapses)])
 

@@ -87,10 +87,12 @@ def lib():
         L.orc_export_graph.argtypes = [P, i64p, i64p, f64p, i32p]
         L.orc_get_state.argtypes = [P, f64p, i32p, f64p, f64p]
         L.orc_set_weight.argtypes = [P, C.c_int64, C.c_double]
+        L.orc_set_weights.argtypes = [P, f64p]
         L.orc_reset.argtypes = [P]
         L.orc_run.argtypes = [P, C.c_int64]
         L.orc_get_spikes.argtypes = [P, i64p, i64p]
         L.orc_run_frozen.argtypes = [P, i64p, i64p, C.c_int64, C.c_int64, P, P]
+        L.orc_run_frozen_pre.argtypes = [P, i64p, i64p, C.c_int64, C.c_int64, P]
         L.orc_backward.argtypes = [P, i64p, i64p, C.c_int64, C.c_int64, f64p, f64p,
                                    C.POINTER(C.c_double)]
         _lib = L
@@ -215,6 +217,12 @@ class OracleNet:
     def set_weight(self, e: int, w: float) -> None:
         _err(lib().orc_set_weight(self._p, int(e), float(w)), "set_weight")
 
+    def set_weights(self, w: np.ndarray) -> None:
+        """All weights at once, canonical order."""
+        w = np.ascontiguousarray(w, np.float64)
+        assert w.shape == (self.E,)
+        _err(lib().orc_set_weights(self._p, w), "set_weights")
+
     def reset(self) -> None:
         _err(lib().orc_reset(self._p), "reset")
 
@@ -238,6 +246,15 @@ class OracleNet:
                                   None if xt is None else xt.ctypes.data,
                                   None if vt is None else vt.ctypes.data), "run_frozen")
         return xt, vt
+
+    def run_frozen_pre(self, steps, ids, n_steps: int):
+        """Frozen run; returns the pre-reset membrane potential [n_steps, n_rec]
+        (NaN on refractory steps)."""
+        st = np.ascontiguousarray(steps, np.int64)
+        ii = np.ascontiguousarray(ids, np.int64)
+        vp = np.zeros((n_steps, self.n_rec))
+        _err(lib().orc_run_frozen_pre(self._p, st, ii, len(st), n_steps, vp.ctypes.data), "run_frozen_pre")
+        return vp
 
     def backward(self, steps, ids, n_steps: int, vstar: np.ndarray):
         st = np.ascontiguousarray(steps, np.int64)

@@ -548,6 +548,11 @@ int orc_set_weight(orc_net* n, int64_t e, double w) {
     return 0;
 }
 
+int orc_set_weights(orc_net* n, const double* w) {
+    memcpy(n->w, w, (size_t)n->E * sizeof(double));
+    return 0;
+}
+
 int orc_reset(orc_net* n) {
     memcpy(n->U, n->U0, (size_t)n->N * sizeof(double));
     memcpy(n->y1, n->y10, (size_t)n->N * sizeof(double));
@@ -695,7 +700,8 @@ static int check_raster(const orc_net* n, const int64_t* st, const int64_t* id, 
    Urec = U after each step, mrec = 1 iff the neuron integrated and did not
    spike (the step map depends on the previous state). */
 static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t nspk,
-                       int64_t n_steps, double* xt, double* vt, double* Urec, unsigned char* mrec) {
+                       int64_t n_steps, double* xt, double* vt, double* Urec, unsigned char* mrec,
+                       double* vpre) {
     if (check_raster(n, st, id, nspk)) return -1;
     int64_t q = 0;
     while (q < nspk && st[q] < n->t) q++;
@@ -716,8 +722,11 @@ static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t
             int spk = 0;
             while (qs < q && id[qs] < i) qs++;
             if (qs < q && id[qs] == i) spk = 1;
-            if (spk) { n->U[i] = n->Ur; n->r[i] = n->k.n_ref; }
             int64_t c = n->col_of[i];
+            /* the membrane potential the threshold test of a closed-loop run
+               would see (NaN on refractory steps, which take no test) */
+            if (vpre && c >= 0) vpre[s * n->n_rec + c] = integ ? n->U[i] + n->E_L : NAN;
+            if (spk) { n->U[i] = n->Ur; n->r[i] = n->k.n_ref; }
             if (c >= 0) {
                 if (xt) xt[s * n->n_rec + c] = x;
                 if (vt) vt[s * n->n_rec + c] = n->U[i] + n->E_L;
@@ -733,7 +742,12 @@ static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t
 
 int orc_run_frozen(orc_net* n, const int64_t* st, const int64_t* id, int64_t nspk,
                    int64_t n_steps, double* xt, double* vt) {
-    return frozen_core(n, st, id, nspk, n_steps, xt, vt, NULL, NULL);
+    return frozen_core(n, st, id, nspk, n_steps, xt, vt, NULL, NULL, NULL);
+}
+
+int orc_run_frozen_pre(orc_net* n, const int64_t* st, const int64_t* id, int64_t nspk,
+                       int64_t n_steps, double* vpre) {
+    return frozen_core(n, st, id, nspk, n_steps, NULL, NULL, NULL, NULL, vpre);
 }
 
 /* Reverse-mode gradient with spikes frozen.  Per neuron, with m_n = 1 iff
@@ -758,7 +772,7 @@ int orc_backward(orc_net* n, const int64_t* st, const int64_t* id, int64_t nspk,
     unsigned char* mrec = (unsigned char*)malloc(cells);
     double* g = (double*)malloc(cells * sizeof(double));
     if (!Urec || !mrec || !g) { free(Urec); free(mrec); free(g); set_err("out of memory"); return -1; }
-    if (frozen_core(n, st, id, nspk, T, NULL, NULL, Urec, mrec)) { free(Urec); free(mrec); free(g); return -1; }
+    if (frozen_core(n, st, id, nspk, T, NULL, NULL, Urec, mrec, NULL)) { free(Urec); free(mrec); free(g); return -1; }
     const consts_t* c = &n->k;
     double L = 0.0;
     for (int64_t i = 0; i < n->N; ++i) {

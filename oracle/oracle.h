@@ -93,6 +93,8 @@ int orc_export_graph(const orc_net* net, int64_t* src, int64_t* tgt, double* w, 
 
 /* Overwrite the stored weight of canonical edge e. */
 int orc_set_weight(orc_net* net, int64_t e, double w);
+/* Overwrite every stored weight (w in canonical order, E entries). */
+int orc_set_weights(orc_net* net, const double* w);
 /* Back to the build-time state: step 0, empty rings, spike log cleared. */
 int orc_reset(orc_net* net);
 
@@ -112,6 +114,13 @@ int orc_get_spikes(const orc_net* net, int64_t* steps, int64_t* ids);
    synaptic input consumed at each step, v = membrane potential after it. */
 int orc_run_frozen(orc_net* net, const int64_t* r_steps, const int64_t* r_ids,
                    int64_t n_spk, int64_t n_steps, double* x_trace, double* v_trace);
+
+/* Frozen raster as orc_run_frozen; vpre [n_steps][n_rec] receives the
+   membrane potential after each step's update and before any reset, i.e.
+   the value a closed-loop run compares with the threshold (NaN on
+   refractory steps, which take no threshold test). */
+int orc_run_frozen_pre(orc_net* net, const int64_t* r_steps, const int64_t* r_ids,
+                       int64_t n_spk, int64_t n_steps, double* vpre);
 
 /* Gradient of L = sum_b 1/(N_b T) sum_{i in b, n < T} (V_i(n) - V*_i(n))^2
    with respect to every stored weight (canonical order), spikes frozen to

@@ -18,11 +18,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcortex.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cortex.h")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
 Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
          STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
-         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16)
+         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16, PLAN=17, NPT=18)
+PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAMED = 0, 1, 2
+_PLAN = {"auto": PLAN_AUTO, "resident": PLAN_RESIDENT, "streamed": PLAN_STREAMED}
 
 
 class CortexError(RuntimeError):
@@ -53,7 +55,8 @@ class cortex_spec(C.Structure):
                 ("n_projs", C.c_int32), ("projs", C.POINTER(cortex_proj)),
                 ("tile_size", C.c_int32), ("block_size", C.c_int32), ("record_steps", C.c_int64),
                 ("ckpt_every", C.c_int32), ("adjoint_steps", C.c_int64),
-                ("spin_limit_log2", C.c_int32), ("steps_per_sync", C.c_int32)]
+                ("spin_limit_log2", C.c_int32), ("steps_per_sync", C.c_int32),
+                ("plan_kind", C.c_int32), ("wg_per_cu", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -142,8 +145,9 @@ _UNIT = {"native": 0, "psp_mV": 1}
 
 def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 0,
               ckpt_every: int = 0, adjoint_steps: int = 0, spin_limit_log2: int = 0,
-              steps_per_sync: int = 0):
+              steps_per_sync: int = 0, plan: str = "auto", wg_per_cu: int = 0):
     """Marshal a network description (netspec.NetSpec) into cortex_spec.
+    ``plan``: "auto", "resident" or "streamed" (FP32 launch plan).
 
     Returns (spec, keepalive)."""
     pops, projs = [], []
@@ -179,6 +183,8 @@ def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 
     s.adjoint_steps = adjoint_steps
     s.spin_limit_log2 = spin_limit_log2
     s.steps_per_sync = steps_per_sync
+    s.plan_kind = _PLAN[plan]
+    s.wg_per_cu = wg_per_cu
     return s, (pa, qa)
 
 

@@ -20,6 +20,7 @@ SOURCES = [
     ("verify.hip", ["-ffp-contract=off"]),
     ("step.hip", []),
     ("adjoint.hip", []),
+    ("stream.hip", []),
 ]
 
 ARCH = os.environ.get("CORTEX_OFFLOAD_ARCH", "gfx950")

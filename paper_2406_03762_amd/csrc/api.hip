@@ -206,6 +206,10 @@ static void validate(const cortex_spec* s) {
     require(s->tile_size >= 0 && s->record_steps >= 0 && s->ckpt_every >= 0 && s->adjoint_steps >= 0 &&
                 s->spin_limit_log2 >= 0 && s->spin_limit_log2 <= 40 && s->steps_per_sync >= 0,
             CORTEX_EINVAL, "negative planning field");
+    require(s->plan_kind >= CORTEX_PLAN_AUTO && s->plan_kind <= CORTEX_PLAN_STREAMED, CORTEX_EINVAL,
+            "unknown plan kind");
+    require(s->wg_per_cu == 0 || s->wg_per_cu == 1 || s->wg_per_cu == 2 || s->wg_per_cu == 4 || s->wg_per_cu == 8,
+            CORTEX_EINVAL, "wg_per_cu must be 0, 1, 2, 4 or 8");
     require(s->n_projs >= 0 && (s->n_projs == 0 || s->projs), CORTEX_EINVAL, "projection list is NULL");
     int prev = 0;
     std::vector<int> seen(s->n_instances, 0);
@@ -354,6 +358,49 @@ static int pow2_at_least(int x) {
     return p;
 }
 
+// Tiles of T_b consecutive targets per instance b (the last one shorter):
+// the partition of Eq. 9-10, one indegree sub-graph per tile.
+static void make_tiles(cortex_net* n, const std::vector<int32_t>& Tb) {
+    n->inst_T = Tb;
+    n->n_tiles = 0;
+    n->inst_tile0.assign(n->n_inst, 0);
+    n->inst_ntiles.assign(n->n_inst, 0);
+    n->inst_offbase.assign(n->n_inst, 0);
+    n->tile_start.clear();
+    n->tile_size.clear();
+    n->tile_inst.clear();
+    uint64_t off = 0;
+    n->ntb_max = 1;
+    for (int b = 0; b < n->n_inst; ++b) {
+        const int Tb_ = Tb[b];
+        const int nt = (int)((n->inst_N[b] + Tb_ - 1) / Tb_);
+        n->inst_tile0[b] = n->n_tiles;
+        n->inst_ntiles[b] = nt;
+        n->inst_offbase[b] = off;
+        off += (uint64_t)n->inst_N[b] * (nt + 1);
+        for (int t = 0; t < nt; ++t) {
+            n->tile_start.push_back(n->inst_n0[b] + (int64_t)t * Tb_);
+            n->tile_size.push_back((int32_t)std::min<int64_t>(Tb_, n->inst_N[b] - (int64_t)t * Tb_));
+            n->tile_inst.push_back(b);
+        }
+        n->n_tiles += nt;
+        n->ntb_max = std::max(n->ntb_max, nt);
+    }
+}
+
+// Mean in-degree of every instance (expected synapses per target).
+static std::vector<double> mean_indegree(const cortex_net* n) {
+    std::vector<double> K(n->n_inst, 0.0);
+    for (const auto& B : n->blocks) {
+        const double per_tgt = B.rule == CORTEX_RULE_FIXED_INDEGREE
+                                   ? (double)B.k
+                                   : (B.all_pairs ? 1.0 : std::ldexp((double)B.thr_p, -64)) * (double)B.n_src;
+        K[B.instance] += per_tgt * (double)B.n_tgt;
+    }
+    for (int b = 0; b < n->n_inst; ++b) K[b] = std::max(1.0, K[b] / (double)n->inst_N[b]);
+    return K;
+}
+
 // Tile sizes.  Every tile's workgroup must be resident at once and its input
 // ring must fit the workgroup-local memory.  Instances of different sizes get
 // different tile sizes so that every tile holds about the same number of
@@ -410,7 +457,9 @@ static void plan_tiles(cortex_net* n) {
     } else {
         bool found = false;
         const int w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
-        for (int per_cu = 1; per_cu <= 8 && !found; per_cu *= 2) {
+        const int pc_lo = n->spec.wg_per_cu > 0 ? n->spec.wg_per_cu : 1;
+        const int pc_hi = n->spec.wg_per_cu > 0 ? n->spec.wg_per_cu : 8;
+        for (int per_cu = pc_lo; per_cu <= pc_hi && !found; per_cu *= 2) {
             const int64_t cap = (int64_t)n_cu * per_cu;
             const int bs_top = BS ? BS : std::min(1024, std::max(256, thr_cu / per_cu));
             for (int bs = bs_top; bs >= (BS ? BS : 256) && !found; bs /= 2) {
@@ -471,35 +520,80 @@ static void plan_tiles(cortex_net* n) {
     require(n->NPT <= 2 || (n->NPT == 4 && BS == 512), CORTEX_EINVAL,
             "tile_size must be at most 2 x block_size (4 x for block_size 512)");
     n->T = T;
-    n->inst_T = Tb;
     n->BS = BS;
     n->chunk = chunk;
-    n->n_tiles = 0;
-    n->inst_tile0.assign(n->n_inst, 0);
-    n->inst_ntiles.assign(n->n_inst, 0);
-    n->inst_offbase.assign(n->n_inst, 0);
-    n->tile_start.clear();
-    n->tile_size.clear();
-    n->tile_inst.clear();
-    uint64_t off = 0;
-    for (int b = 0; b < n->n_inst; ++b) {
-        const int Tb_ = Tb[b];
-        const int nt = (int)((n->inst_N[b] + Tb_ - 1) / Tb_);
-        n->inst_tile0[b] = n->n_tiles;
-        n->inst_ntiles[b] = nt;
-        n->inst_offbase[b] = off;
-        off += (uint64_t)n->inst_N[b] * (nt + 1);
-        for (int t = 0; t < nt; ++t) {
-            n->tile_start.push_back(n->inst_n0[b] + (int64_t)t * Tb_);
-            n->tile_size.push_back((int32_t)std::min<int64_t>(Tb_, n->inst_N[b] - (int64_t)t * Tb_));
-            n->tile_inst.push_back(b);
-        }
-        n->n_tiles += nt;
-    }
-    n->ntb_max = ntb_max_of(Tb);
+    make_tiles(n, Tb);
     n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk, n->ring_bytes);
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
     n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
+}
+
+// Streamed plan: no co-residency, so tiles are as large as one tile's ring
+// and work arrays allow in the workgroup-local memory share of `wg_per_cu`
+// workgroups (T a multiple of 4, so that rings move as 16-byte words).  The
+// launch order of the tiles: with tiles of one size, XCD-aware (the
+// workgroups the hardware places on one XCD take a contiguous run of tiles,
+// whose segments of a source are adjacent in memory and share its L2);
+// otherwise the largest expected synapse count first (longest-processing-
+// time order for the load balance of Sec. III-A).
+static void plan_stream(cortex_net* n) {
+    const cortex_spec& s = n->spec;
+    hipDeviceProp_t prop;
+    CX_HIP(hipGetDeviceProperties(&prop, n->device));
+    const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+    const int per_cu = s.wg_per_cu > 0 ? s.wg_per_cu : 1;
+    n->W = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(n->dmin, 8);
+    n->R = n->dmax - n->dmin + n->W;
+    n->H = pow2_at_least(n->dmin + 2 * n->W);
+    n->ring_bytes = 4;
+    n->chunk = 512;
+    int Tmax = 0;
+    for (int t = 4; t <= 4096; t += 4)
+        if (stream_lds_bytes(n->R, t, n->W, n->chunk) * per_cu <= lds_cu) Tmax = t;
+    require(Tmax >= 4, CORTEX_EUNSUPPORTED, "delay range too long for a streamed tile's input ring");
+    if (s.tile_size > 0) {
+        require(((s.tile_size + 3) & ~3) <= Tmax, CORTEX_EUNSUPPORTED,
+                "tile_size too large for the streamed plan's workgroup-local memory");
+        Tmax = s.tile_size;
+    }
+    int64_t Nmax = 1;
+    for (int b = 0; b < n->n_inst; ++b) Nmax = std::max(Nmax, n->inst_N[b]);
+    std::vector<int32_t> Tb(n->n_inst);
+    for (int b = 0; b < n->n_inst; ++b) Tb[b] = (int32_t)std::min<int64_t>(Tmax, n->inst_N[b]);
+    const int Tm = *std::max_element(Tb.begin(), Tb.end());
+    n->T = (Tm + 3) & ~3;
+    int BS = s.block_size ? s.block_size : (n->T >= 1024 ? 1024 : (n->T >= 512 ? 512 : 256));
+    int npt = (n->T + BS - 1) / BS;
+    if (npt == 3) npt = 4;
+    require(npt <= 4, CORTEX_EINVAL, "tile_size must be at most 4 x block_size");
+    n->BS = BS;
+    n->NPT = npt;
+    make_tiles(n, Tb);
+    n->lds_bytes = stream_lds_bytes(n->R, n->T, n->W, n->chunk);
+    require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "streamed tile does not fit workgroup-local memory");
+    const int meta = (uint64_t)n->T * (uint64_t)n->R <= 65536 ? 2 : 4;
+    const int w_bytes = (s.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
+    require(stream_occupancy(s.model, meta, w_bytes, n->NPT, n->BS, n->lds_bytes) >= 1, CORTEX_EUNSUPPORTED,
+            "streamed kernel does not fit a compute unit with this plan");
+    // launch order
+    const auto K = mean_indegree(n);
+    std::vector<double> load(n->n_tiles);
+    for (int t = 0; t < n->n_tiles; ++t) load[t] = K[n->tile_inst[t]] * n->tile_size[t];
+    const bool uniform = *std::max_element(load.begin(), load.end()) <= 1.05 * *std::min_element(load.begin(), load.end());
+    std::vector<int32_t> order(n->n_tiles);
+    if (uniform) {
+        const int n8 = n->n_tiles / 8, rem = n->n_tiles % 8;
+        for (int bid = 0; bid < n->n_tiles; ++bid) {
+            const int x = bid % 8, r = bid / 8;
+            order[bid] = x * n8 + std::min(x, rem) + r;
+        }
+    } else {
+        for (int t = 0; t < n->n_tiles; ++t) order[t] = t;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
+    }
+    n->d_order = dev_alloc_t<int32_t>(n, n->n_tiles);
+    upload(n, n->d_order, order);
+    n->xcd_map = 0;
 }
 
 static void upload_tables_fp32(cortex_net* n) {
@@ -539,8 +633,15 @@ static void alloc_state_fp32(cortex_net* n) {
     n->d_y2 = dev_alloc_t<float>(n, N);
     n->d_r = dev_alloc_t<int32_t>(n, N);
     n->d_ring = dev_alloc(n, (size_t)n->n_tiles * n->R * n->T * n->ring_bytes);
-    // (+8 words: a reader fetches a few id words past a record without bounds checks)
-    n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
+    if (n->plan_kind == CORTEX_PLAN_STREAMED) {
+        n->d_spk_cnt = dev_alloc_t<uint32_t>(n, (size_t)n->H * n->n_inst);
+        n->d_spk_ids = dev_alloc_t<uint32_t>(n, (size_t)n->H * n->N);
+        n->d_clock = dev_alloc_t<int64_t>(n, 2);
+        n->use_graph = true;
+    } else {
+        // (+8 words: a reader fetches a few id words past a record without bounds checks)
+        n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
+    }
     n->log_steps = std::max<int64_t>(0, n->spec.record_steps);
     if (n->ckpt > 0) n->log_steps = std::max(n->log_steps, n->adj_steps);   // the adjoint replays the raster
     n->d_log_cnt = dev_alloc_t<uint32_t>(n, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles);
@@ -556,6 +657,16 @@ static void alloc_state_fp32(cortex_net* n) {
     n->d_err = dev_alloc_t<int32_t>(n, 4);
 }
 
+// Forget the captured window graph (its arguments hold the log window and
+// the fixed-point scale).
+static void drop_graph(cortex_net* n) {
+    if (n->graph_exec) {
+        (void)hipStreamSynchronize(n->graph_stream);
+        (void)hipGraphExecDestroy(n->graph_exec);
+        n->graph_exec = nullptr;
+    }
+}
+
 static void zero_dynamic_fp32(cortex_net* n) {
     const int64_t N = n->N;
     CX_HIP(hipMemcpyAsync(n->d_U, n->d_U0, N * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
@@ -563,7 +674,14 @@ static void zero_dynamic_fp32(cortex_net* n) {
     dev_zero(n, n->d_y2, N * sizeof(float));
     dev_zero(n, n->d_r, N * sizeof(int32_t));
     dev_zero(n, n->d_ring, (size_t)n->n_tiles * n->R * n->T * n->ring_bytes);
-    dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
+    if (n->plan_kind == CORTEX_PLAN_STREAMED) {
+        dev_zero(n, n->d_spk_cnt, (size_t)n->H * n->n_inst * sizeof(uint32_t));
+        dev_zero(n, n->d_clock, 2 * sizeof(int64_t));
+        n->clock_parity = 0;
+        drop_graph(n);
+    } else {
+        dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
+    }
     dev_zero(n, n->d_log_pos, n->n_tiles * sizeof(uint64_t));
     dev_zero(n, n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * n->n_tiles * sizeof(uint32_t));
     dev_zero(n, n->d_events, n->n_tiles * sizeof(uint64_t));
@@ -639,24 +757,35 @@ static void build(cortex_net* n) {
         // fit workgroup-local memory
         const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
         require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
-        // 64-bit input sums first; 32-bit sums (scaled by the largest exact
-        // input bound of any neuron) when the 64-bit rings cannot fit
         bool planned = false;
-        for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
-            n->ring_bytes = rb;
-            for (int W = W0;; W = std::max(1, W / 2)) {
-                n->W = W;
-                n->R = dmax - dmin + n->W;
-                n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
-                try {
-                    plan_tiles(n);
-                    planned = true;
-                    break;
-                } catch (const Error& e) {
-                    if (e.status != CORTEX_EUNSUPPORTED || (rb == 4 && (W == 1 || s.steps_per_sync > 0))) throw;
-                    if (W == 1 || s.steps_per_sync > 0) break;
+        if (s.plan_kind != CORTEX_PLAN_STREAMED) {
+            // 64-bit input sums first; 32-bit sums (scaled by the largest
+            // exact input bound of any neuron) when the 64-bit rings cannot fit
+            n->plan_kind = CORTEX_PLAN_RESIDENT;
+            for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
+                n->ring_bytes = rb;
+                for (int W = W0;; W = std::max(1, W / 2)) {
+                    n->W = W;
+                    n->R = dmax - dmin + n->W;
+                    n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+                    try {
+                        plan_tiles(n);
+                        planned = true;
+                        break;
+                    } catch (const Error& e) {
+                        const bool last = rb == 4 && (W == 1 || s.steps_per_sync > 0);
+                        if (e.status != CORTEX_EUNSUPPORTED || (last && s.plan_kind == CORTEX_PLAN_RESIDENT))
+                            throw;
+                        if (W == 1 || s.steps_per_sync > 0) break;
+                    }
                 }
             }
+        }
+        if (!planned) {
+            n->plan_kind = CORTEX_PLAN_STREAMED;
+            require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "the adjoint needs the resident plan (the network is too "
+                                                         "large for workgroup-local input rings)");
+            plan_stream(n);
         }
         n->fx = fixed_point_bits(n);
         n->fx_shift = fixed_point_shift(n, n->fx);
@@ -672,12 +801,14 @@ static void build(cortex_net* n) {
         init_state(n);
         zero_dynamic_fp32(n);
         save_checkpoint(n, 0);
-        const int per_cu = step_max_blocks_per_cu(n);
-        hipDeviceProp_t prop;
-        CX_HIP(hipGetDeviceProperties(&prop, n->device));
-        require((int64_t)per_cu * prop.multiProcessorCount >= n->n_tiles, CORTEX_EUNSUPPORTED,
-                "not every tile's workgroup can be resident at once (" + std::to_string(n->n_tiles) +
-                    " tiles, " + std::to_string(per_cu) + " per CU)");
+        if (n->plan_kind == CORTEX_PLAN_RESIDENT) {
+            const int per_cu = step_max_blocks_per_cu(n);
+            hipDeviceProp_t prop;
+            CX_HIP(hipGetDeviceProperties(&prop, n->device));
+            require((int64_t)per_cu * prop.multiProcessorCount >= n->n_tiles, CORTEX_EUNSUPPORTED,
+                    "not every tile's workgroup can be resident at once (" + std::to_string(n->n_tiles) +
+                        " tiles, " + std::to_string(per_cu) + " per CU)");
+        }
     }
     n->step = 0;
     n->log_step0 = 0;
@@ -794,6 +925,10 @@ void restore_checkpoint(cortex_net* n, int k) {
 // first step.
 static void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
                          uint64_t frz_n, float* x_trace, float* v_trace) {
+    if (n->plan_kind == CORTEX_PLAN_STREAMED) {
+        launch_stream_fp32(n, n_steps, frz_ids, frz_ptr, frz_n, x_trace, v_trace);
+        return;
+    }
     const int64_t first = n->step;
     int64_t left = n_steps;
     while (left > 0) {
@@ -956,7 +1091,8 @@ int cortex_backward(cortex_net* n, const float* vstar, float* grad_w, double* lo
     CX_API_BEGIN
     require_net(n);
     require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "the adjoint runs in FP32 mode");
-    require(n->ckpt > 0, CORTEX_ESTATE, "adjoint not enabled (ckpt_every = 0 at build)");
+    require(n->ckpt > 0 && n->plan_kind == CORTEX_PLAN_RESIDENT, CORTEX_ESTATE,
+            "adjoint not enabled (ckpt_every = 0 at build)");
     require(vstar != nullptr && grad_w != nullptr && loss != nullptr, CORTEX_EINVAL,
             "vstar, grad_w and loss must not be NULL");
     check_device_flag(n);
@@ -974,6 +1110,7 @@ int cortex_set_weights(cortex_net* n, const float* w_canonical) {
     require(n->d_canon != nullptr, CORTEX_ESTATE, "setting weights needs ckpt_every > 0 (canonical order)");
     require(n->step == 0, CORTEX_ESTATE, "weights are set at step 0 (after the build or cortex_reset)");
     check_device_flag(n);
+    drop_graph(n);
     set_weights_fp32(n, w_canonical);
     // fixed-point scale from the exact bound of the new weights
     double wmax = 0.0;
@@ -1135,6 +1272,8 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
         }
         case CORTEX_Q_STEPS_PER_SYNC: *value = fp64 ? 1 : n->W; break;
         case CORTEX_Q_RING_BYTES: *value = fp64 ? 8 : n->ring_bytes; break;
+        case CORTEX_Q_PLAN: *value = fp64 ? 0 : n->plan_kind; break;
+        case CORTEX_Q_NPT: *value = fp64 ? 0 : n->NPT; break;
         case CORTEX_Q_EVENTS:
         case CORTEX_Q_SPIKES: {
             require(!n->failed, CORTEX_ESTATE, "network failed earlier");
@@ -1158,7 +1297,12 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
 
 void cortex_destroy(cortex_net* n) {
     if (!n) return;
-    if (n->stream || true) (void)hipStreamSynchronize(n->stream);
+    (void)hipStreamSynchronize(n->stream);
+    if (n->graph_stream) (void)hipStreamSynchronize(n->graph_stream);
+    if (n->graph_exec) (void)hipGraphExecDestroy(n->graph_exec);
+    if (n->fence_in) (void)hipEventDestroy(n->fence_in);
+    if (n->fence_out) (void)hipEventDestroy(n->fence_out);
+    if (n->graph_stream) (void)hipStreamDestroy(n->graph_stream);
     release(n, n->scratch);
     release(n, n->bufs);
     delete n;

@@ -100,6 +100,7 @@ struct cortex_net {
     int meta_bytes = 2, w_bytes = 4;    // record: (delay - dmin) T + target in tile
     size_t lds_bytes = 0;
     int xcd_map = 0;
+    int plan_kind = CORTEX_PLAN_RESIDENT;   // resolved plan (never AUTO)
     int64_t step = 0;
     std::vector<cortex::GenBlock> blocks;
 
@@ -141,6 +142,17 @@ struct cortex_net {
     uint64_t* d_events = nullptr;      // [n_tiles]
     uint64_t* d_spikes = nullptr;      // [n_tiles]
     int32_t* d_err = nullptr;          // [4]
+    // streamed plan: per-step spike lists, device clock, workgroup order
+    uint32_t* d_spk_cnt = nullptr;     // [H][n_inst]
+    uint32_t* d_spk_ids = nullptr;     // [H][N]
+    int64_t* d_clock = nullptr;        // [2]
+    int32_t* d_order = nullptr;        // [n_tiles]
+    int clock_parity = 0;
+    bool use_graph = true;
+    hipGraphExec_t graph_exec = nullptr;   // kGraphWindows window launches
+    hipStream_t graph_stream = nullptr;    // library stream the graph is captured on and replayed on
+    hipEvent_t fence_in = nullptr, fence_out = nullptr;   // order it after / before the caller's stream
+    int64_t graph_log_step0 = -1, graph_log_steps = -1;
     // initial state copy (reset / adjoint)
     float *d_U0 = nullptr;
     // FP64 verify graph and state
@@ -201,6 +213,12 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
 void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const uint64_t* ptr,
                uint64_t n_ids);
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_bytes);
+// stream.hip: window launches of the streamed plan
+constexpr int kGraphWindows = 32;   // window launches per captured graph (even)
+size_t stream_lds_bytes(int R, int T, int W, int chunk);
+int stream_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds);
+void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
+                        uint64_t frz_n, float* x_trace, float* v_trace, uint8_t* m_trace = nullptr);
 int step_max_blocks_per_cu(cortex_net* n);
 // Resident workgroups per CU of the step kernel variant for a model, record
 // format, neurons per thread, workgroup size and LDS bytes (0 if none fit).

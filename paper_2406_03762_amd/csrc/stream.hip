@@ -1,0 +1,513 @@
+// Streamed FP32 step: one kernel launch per window of W <= d_min steps over
+// all tiles, for networks whose input rings do not all fit the workgroup-local
+// memory of the chip at once (e.g. two million neurons with 26 delay values:
+// 240 MB of rings against 40 MB of LDS).
+//
+// Each workgroup takes one tile for one window: it stages the tile's input
+// ring (R slots x T targets, 32-bit fixed point) and neuron state from HBM,
+// delivers the spikes of steps [t0 - d_min, t0 - d_min + W) of its instance
+// into the ring (the same segment layout as the persistent kernel: the
+// spiking part, Eq. 11, of the tile's indegree sub-graph, Eq. 5), advances
+// its neurons through the W steps, appends their spikes to the per-step
+// spike lists and writes ring and state back.  The tile is still the only
+// writer of its targets' input (Sec. III-B), so delivery needs no global
+// atomic; the kernel boundary replaces the persistent kernel's spin waits
+// (every spike a window delivers was emitted by an earlier launch, as
+// W <= d_min), and a run is a sequence of window launches that a captured
+// HIP graph replays.
+//
+// Per step and instance, the spike list has one counter (spikes appended so
+// far, one atomic reservation per tile and step) and room for every neuron of
+// the instance; H >= d_min + 2 W list slots cycle.  The first workgroup of a
+// launch clears the counters of the next window's slots, which no workgroup
+// of the launch reads or writes.
+//
+// The window start t0 lives in device memory (clock[parity]); the first
+// workgroup writes the next window's start into clock[1 - parity], so a
+// captured sequence of launches can be replayed without new arguments.
+#include <algorithm>
+#include <cmath>
+
+#include "deliver.hpp"
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cortex {
+namespace {
+
+constexpr int kMaxThr = 32;   // Poisson table entries in kernel arguments
+constexpr int kMaxW = 8;      // steps per window
+
+struct StreamArgs {
+    const int32_t* order;          // [n_tiles] tile of each workgroup
+    const int32_t* tile_inst;
+    const int32_t* tile_size;
+    const int32_t* inst_tile0;
+    const int32_t* inst_ntiles;
+    const int32_t* inst_T;
+    const int64_t* inst_n0;
+    const uint64_t* inst_offbase;
+    const uint64_t* row_start;
+    const uint32_t* off_rel;
+    const void* meta;
+    const void* w;
+    float* U;
+    float* y1;
+    float* y2;
+    int32_t* r;
+    int32_t* ring;                 // [n_tiles][R][T] 32-bit fixed-point sums
+    uint32_t* spk_cnt;             // [H][n_inst] spikes per step and instance
+    uint32_t* spk_ids;             // [H][N] their ids (instance b at offset inst_n0[b])
+    int64_t* clock;                // [2] window starts
+    uint32_t* log_cnt;
+    uint32_t* log_ids;
+    const uint64_t* log_base;
+    uint64_t* log_pos;
+    uint64_t* events;
+    uint64_t* spikes;
+    const uint32_t* frz_ids;
+    const uint64_t* frz_ptr;       // [(step - frz_step0) * n_tiles + tile]
+    uint64_t frz_n;
+    int64_t frz_step0;
+    float* x_trace;                // [(step - trace_step0) * N + neuron]
+    float* v_trace;
+    uint8_t* m_trace;
+    int64_t trace_step0;
+    int64_t log_step0, log_steps, N;
+    int parity, wn;
+    int n_tiles, n_inst, T, R, dmin, H, W, chunk, n_ref, n_thr;
+    float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
+    float fxw_scale;
+    double fx_inv;
+    uint64_t seed;
+    uint32_t thr[kMaxThr];
+};
+
+}  // namespace
+
+// Bytes of workgroup-local memory of the streamed kernel; the kernel carves
+// its arrays in this order.
+size_t stream_lds_bytes(int R, int T, int W, int chunk) {
+    size_t b = (size_t)chunk * 16;                 // s_sg: segment descriptors
+    b += (size_t)R * T * 4;                        // ring
+    b += (size_t)(chunk + 1) * 4;                  // s_len: segment prefix
+    b += ((size_t)W * T * 2 + 3) & ~(size_t)3;     // s_spk: local ids of each step's spikes
+    b += (size_t)T * 4;                            // s_frz: frozen-spike bits
+    b += (size_t)kDeliverBlk * 4;                  // s_blk
+    b += (size_t)kMaxThr * 4;                      // s_thr
+    b += (size_t)(kMaxW + 1) * 4;                  // s_pc: spikes per delivered step (prefix)
+    b += (size_t)kMaxW * 4;                        // s_cnt: spikes per updated step
+    b += (size_t)20 * 4 + 20 * 4 + 8 * 4;          // s_wsum, s_kw, s_misc
+    return (b + 15) & ~(size_t)15;
+}
+
+namespace {
+
+template <int MODEL, typename META, bool WBF16, int NPT>
+__global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
+    const int tile = a.order[blockIdx.x];
+    const int b = a.tile_inst[tile];
+    const int ntb = a.inst_ntiles[b];
+    const int tl = tile - a.inst_tile0[b];
+    const int64_t n0b = a.inst_n0[b];
+    const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
+    const int tsz = a.tile_size[tile];
+    const uint64_t offb = a.inst_offbase[b];
+    const int T = a.T, R = a.R, H = a.H, CH = a.chunk;
+    const uint32_t RT = (uint32_t)R * (uint32_t)T;
+    const int64_t t0 = a.clock[a.parity];
+    const int wn = a.wn;
+
+    uint4* s_sg = reinterpret_cast<uint4*>(lds_raw);                        // CH
+    int32_t* ring = reinterpret_cast<int32_t*>(s_sg + CH);                  // R * T
+    uint32_t* s_len = reinterpret_cast<uint32_t*>(ring + (size_t)R * T);    // CH + 1
+    uint16_t* s_spk = reinterpret_cast<uint16_t*>(s_len + CH + 1);          // W * T
+    uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_spk + (size_t)a.W * T + ((a.W * T) & 1));   // T
+    uint32_t* s_blk = s_frz + T;                                            // kDeliverBlk
+    uint32_t* s_thr = s_blk + kDeliverBlk;                                  // kMaxThr
+    uint32_t* s_pc = s_thr + kMaxThr;                                       // kMaxW + 1
+    int* s_cnt = reinterpret_cast<int*>(s_pc + kMaxW + 1);                  // kMaxW
+    uint32_t* s_wsum = reinterpret_cast<uint32_t*>(s_cnt + kMaxW);          // 20
+    int* s_kw = reinterpret_cast<int*>(s_wsum + 20);                        // 20
+    int* s_misc = s_kw + 20;                                                // 8
+
+    if (blockIdx.x == 0) {
+        // the next window's start, and its spike-list counters cleared
+        if (tid == 0) a.clock[1 - a.parity] = t0 + wn;
+        for (int i = tid; i < a.W * a.n_inst; i += bs) {
+            const int64_t n = t0 + wn + i / a.n_inst;
+            a.spk_cnt[(size_t)(n & (H - 1)) * a.n_inst + (i % a.n_inst)] = 0u;
+        }
+    }
+    // ------------------------------------------------------------ stage in
+    {
+        const int4* src = reinterpret_cast<const int4*>(a.ring + (size_t)tile * R * T);
+        int4* dst = reinterpret_cast<int4*>(ring);
+        for (int i = tid; i < (R * T) / 4; i += bs) dst[i] = src[i];
+        for (int i = ((R * T) & ~3) + tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
+    }
+    float U[NPT], Y1[NPT], Y2[NPT];
+    int RF[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = tid + k * bs;
+        U[k] = Y1[k] = Y2[k] = 0.f;
+        RF[k] = 0;
+        if (li < tsz) {
+            U[k] = a.U[g0 + li];
+            RF[k] = a.r[g0 + li];
+            if (MODEL != CORTEX_MODEL_DELTA) Y1[k] = a.y1[g0 + li];
+            if (MODEL == CORTEX_MODEL_ALPHA) Y2[k] = a.y2[g0 + li];
+        }
+    }
+    for (int i = tid; i < T; i += bs) s_frz[i] = 0;
+    if (tid < kMaxThr) s_thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xFFFFFFFFu;
+    if (tid < kMaxW) s_cnt[tid] = 0;
+    // spikes of the delivered steps [q_lo, q_hi) of this instance
+    const int64_t q_hi = t0 - a.dmin + wn;
+    const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
+    const int nq = (int)max((int64_t)0, q_hi - q_lo);
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int qi = 0; qi < nq; ++qi) {
+            s_pc[qi] = run;
+            run += a.spk_cnt[(size_t)((q_lo + qi) & (H - 1)) * a.n_inst + b];
+        }
+        s_pc[nq] = run;
+    }
+    // frozen spikes of the updated steps (replay)
+    if (a.frz_ptr) {
+        for (int si = 0; si < wn; ++si) {
+            const int64_t n = t0 + si;
+            const size_t at = (size_t)(n - a.frz_step0) * a.n_tiles + tile;
+            const uint64_t f0 = min(a.frz_ptr[at], a.frz_n), f1 = min(a.frz_ptr[at + 1], a.frz_n);
+            for (uint64_t q = f0 + tid; q < f1; q += bs) {
+                const int64_t li = (int64_t)a.frz_ids[q] - g0;
+                if (li >= 0 && li < tsz) atomicOr(&s_frz[li], 1u << si);
+            }
+        }
+    }
+    __syncthreads();
+    // ------------------------------------------------------------ deliver
+    const uint32_t S = s_pc[nq];
+    const int base_slot = (int)((q_lo + a.dmin) % R);
+    uint64_t ev = 0;
+    for (uint32_t c0 = 0; c0 < S; c0 += CH) {
+        const int cn = (int)min((uint32_t)CH, S - c0);
+        for (int k = tid; k < cn; k += bs) {
+            const uint32_t kk = c0 + k;
+            int qi = 0;
+            while (qi + 1 < nq && s_pc[qi + 1] <= kk) ++qi;
+            const uint32_t j = a.spk_ids[(size_t)((q_lo + qi) & (H - 1)) * a.N + n0b + (kk - s_pc[qi])];
+            const uint64_t rs = a.row_start[j];
+            const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
+            const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
+            const uint64_t beg = rs + o0;
+            s_sg[k] = make_uint4(o1 - o0, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
+            s_len[k] = o1 - o0;
+        }
+        __syncthreads();
+        const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
+        wave_runs(s_len, s_kw, cn, EL, n_waves, tid, bs);
+        __syncthreads();
+        if (EL >= 32u * (uint32_t)cn)
+            deliver_long<META, WBF16, int32_t>(s_sg, ring, s_kw[wave], s_kw[wave + 1], lane, a.meta, a.w,
+                                               base_slot, (uint32_t)T, RT, a.fxw_scale);
+        else
+            deliver_short<META, WBF16, int32_t>(s_sg, s_len, s_blk, ring, cn, EL, tid, bs, lane, wave, n_waves,
+                                                a.meta, a.w, base_slot, (uint32_t)T, RT, a.fxw_scale);
+        ev += EL;
+        __syncthreads();
+    }
+    // ------------------------------------------------------------ update
+    const int slot0 = (int)(t0 % R);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = tid + k * bs;
+        if (li < tsz) {
+            const uint32_t frz = s_frz[li];
+            const uint64_t nl = (uint64_t)(g0 - n0b + li);   // instance-local neuron
+            Philox4 pw{};
+            int slot = slot0;
+            for (int si = 0; si < wn; ++si, slot = (slot + 1 == R) ? 0 : slot + 1) {
+                const int64_t n = t0 + si;
+                const float x = (float)((double)ring[slot * T + li] * a.fx_inv);
+                ring[slot * T + li] = 0;
+                // Poisson count: 32-bit half (n & 1) of word (n & 7) >> 1 of
+                // the block (neuron, n >> 3, 0, Poisson tag)
+                if (si == 0 || (n & 7) == 0)
+                    pw = philox(nl, (uint64_t)(n >> 3), 0, kTagPoisson, a.seed, (uint64_t)b);
+                const uint64_t word = pw.v[(n & 7) >> 1];
+                const uint32_t u = (n & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+                int kc = 0;
+#pragma unroll
+                for (int h = kMaxThr; h > 0; h >>= 1)
+                    if (kc + h <= a.n_thr && s_thr[kc + h - 1] <= u) kc += h;
+                const float inp = x + a.w_ext * (float)kc;
+                const bool integ = RF[k] == 0;
+                float u_new;
+                if (!integ) {
+                    RF[k] -= 1;
+                    u_new = a.Ur;
+                } else if (MODEL == CORTEX_MODEL_DELTA) {
+                    u_new = a.P22 * U[k] + a.P20Ie + inp;
+                } else if (MODEL == CORTEX_MODEL_EXP) {
+                    u_new = a.P22 * U[k] + a.P21 * Y1[k] + a.P20Ie;
+                } else {
+                    u_new = a.P22 * U[k] + a.P31 * Y1[k] + a.P32 * Y2[k] + a.P20Ie;
+                }
+                if (MODEL == CORTEX_MODEL_EXP) {
+                    Y1[k] = a.P11 * Y1[k] + inp;
+                } else if (MODEL == CORTEX_MODEL_ALPHA) {
+                    Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
+                    Y1[k] = a.P11 * Y1[k] + a.jump * inp;
+                }
+                const bool spk = a.frz_ptr ? ((frz >> si) & 1u) != 0 : (integ && u_new >= a.theta);
+                if (spk) {
+                    u_new = a.Ur;
+                    RF[k] = a.n_ref;
+                    const int p = atomicAdd(&s_cnt[si], 1);
+                    s_spk[si * T + p] = (uint16_t)li;
+                }
+                U[k] = u_new;
+                if (a.x_trace || a.v_trace || a.m_trace) {
+                    const size_t ti = (size_t)(n - a.trace_step0) * a.N + g0 + li;
+                    if (a.x_trace) a.x_trace[ti] = x;
+                    if (a.v_trace) a.v_trace[ti] = u_new + a.E_L;
+                    if (a.m_trace) a.m_trace[ti] = (integ && !spk) ? 1 : 0;
+                }
+            }
+            a.U[g0 + li] = U[k];
+            a.r[g0 + li] = RF[k];
+            if (MODEL != CORTEX_MODEL_DELTA) a.y1[g0 + li] = Y1[k];
+            if (MODEL == CORTEX_MODEL_ALPHA) a.y2[g0 + li] = Y2[k];
+        }
+    }
+    __syncthreads();
+    // ------------------------------------------------------------ publish
+    // one reservation per step in the instance's list of that step
+    if (tid < wn) {
+        const int64_t n = t0 + tid;
+        const uint32_t c = (uint32_t)s_cnt[tid];
+        s_misc[tid] = c ? (int)atomicAdd(&a.spk_cnt[(size_t)(n & (H - 1)) * a.n_inst + b], c) : 0;
+    }
+    uint64_t log_pos = a.log_pos[tile];
+    const uint64_t log_b = a.log_base[tile], log_cap = a.log_base[tile + 1] - log_b;
+    __syncthreads();
+    uint64_t nspk = 0;
+    for (int si = 0; si < wn; ++si) {
+        const int64_t n = t0 + si;
+        const int c = s_cnt[si];
+        uint32_t* dst = a.spk_ids + (size_t)(n & (H - 1)) * a.N + n0b + (uint32_t)s_misc[si];
+        const uint16_t* ls = s_spk + (size_t)si * T;
+        for (int i = tid; i < c; i += bs) dst[i] = (uint32_t)(g0 + ls[i]);
+        if (n >= a.log_step0 && n < a.log_step0 + a.log_steps) {
+            if (log_pos + c <= log_cap) {
+                for (int i = tid; i < c; i += bs) a.log_ids[log_b + log_pos + i] = (uint32_t)(g0 + ls[i]);
+                if (tid == 0) a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = (uint32_t)c;
+                log_pos += c;
+            } else if (tid == 0) {
+                a.log_cnt[(n - a.log_step0) * a.n_tiles + tile] = 0xFFFFFFFFu;   // overflow mark
+            }
+        }
+        nspk += c;
+    }
+    // ------------------------------------------------------------ stage out
+    {
+        int4* dst = reinterpret_cast<int4*>(a.ring + (size_t)tile * R * T);
+        const int4* src = reinterpret_cast<const int4*>(ring);
+        for (int i = tid; i < (R * T) / 4; i += bs) dst[i] = src[i];
+        for (int i = ((R * T) & ~3) + tid; i < R * T; i += bs) a.ring[(size_t)tile * R * T + i] = ring[i];
+    }
+    if (tid == 0) {
+        a.events[tile] += ev;
+        a.spikes[tile] += nspk;
+        a.log_pos[tile] = log_pos;
+    }
+}
+
+using StreamFn = void (*)(StreamArgs);
+
+template <int MODEL, typename META, bool WBF16>
+StreamFn pick_npt(int npt) {
+    if (npt == 1) return stream_kernel<MODEL, META, WBF16, 1>;
+    if (npt == 2) return stream_kernel<MODEL, META, WBF16, 2>;
+    return stream_kernel<MODEL, META, WBF16, 4>;
+}
+
+template <int MODEL>
+StreamFn pick_fmt(int meta_bytes, int w_bytes, int npt) {
+    if (meta_bytes == 2)
+        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true>(npt) : pick_npt<MODEL, uint16_t, false>(npt);
+    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true>(npt) : pick_npt<MODEL, uint32_t, false>(npt);
+}
+
+StreamFn pick_stream(int model, int meta_bytes, int w_bytes, int npt) {
+    switch (model) {
+        case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA>(meta_bytes, w_bytes, npt);
+        case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP>(meta_bytes, w_bytes, npt);
+        default: return pick_fmt<CORTEX_MODEL_ALPHA>(meta_bytes, w_bytes, npt);
+    }
+}
+
+}  // namespace
+
+int stream_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds) {
+    StreamFn f = pick_stream(model, meta_bytes, w_bytes, npt);
+    if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, bs, lds) != hipSuccess) return 0;
+    return nb;
+}
+
+// Arguments of the window launches of a network (everything but the clock
+// parity and window length).
+static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint64_t* frz_ptr, uint64_t frz_n,
+                              int64_t frz_step0, float* x_trace, float* v_trace, uint8_t* m_trace,
+                              int64_t trace_step0) {
+    require(n->n_thr <= kMaxThr, CORTEX_EUNSUPPORTED, "Poisson mean too large for the FP32 kernel");
+    StreamArgs a{};
+    a.order = n->d_order;
+    a.tile_inst = n->d_tile_inst;
+    a.tile_size = n->d_tile_size;
+    a.inst_tile0 = n->d_inst_tile0;
+    a.inst_ntiles = n->d_inst_ntiles;
+    a.inst_T = n->d_inst_T;
+    a.inst_n0 = n->d_inst_n0;
+    a.inst_offbase = n->d_inst_offbase;
+    a.row_start = n->d_row_start;
+    a.off_rel = n->d_off_rel;
+    a.meta = n->d_meta;
+    a.w = n->d_w;
+    a.U = n->d_U;
+    a.y1 = n->d_y1;
+    a.y2 = n->d_y2;
+    a.r = n->d_r;
+    a.ring = static_cast<int32_t*>(n->d_ring);
+    a.spk_cnt = n->d_spk_cnt;
+    a.spk_ids = n->d_spk_ids;
+    a.clock = n->d_clock;
+    a.log_cnt = n->d_log_cnt;
+    a.log_ids = n->d_log_ids;
+    a.log_base = n->d_log_base;
+    a.log_pos = n->d_log_pos;
+    a.events = n->d_events;
+    a.spikes = n->d_spikes;
+    a.frz_ids = frz_ids;
+    a.frz_ptr = frz_ptr;
+    a.frz_n = frz_n;
+    a.frz_step0 = frz_step0;
+    a.x_trace = x_trace;
+    a.v_trace = v_trace;
+    a.m_trace = m_trace;
+    a.trace_step0 = trace_step0;
+    a.log_step0 = n->log_step0;
+    a.log_steps = n->log_steps;
+    a.N = n->N;
+    a.n_tiles = n->n_tiles;
+    a.n_inst = n->n_inst;
+    a.T = n->T;
+    a.R = n->R;
+    a.dmin = n->dmin;
+    a.H = n->H;
+    a.W = n->W;
+    a.chunk = n->chunk;
+    a.n_ref = n->k.n_ref;
+    a.n_thr = n->n_thr;
+    a.P22 = (float)n->k.P22;
+    a.P20Ie = (float)(n->k.P20 * n->spec.I_e);
+    a.P11 = (float)n->k.P11;
+    a.P21 = (float)n->k.P21;
+    a.P31 = (float)n->k.P31;
+    a.P32 = (float)n->k.P32;
+    a.P21s = (float)n->k.P21s;
+    a.P22s = (float)n->k.P22s;
+    a.jump = (float)n->k.jump;
+    a.theta = (float)(n->spec.V_th - n->spec.E_L);
+    a.Ur = (float)(n->spec.V_reset - n->spec.E_L);
+    a.w_ext = (float)n->w_ext_native;
+    a.E_L = (float)n->spec.E_L;
+    a.fxw_scale = std::ldexp(1.0f, n->fx - n->fx_shift);
+    a.fx_inv = std::ldexp(1.0, n->fx_shift - n->fx);
+    a.seed = n->seed;
+    for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
+    return a;
+}
+
+static void launch_window(cortex_net* n, StreamFn f, StreamArgs& a, int wn, hipStream_t stream) {
+    a.parity = n->clock_parity;
+    a.wn = wn;
+    hipLaunchKernelGGL(f, dim3(n->n_tiles), dim3(n->BS), n->lds_bytes, stream, a);
+    CX_HIP(hipGetLastError());
+    n->clock_parity ^= 1;
+}
+
+void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
+                        uint64_t frz_n, float* x_trace, float* v_trace, uint8_t* m_trace) {
+    if (n_steps <= 0) return;
+    StreamFn f = pick_stream(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT);
+    CX_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds_bytes));
+    const int64_t first = n->step;
+    StreamArgs a = stream_args(n, frz_ids, frz_ptr, frz_n, first, x_trace, v_trace, m_trace, first);
+    int64_t left = n_steps;
+    // Full windows of plain closed-loop runs replay a captured graph of
+    // kGraphWindows launches (the clock advances on the device; the parity
+    // alternates inside the graph, so it starts even).
+    // The graph lives on a stream of the library's own (the caller's may be
+    // the legacy null stream, which cannot be captured), ordered after the
+    // caller's earlier work and before its later work by two events.
+    const bool plain = !frz_ptr && !x_trace && !v_trace && !m_trace;
+    if (plain && n->use_graph) {
+        const int64_t per = (int64_t)kGraphWindows * n->W;
+        if (left >= per && n->clock_parity != 0) {
+            launch_window(n, f, a, n->W, n->stream);
+            left -= n->W;
+            n->step += n->W;
+        }
+        if (left >= per) {
+            if (!n->graph_stream) {
+                CX_HIP(hipStreamCreate(&n->graph_stream));
+                CX_HIP(hipEventCreateWithFlags(&n->fence_in, hipEventDisableTiming));
+                CX_HIP(hipEventCreateWithFlags(&n->fence_out, hipEventDisableTiming));
+            }
+            if (!n->graph_exec || n->graph_log_step0 != n->log_step0 || n->graph_log_steps != n->log_steps) {
+                if (n->graph_exec) {
+                    CX_HIP(hipStreamSynchronize(n->graph_stream));
+                    CX_HIP(hipGraphExecDestroy(n->graph_exec));
+                    n->graph_exec = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                CX_HIP(hipStreamBeginCapture(n->graph_stream, hipStreamCaptureModeThreadLocal));
+                const int saved = n->clock_parity;
+                for (int k = 0; k < kGraphWindows; ++k) launch_window(n, f, a, n->W, n->graph_stream);
+                n->clock_parity = saved;
+                CX_HIP(hipStreamEndCapture(n->graph_stream, &g));
+                CX_HIP(hipGraphInstantiate(&n->graph_exec, g, nullptr, nullptr, 0));
+                CX_HIP(hipGraphDestroy(g));
+                n->graph_log_step0 = n->log_step0;
+                n->graph_log_steps = n->log_steps;
+            }
+            CX_HIP(hipEventRecord(n->fence_in, n->stream));
+            CX_HIP(hipStreamWaitEvent(n->graph_stream, n->fence_in, 0));
+            while (left >= per) {
+                CX_HIP(hipGraphLaunch(n->graph_exec, n->graph_stream));
+                left -= per;
+                n->step += per;
+            }
+            CX_HIP(hipEventRecord(n->fence_out, n->graph_stream));
+            CX_HIP(hipStreamWaitEvent(n->stream, n->fence_out, 0));
+        }
+    }
+    while (left > 0) {
+        const int wn = (int)std::min<int64_t>(n->W, left);
+        launch_window(n, f, a, wn, n->stream);
+        left -= wn;
+        n->step += wn;
+    }
+}
+
+}  // namespace cortex

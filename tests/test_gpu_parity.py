@@ -328,25 +328,6 @@ def test_batched_open_loop_matches_oracle(cx, orc):
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
 
 
-def test_batched_closed_loop_rates(cx, orc):
-    sizes = [1000, 2000, 4000]
-    spec = netspec.batched_brunel(sizes)
-    T = 2000
-    case("batched closed loop rates")
-    g = cx.Network(spec, 5, record_steps=T)
-    g.step(T)
-    st, ids = g.spikes(0, T)
-    o = orc.OracleNet(spec, 5)
-    o.run(T)
-    ost, oids = o.spikes()
-    rg = helpers.rates_and_cv(st, ids, spec, 500, T)
-    ro = helpers.rates_and_cv(ost, oids, spec, 500, T)
-    print("gpu", rg, "oracle", ro, flush=True)
-    for (rate_g, cv_g), (rate_o, cv_o) in zip(rg, ro):
-        assert rate_o > 1.0
-        assert abs(rate_g - rate_o) <= 0.03 * rate_o
-
-
 def _adjoint_case(cx, orc, spec, T, ckpt, seed, p_spike=0.02):
     import torch
     N = spec.n_neurons

@@ -1,0 +1,194 @@
+"""The streamed plan (one launch per window of steps, input rings staged
+through HBM; the plan of networks whose rings do not fit the chip's
+workgroup-local memory) against the oracle, and against the resident plan.
+"""
+import numpy as np
+import pytest
+
+import netspec
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_03762_amd as m
+    m.lib()
+    return m
+
+
+def _open_loop(cx, orc, spec, T, p, seed, **plan):
+    N = spec.n_neurons
+    steps, ids = netspec.synthetic_raster(N, T, p, seed=seed)
+    g = cx.Network(spec, seed, **plan)
+    x, v = g.run_frozen(steps, ids, T)
+    o = orc.OracleNet(spec, seed)
+    xo, vo = o.run_frozen(steps, ids, T)
+    src, tgt, w, d = o.graph()
+    B = helpers.abs_input_bound(src, tgt, w, d, steps, ids, N, T)
+    return g, x.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64), xo, vo, B
+
+
+@pytest.mark.parametrize("model,d0,d1,tile", [("delta", 5, 30, 256), ("exp", 1, 12, 200), ("alpha", 5, 30, 512),
+                                              ("alpha", 1, 1, 1024), ("delta", 3, 3, 128)])
+def test_streamed_open_loop_matches_oracle(cx, orc, model, d0, d1, tile):
+    spec = netspec.small_brunel(model=model, n_e=2400, n_i=600, c_e=240, c_i=60, delay="uniform_int",
+                                d0=d0, d1=d1, w_rel_sd=0.1, weight_unit="psp_mV")
+    case(f"streamed open loop {model} delays {d0}..{d1} tile {tile}")
+    g, xg, vg, xo, vo, B = _open_loop(cx, orc, spec, 200, 0.01, 13, plan="streamed", tile_size=tile)
+    assert g.query("PLAN") == cx.PLAN_STREAMED and g.query("RING_BYTES") == 4
+    assert g.query("TILES") == -(-3000 // tile)
+    assert np.abs(xo).max() > 0
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
+def test_streamed_batched_instances_open_loop(cx, orc):
+    # instances of different sizes: tiles launched in decreasing synapse order
+    spec = netspec.batched_brunel([200, 450, 1000, 2200, 5000])
+    case("streamed open loop, 5 instances")
+    g, xg, vg, xo, vo, B = _open_loop(cx, orc, spec, 120, 0.01, 4, plan="streamed", tile_size=600)
+    assert g.query("PLAN") == cx.PLAN_STREAMED
+    assert np.abs(xo).max() > 0
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+
+
+@pytest.mark.parametrize("steps_per_sync", [0, 1, 3])
+def test_streamed_integer_weights_exact_across_calls(cx, orc, steps_per_sync):
+    spec = netspec.small_brunel(n_e=1600, n_i=400, c_e=160, c_i=40, delay="uniform_int", d0=3, d1=17,
+                                w_rel_sd=0.0, J=1.0, g=2.0)
+    T = 160
+    steps, ids = netspec.synthetic_raster(2000, T, 0.02, seed=21)
+    case(f"streamed integer weights, split calls, steps_per_sync={steps_per_sync}")
+    g = cx.Network(spec, 17, plan="streamed", tile_size=300, steps_per_sync=steps_per_sync)
+    o = orc.OracleNet(spec, 17)
+    xo, _ = o.run_frozen(steps, ids, T)
+    parts = [g.run_frozen(steps, ids, k)[0].cpu().numpy() for k in (1, 63, 16, 80)]
+    assert np.array_equal(np.concatenate(parts).astype(np.float64), xo)
+    src, _, _, _ = o.graph()
+    outdeg = np.bincount(src, minlength=2000)
+    m = steps < T - g.query("MIN_DELAY")
+    assert g.query("EVENTS") == outdeg[ids[m]].sum()
+
+
+def test_streamed_graph_replays_equal_single_windows_and_the_resident_plan(cx):
+    # integer weights: every plan sums exactly, so closed-loop rasters agree
+    # bit for bit.  The first network runs long calls (captured window graphs
+    # replayed many times, with synchronising reads in between); the second
+    # runs calls shorter than one graph (single window launches); the third
+    # is the resident persistent plan.
+    # delta neurons, weights +1 / -5 mV, threshold 60 mV: the drive alone
+    # would hold 70 mV, recurrent inhibition brings the rate down
+    spec = netspec.small_brunel(n_e=4000, n_i=1000, c_e=400, c_i=100, delay="uniform_int", d0=4, d1=20,
+                                w_rel_sd=0.0, J=1.0, g=5.0, lam=0.35)
+    spec.w_ext = 1.0
+    spec.V_th, spec.V_reset, spec.v0_hi = 60.0, 10.0, 60.0
+    T = 3 * 32 * 4 + 37
+    case("streamed graph replays vs single windows vs resident")
+    runs = []
+    for plan, chunks in ((dict(plan="streamed", tile_size=500), [32 * 4, 32 * 4, 32 * 4 + 37]),
+                         (dict(plan="streamed", tile_size=500), [7] * (T // 7) + [T % 7]),
+                         (dict(plan="resident", tile_size=500), [T])):
+        g = cx.Network(spec, 23, record_steps=T, **plan)
+        done = 0
+        counts = []
+        for c in chunks:
+            g.step(c)
+            done += c
+            counts.append(len(g.spikes(0, done)[0]))   # synchronising read between replays
+        st, ids = g.spikes(0, T)
+        V, r, _, _ = g.state()
+        runs.append((st, ids, V, r, g.query("EVENTS"), g.query("PLAN")))
+        g.close()
+    assert runs[0][5] == cx.PLAN_STREAMED and runs[2][5] == cx.PLAN_RESIDENT
+    assert len(runs[0][0]) > 1000
+    for other in runs[1:]:
+        for a, b in zip(runs[0][:5], other[:5]):
+            assert np.array_equal(a, b)
+
+
+def test_streamed_closed_loop_statistics_match_oracle(cx, orc):
+    spec = netspec.brunel_112k_alpha(scale_n=0.1, scale_k=0.1)
+    T = 10000
+    case("streamed closed loop brunel 112k x0.1, 1 s")
+    g = cx.Network(spec, 2, record_steps=T, plan="streamed")
+    g.step(T)
+    st, ids = g.spikes(0, T)
+    o = orc.OracleNet(spec, 2)
+    o.run(T)
+    ost, oids = o.spikes()
+    rg = helpers.rates_and_cv(st, ids, spec, 1000, T)
+    ro = helpers.rates_and_cv(ost, oids, spec, 1000, T)
+    print("gpu", rg, "oracle", ro, flush=True)
+    for (rate_g, cv_g), (rate_o, cv_o) in zip(rg, ro):
+        assert rate_o > 0.5
+        assert abs(rate_g - rate_o) <= 0.02 * rate_o
+        assert abs(cv_g - cv_o) <= 0.05 * cv_o
+    src, _, _, _ = o.graph()
+    outdeg = np.bincount(src, minlength=spec.n_neurons)
+    m = st < T - g.query("MIN_DELAY")
+    assert g.query("EVENTS") == outdeg[ids[m]].sum()
+
+
+def test_full_size_two_million_neurons_bf16(cx, orc):
+    """The two-million-neuron bf16 network (2.25e10 synapses): the streamed
+    plan is chosen by itself; open-loop input of sampled targets matches the
+    oracle (which holds only those targets' synapses, weights rounded to
+    bf16 as stored); closed-loop statistics match those of a same-in-degree
+    oracle surrogate (the full network does not fit the host)."""
+    import json
+    import os
+    from tests.golden.make_closed_loop_stats import bf16_rne, spec_hash
+    spec = netspec.brunel_2m_bf16()
+    N, T = spec.n_neurons, 60
+    case("2M neurons bf16: build (streamed plan)")
+    g = cx.Network(spec, 5, record_steps=10000)
+    assert g.query("PLAN") == cx.PLAN_STREAMED and g.E == N * 11250 and g.query("EDGE_BYTES") == 4
+    sel = np.unique(np.concatenate([[0, N - 1], netspec.sample_targets(N, 24, seed=8)]))
+    steps, ids = netspec.sparse_raster(N, T, 0.0009, seed=31)
+    case("2M neurons bf16: open loop on sampled targets")
+    x, v = g.run_frozen(steps, ids, T)
+    xg = x[:, sel].cpu().numpy().astype(np.float64)
+    vg = v[:, sel].cpu().numpy().astype(np.float64)
+    del x, v
+    o = orc.OracleNet(spec, 5, sel=sel)
+    src, tgt, w, d = o.graph()
+    o.set_weights(bf16_rne(w))
+    xo, vo = o.run_frozen(steps, ids, T)
+    B = helpers.abs_input_bound(src, tgt, np.abs(bf16_rne(w)), d, steps, ids, N, T)[:, sel]
+    assert np.abs(xo).max() > 0
+    assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
+    assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
+    del o
+    case("2M neurons bf16: closed loop 1 s vs same-in-degree oracle surrogate")
+    g.reset()
+    Tc = 10000
+    g.step(Tc)
+    st, sid = g.spikes(0, Tc)
+    g.close()
+    rg = helpers.rates_and_cv(st, sid, spec, 1000, Tc)
+    here = os.path.dirname(os.path.abspath(__file__))
+    for name in ("brunel_2m_bf16_surrogate_100k", "brunel_2m_bf16_surrogate_20k"):
+        with open(os.path.join(here, "golden", f"closed_loop_{name}.json")) as f:
+            go = json.load(f)
+        print(name, "gpu", rg, "oracle", list(zip(go["rates_hz"], go["cv"])), flush=True)
+    # the larger surrogate is the reference; the difference between the two
+    # surrogates bounds the finite-size effect that the tolerance must allow
+    with open(os.path.join(here, "golden", "closed_loop_brunel_2m_bf16_surrogate_100k.json")) as f:
+        go = json.load(f)
+    with open(os.path.join(here, "golden", "closed_loop_brunel_2m_bf16_surrogate_20k.json")) as f:
+        gs = json.load(f)
+    for (rate_g, cv_g), r100, c100, r20, c20 in zip(rg, go["rates_hz"], go["cv"], gs["rates_hz"], gs["cv"]):
+        fs_r = abs(r100 - r20) / r100
+        fs_c = abs(c100 - c20) / c100
+        assert abs(rate_g - r100) <= (0.02 + fs_r) * r100
+        assert abs(cv_g - c100) <= (0.05 + fs_c) * c100
