@@ -151,6 +151,24 @@ typedef struct cortex_net cortex_net;
 int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_device* dev,
                          cortex_net** out);
 
+/* Passage: the partition of the neurons into parts, one per owner (Eq.
+   9-10), balanced by edge count (Sec. III-A, load balance), with every owner's
+   input buffers in workgroup-local memory (Sec. III-B).
+   The FP32 launch plan cortex_build_network would choose for `spec` on a
+   device with n_cu compute units, lds_per_cu bytes of workgroup-local memory
+   and threads_per_cu resident threads per compute unit, made on the host
+   alone (no device call; register limits are not known, so a plan that
+   fits here may still be refused by the device; normal delays are planned
+   for their widest possible range).  Every plan is checked: the indices the
+   kernels derive from it stay inside their arrays.  plan (host, n_plan
+   entries, fewer are cut): plan kind, tiles, tile stride T, workgroup size,
+   neurons per thread, steps per exchange W, ring slots, history slots, chunk,
+   largest tile count of an instance, LDS bytes, ring element bytes, d_min,
+   d_max, XCD map, one-thread-per-segment delivery.  Errors: EINVAL,
+   EUNSUPPORTED (no plan fits, or a plan failed its check). */
+int cortex_plan(const cortex_spec* spec, int32_t n_cu, int64_t lds_per_cu, int32_t threads_per_cu,
+                int64_t* plan, int32_t n_plan);
+
 /* Passage: the simulation step of Sec. II-B (Fig.
    brain_simulation_procedure (d)): synapses of spiking sources act on their
    targets after each synapse's delay, then every neuron advances by the LIF

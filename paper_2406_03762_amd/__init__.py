@@ -84,6 +84,7 @@ def lib() -> C.CDLL:
         L.cortex_build_network.argtypes = [C.POINTER(cortex_spec), C.c_uint64, C.POINTER(cortex_device),
                                            C.POINTER(P)]
         L.cortex_step.argtypes = [P, i64]
+        L.cortex_plan.argtypes = [C.POINTER(cortex_spec), C.c_int32, i64, C.c_int32, C.POINTER(i64), C.c_int32]
         L.cortex_get_spikes.argtypes = [P, i64, i64, P, P, i64, C.POINTER(i64)]
         L.cortex_clear_spikes.argtypes = [P]
         L.cortex_run_frozen.argtypes = [P, P, P, i64, i64, P, P]
@@ -224,6 +225,19 @@ def cortex_build_network(net, seed: int, device=None, stream=None, **plan):
     h = C.c_void_p()
     _check(lib().cortex_build_network(C.byref(spec), seed, C.byref(dev), C.byref(h)))
     return h, (alloc, keep, dev, st)
+
+
+PLAN_FIELDS = ("plan", "tiles", "T", "block_size", "npt", "W", "R", "H", "chunk", "ntb_max", "lds_bytes",
+               "ring_bytes", "dmin", "dmax", "xcd_map", "thread_segments")
+
+
+def cortex_plan(net, n_cu: int = 256, lds_per_cu: int = 163840, threads_per_cu: int = 2048, **plan) -> dict:
+    """The FP32 launch plan of a network description on a device of the given
+    size, made on the host (no GPU needed)."""
+    spec, keep = make_spec(net, **plan)
+    out = (C.c_int64 * len(PLAN_FIELDS))()
+    _check(lib().cortex_plan(C.byref(spec), n_cu, lds_per_cu, threads_per_cu, out, len(PLAN_FIELDS)))
+    return dict(zip(PLAN_FIELDS, list(out)))
 
 
 def cortex_step(h, n_steps: int) -> None:

@@ -151,7 +151,8 @@ struct WgradArgs {
     const uint64_t* row_start;
     const uint32_t* off_rel;
     const void* meta;
-    int meta16;
+    int meta16;                 // 16-bit records (alone, or under a bf16 weight when packed)
+    int packed;
     int T, dmin;                // record = (delay - dmin) T + target in tile
     int sw, n_sub;              // steps per sub-window, sub-windows of the segment
     int n_inst;
@@ -229,8 +230,9 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
                         m[u] = 0;
                         g[u] = 0.f;
                         if (e < e1) {
-                            m[u] = a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                            : static_cast<const uint32_t*>(a.meta)[e];
+                            m[u] = a.packed ? (static_cast<const uint32_t*>(a.meta)[e] & 0xFFFFu)
+                                   : a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                              : static_cast<const uint32_t*>(a.meta)[e];
                             g[u] = a.grad[e];
                         }
                     }
@@ -492,7 +494,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 wa.inst_ntiles = n->d_inst_ntiles; wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0;
                 wa.inst_offbase = n->d_inst_offbase;
                 wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
-                wa.meta16 = n->meta_bytes == 2; wa.T = n->T; wa.dmin = n->dmin;
+                wa.meta16 = n->meta_bytes == 2; wa.packed = n->w_bytes == 2; wa.T = n->T; wa.dmin = n->dmin;
                 wa.sw = sw; wa.n_sub = n_sub; wa.n_inst = n->n_inst;
                 wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
                 wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;

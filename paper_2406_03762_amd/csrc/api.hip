@@ -297,13 +297,18 @@ static void make_blocks(cortex_net* n) {
     }
 }
 
-// Delay range known from the specification (normal delays need a device pass).
-static bool host_delay_range(const cortex_net* n, int* dmin, int* dmax) {
+// Delay range known from the specification.  Normal delays need a device
+// pass over the drawn values, unless `bound` asks for the widest range any
+// draw can give (a Box-Muller normal stays within 8.6 standard deviations).
+static bool host_delay_range(const cortex_net* n, int* dmin, int* dmax, bool bound = false) {
     int lo = 1 << 30, hi = 0;
     for (const auto& B : n->blocks) {
-        if (B.delay_kind == CORTEX_DELAY_NORMAL) return false;
+        if (B.delay_kind == CORTEX_DELAY_NORMAL && !bound) return false;
         int a, b;
-        if (B.delay_kind == CORTEX_DELAY_CONST) {
+        if (B.delay_kind == CORTEX_DELAY_NORMAL) {
+            a = steps_of_ms(B.d0 - 8.6 * B.d1, n->spec.dt);
+            b = steps_of_ms(B.d0 + 8.6 * B.d1, n->spec.dt);
+        } else if (B.delay_kind == CORTEX_DELAY_CONST) {
             a = b = steps_of_ms(B.d0, n->spec.dt);
         } else {
             a = (int)B.d0;
@@ -406,12 +411,21 @@ static std::vector<double> mean_indegree(const cortex_net* n) {
 // different tile sizes so that every tile holds about the same number of
 // synapses (the memory/edge-count balance of Sec. III-A): T_b ~ C / K_b for
 // mean in-degree K_b, with C the smallest load that fits the device.
+// Resident workgroups of a kernel variant per compute unit: asked of the
+// runtime on a live device, else bounded by LDS and threads alone.
+static int occupancy(const cortex_net* n, bool streamed, int meta, int w_bytes, int npt, int bs, size_t lds) {
+    if (n->dd.live)
+        return streamed ? stream_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds)
+                        : step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds, n->ring_bytes);
+    if (w_bytes == 2 && meta != 2) return 0;   // no kernel for bf16 with 32-bit records
+    if (!streamed && npt == 4 && bs != 512) return 0;   // launch bound of the four-neuron variant
+    return (int)std::min<size_t>((size_t)(n->dd.thr_cu / bs), lds ? n->dd.lds_cu / lds : 64);
+}
+
 static void plan_tiles(cortex_net* n) {
-    hipDeviceProp_t prop;
-    CX_HIP(hipGetDeviceProperties(&prop, n->device));
-    const int n_cu = prop.multiProcessorCount;
-    const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
-    const int thr_cu = prop.maxThreadsPerMultiProcessor ? prop.maxThreadsPerMultiProcessor : 2048;
+    const int n_cu = n->dd.n_cu;
+    const size_t lds_cu = n->dd.lds_cu;
+    const int thr_cu = n->dd.thr_cu;
     std::vector<double> K(n->n_inst, 0.0);
     for (const auto& B : n->blocks) {
         const double per_tgt = B.rule == CORTEX_RULE_FIXED_INDEGREE
@@ -490,7 +504,7 @@ static void plan_tiles(cortex_net* n) {
                         const int meta = (uint64_t)Tm * (uint64_t)n->R <= 65536 ? 2 : 4;
                         // four neurons per thread only in 512-thread workgroups
                         if ((npt <= 2 || (npt == 4 && bs == 512)) &&
-                            step_occupancy(n->spec.model, meta, w_bytes, npt, bs, lds, n->ring_bytes) >= per_cu) {
+                            occupancy(n, false, meta, w_bytes, npt, bs, lds) >= per_cu) {
                             Tb = cand;
                             BS = bs;
                             chunk = c;
@@ -525,6 +539,15 @@ static void plan_tiles(cortex_net* n) {
     make_tiles(n, Tb);
     n->lds_bytes = step_lds_bytes(n->R, T, n->W, n->ntb_max, chunk, n->ring_bytes);
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "input ring does not fit workgroup-local memory");
+    // every tile's workgroup must be resident at once
+    {
+        const int meta = (uint64_t)T * (uint64_t)n->R <= 65536 ? 2 : 4;
+        const int w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
+        const int per_cu = occupancy(n, false, meta, w_bytes, n->NPT, BS, n->lds_bytes);
+        require((int64_t)per_cu * n_cu >= n->n_tiles, CORTEX_EUNSUPPORTED,
+                "not every tile's workgroup can be resident at once (" + std::to_string(n->n_tiles) +
+                    " tiles, " + std::to_string(per_cu) + " per CU)");
+    }
     n->xcd_map = (n->n_tiles % 8 == 0) ? 1 : 0;
 }
 
@@ -538,15 +561,14 @@ static void plan_tiles(cortex_net* n) {
 // time order for the load balance of Sec. III-A).
 static void plan_stream(cortex_net* n) {
     const cortex_spec& s = n->spec;
-    hipDeviceProp_t prop;
-    CX_HIP(hipGetDeviceProperties(&prop, n->device));
-    const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+    const size_t lds_cu = n->dd.lds_cu;
     const int per_cu = s.wg_per_cu > 0 ? s.wg_per_cu : 1;
     n->W = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(n->dmin, 8);
     n->R = n->dmax - n->dmin + n->W;
     n->H = pow2_at_least(n->dmin + 2 * n->W);
     n->ring_bytes = 4;
-    n->chunk = 512;
+    // descriptor slots: a chunk, or 64 per wave of the wave-flattened mapping
+    n->chunk = 1024;
     int Tmax = 0;
     for (int t = 4; t <= 4096; t += 4)
         if (stream_lds_bytes(n->R, t, n->W, n->chunk) * per_cu <= lds_cu) Tmax = t;
@@ -556,8 +578,9 @@ static void plan_stream(cortex_net* n) {
                 "tile_size too large for the streamed plan's workgroup-local memory");
         Tmax = s.tile_size;
     }
-    int64_t Nmax = 1;
-    for (int b = 0; b < n->n_inst; ++b) Nmax = std::max(Nmax, n->inst_N[b]);
+    // one neuron per thread of a 1024-thread workgroup when the ring allows
+    // it: a thread with two neurons doubles the update's critical path
+    if (s.tile_size == 0 && s.block_size == 0 && Tmax > 1024 && Tmax < 2048) Tmax = 1024;
     std::vector<int32_t> Tb(n->n_inst);
     for (int b = 0; b < n->n_inst; ++b) Tb[b] = (int32_t)std::min<int64_t>(Tmax, n->inst_N[b]);
     const int Tm = *std::max_element(Tb.begin(), Tb.end());
@@ -573,14 +596,20 @@ static void plan_stream(cortex_net* n) {
     require(n->lds_bytes <= lds_cu, CORTEX_EUNSUPPORTED, "streamed tile does not fit workgroup-local memory");
     const int meta = (uint64_t)n->T * (uint64_t)n->R <= 65536 ? 2 : 4;
     const int w_bytes = (s.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
-    require(stream_occupancy(s.model, meta, w_bytes, n->NPT, n->BS, n->lds_bytes) >= 1, CORTEX_EUNSUPPORTED,
+    require(occupancy(n, true, meta, w_bytes, n->NPT, n->BS, n->lds_bytes) >= 1, CORTEX_EUNSUPPORTED,
             "streamed kernel does not fit a compute unit with this plan");
     // launch order
     const auto K = mean_indegree(n);
+    // mean segment length (synapses of one source into one tile): a few
+    // synapses make one thread per segment the better mapping
+    double seg = 0.0;
+    for (int b = 0; b < n->n_inst; ++b) seg = std::max(seg, K[b] * (double)Tb[b] / (double)n->inst_N[b]);
+    n->thread_segments = seg < 16.0 ? 1 : 0;
     std::vector<double> load(n->n_tiles);
     for (int t = 0; t < n->n_tiles; ++t) load[t] = K[n->tile_inst[t]] * n->tile_size[t];
     const bool uniform = *std::max_element(load.begin(), load.end()) <= 1.05 * *std::min_element(load.begin(), load.end());
-    std::vector<int32_t> order(n->n_tiles);
+    std::vector<int32_t>& order = n->order;
+    order.assign(n->n_tiles, 0);
     if (uniform) {
         const int n8 = n->n_tiles / 8, rem = n->n_tiles % 8;
         for (int bid = 0; bid < n->n_tiles; ++bid) {
@@ -591,9 +620,110 @@ static void plan_stream(cortex_net* n) {
         for (int t = 0; t < n->n_tiles; ++t) order[t] = t;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
     }
-    n->d_order = dev_alloc_t<int32_t>(n, n->n_tiles);
-    upload(n, n->d_order, order);
     n->xcd_map = 0;
+}
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Every index the step kernels derive from a plan stays inside the array it
+// addresses: the LDS carve-up (step_lds_bytes / stream_lds_bytes, in the
+// kernels' order) fits the device, neurons fit the threads, record fields
+// fit their width, the spike windows fit the per-step arrays and the
+// publication / spike-list slots outlive every reader.  Returns what is
+// violated ("" if nothing).
+static std::string plan_violation(const cortex_net* n) {
+    std::string v;
+    auto need = [&](bool ok, const char* what) {
+        if (!ok) v += std::string(v.empty() ? "" : "; ") + what;
+    };
+    const bool streamed = n->plan_kind == CORTEX_PLAN_STREAMED;
+    need(n->BS == 256 || n->BS == 512 || n->BS == 1024, "block size");
+    need(n->NPT == 1 || n->NPT == 2 || n->NPT == 4, "neurons per thread");
+    need((int64_t)n->NPT * n->BS >= n->T, "tile larger than its threads' neurons");
+    need(streamed || n->NPT != 4 || n->BS == 512, "four neurons per thread outside 512-thread workgroups");
+    need(n->W >= 1 && n->W <= 8 && n->W <= n->dmin, "steps per exchange");
+    need(n->R == n->dmax - n->dmin + n->W, "ring slots");
+    need((uint64_t)n->R * (uint64_t)n->T <= 0xFFFFFFFFull, "record width");
+    need(n->spec.weight_dtype != CORTEX_W_BF16 || (uint64_t)n->R * n->T <= 65536, "packed bf16 records");
+    need(is_pow2(n->H) && n->H >= (streamed ? n->dmin + 2 * n->W : 2 * n->dmin + 2 * n->W + 2), "history slots");
+    need(n->BS / 64 + 1 <= 20, "per-wave arrays");
+    need(n->chunk >= 128, "chunk");
+    need(n->lds_bytes <= n->dd.lds_cu, "LDS per workgroup");
+    int64_t covered = 0;
+    int tiles = 0;
+    for (int b = 0; b < n->n_inst; ++b) {
+        need(n->inst_T[b] <= n->T && n->inst_ntiles[b] <= n->ntb_max, "instance tiles");
+        tiles += n->inst_ntiles[b];
+    }
+    need(tiles == n->n_tiles && (int)n->tile_size.size() == n->n_tiles, "tile table");
+    for (int t = 0; t < n->n_tiles; ++t) {
+        need(n->tile_size[t] >= 1 && n->tile_size[t] <= n->inst_T[n->tile_inst[t]], "tile size");
+        need(n->tile_start[t] == covered, "tiles do not partition the neurons");
+        covered += n->tile_size[t];
+    }
+    need(covered == n->N, "tiles do not cover the neurons");
+    if (streamed) {
+        need(n->T % 4 == 0 && n->T <= 65535, "streamed tile stride");
+        need(n->ring_bytes == 4, "streamed ring width");
+        need(n->chunk >= n->BS, "streamed descriptor slots (64 per wave)");
+        need(n->lds_bytes == stream_lds_bytes(n->R, n->T, n->W, n->chunk), "streamed LDS carve-up");
+        std::vector<char> seen(n->n_tiles, 0);
+        bool perm = (int)n->order.size() == n->n_tiles;
+        for (size_t i = 0; perm && i < n->order.size(); ++i) {
+            const int t = n->order[i];
+            perm = t >= 0 && t < n->n_tiles && !seen[t];
+            if (perm) seen[t] = 1;
+        }
+        need(perm, "workgroup order is not a permutation of the tiles");
+    } else {
+        need(n->lds_bytes == step_lds_bytes(n->R, n->T, n->W, n->ntb_max, n->chunk, n->ring_bytes),
+             "resident LDS carve-up");
+        need(n->ring_bytes == 8 || n->ring_bytes == 4, "ring width");
+        need(!n->xcd_map || n->n_tiles % 8 == 0, "XCD map");
+    }
+    return v;
+}
+
+// FP32 plan: the resident persistent plan when every tile's ring fits the
+// workgroup-local memory (64-bit sums first, then 32-bit, then shorter
+// exchange windows), else (or when asked) the streamed plan.  Host-side
+// only (no device memory); the plan is checked before it is used.
+static void plan_fp32(cortex_net* n) {
+    const cortex_spec& s = n->spec;
+    const int dmin = n->dmin, dmax = n->dmax;
+    // spikes are exchanged every W steps (W <= d_min keeps every input on
+    // time); pending arrivals then span d_max - d_min + W steps
+    const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
+    require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
+    bool planned = false;
+    if (s.plan_kind != CORTEX_PLAN_STREAMED) {
+        n->plan_kind = CORTEX_PLAN_RESIDENT;
+        for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
+            n->ring_bytes = rb;
+            for (int W = W0;; W = std::max(1, W / 2)) {
+                n->W = W;
+                n->R = dmax - dmin + n->W;
+                n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
+                try {
+                    plan_tiles(n);
+                    planned = true;
+                    break;
+                } catch (const Error& e) {
+                    const bool last = rb == 4 && (W == 1 || s.steps_per_sync > 0);
+                    if (e.status != CORTEX_EUNSUPPORTED || (last && s.plan_kind == CORTEX_PLAN_RESIDENT)) throw;
+                    if (W == 1 || s.steps_per_sync > 0) break;
+                }
+            }
+        }
+    }
+    if (!planned) {
+        n->plan_kind = CORTEX_PLAN_STREAMED;
+        require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "the adjoint needs the resident plan (the network is too "
+                                                     "large for workgroup-local input rings)");
+        plan_stream(n);
+    }
+    const std::string bad = plan_violation(n);
+    require(bad.empty(), CORTEX_EUNSUPPORTED, "plan check failed: " + bad);
 }
 
 static void upload_tables_fp32(cortex_net* n) {
@@ -718,7 +848,7 @@ static void zero_dynamic_fp64(cortex_net* n) {
 }
 
 // Device error flag raised by a kernel (a wait that exceeded its limit).
-static void check_device_flag(cortex_net* n) {
+void check_device_flag(cortex_net* n) {
     CX_HIP(hipStreamSynchronize(n->stream));
     int32_t e = 0;
     CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
@@ -751,41 +881,10 @@ static void build(cortex_net* n) {
         if (!host_delay_range(n, &dmin, &dmax)) delay_range(n, &dmin, &dmax);
         n->dmin = dmin;
         n->dmax = dmax;
-        // spikes are exchanged every W steps (W <= d_min keeps every input on
-        // time); pending arrivals then span d_max - d_min + W steps
-        // fewer steps per exchange shorten the rings when a plan does not
-        // fit workgroup-local memory
-        const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
-        require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
-        bool planned = false;
-        if (s.plan_kind != CORTEX_PLAN_STREAMED) {
-            // 64-bit input sums first; 32-bit sums (scaled by the largest
-            // exact input bound of any neuron) when the 64-bit rings cannot fit
-            n->plan_kind = CORTEX_PLAN_RESIDENT;
-            for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
-                n->ring_bytes = rb;
-                for (int W = W0;; W = std::max(1, W / 2)) {
-                    n->W = W;
-                    n->R = dmax - dmin + n->W;
-                    n->H = pow2_at_least(2 * dmin + 2 * n->W + 2);
-                    try {
-                        plan_tiles(n);
-                        planned = true;
-                        break;
-                    } catch (const Error& e) {
-                        const bool last = rb == 4 && (W == 1 || s.steps_per_sync > 0);
-                        if (e.status != CORTEX_EUNSUPPORTED || (last && s.plan_kind == CORTEX_PLAN_RESIDENT))
-                            throw;
-                        if (W == 1 || s.steps_per_sync > 0) break;
-                    }
-                }
-            }
-        }
-        if (!planned) {
-            n->plan_kind = CORTEX_PLAN_STREAMED;
-            require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "the adjoint needs the resident plan (the network is too "
-                                                         "large for workgroup-local input rings)");
-            plan_stream(n);
+        plan_fp32(n);
+        if (n->plan_kind == CORTEX_PLAN_STREAMED) {
+            n->d_order = dev_alloc_t<int32_t>(n, n->n_tiles);
+            upload(n, n->d_order, n->order);
         }
         n->fx = fixed_point_bits(n);
         n->fx_shift = fixed_point_shift(n, n->fx);
@@ -803,9 +902,7 @@ static void build(cortex_net* n) {
         save_checkpoint(n, 0);
         if (n->plan_kind == CORTEX_PLAN_RESIDENT) {
             const int per_cu = step_max_blocks_per_cu(n);
-            hipDeviceProp_t prop;
-            CX_HIP(hipGetDeviceProperties(&prop, n->device));
-            require((int64_t)per_cu * prop.multiProcessorCount >= n->n_tiles, CORTEX_EUNSUPPORTED,
+            require((int64_t)per_cu * n->dd.n_cu >= n->n_tiles, CORTEX_EUNSUPPORTED,
                     "not every tile's workgroup can be resident at once (" + std::to_string(n->n_tiles) +
                         " tiles, " + std::to_string(per_cu) + " per CU)");
         }
@@ -923,8 +1020,8 @@ void restore_checkpoint(cortex_net* n, int k) {
 // Advance the FP32 network, splitting launches at checkpoint steps when the
 // adjoint is enabled.  Frozen lists and traces are indexed from the call's
 // first step.
-static void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
-                         uint64_t frz_n, float* x_trace, float* v_trace) {
+void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
+                  uint64_t frz_n, float* x_trace, float* v_trace) {
     if (n->plan_kind == CORTEX_PLAN_STREAMED) {
         launch_stream_fp32(n, n_steps, frz_ids, frz_ptr, frz_n, x_trace, v_trace);
         return;
@@ -986,6 +1083,12 @@ int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_de
         if (dev) n->dev = *dev;
         n->stream = static_cast<hipStream_t>(n->dev.stream);
         CX_HIP(hipGetDevice(&n->device));
+        hipDeviceProp_t prop;
+        CX_HIP(hipGetDeviceProperties(&prop, n->device));
+        n->dd.n_cu = prop.multiProcessorCount;
+        n->dd.lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+        n->dd.thr_cu = prop.maxThreadsPerMultiProcessor ? prop.maxThreadsPerMultiProcessor : 2048;
+        n->dd.live = true;
         n->seed = seed;
         build(n);
         *out = n;
@@ -997,6 +1100,45 @@ int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_de
     } catch (const std::bad_alloc&) {
         set_error("host allocation failed");
         if (n) cortex_destroy(n);
+        return CORTEX_ENOMEM;
+    }
+}
+
+int cortex_plan(const cortex_spec* spec, int32_t n_cu, int64_t lds_per_cu, int32_t threads_per_cu,
+                int64_t* plan, int32_t n_plan) {
+    cortex_net* n = nullptr;
+    try {
+        require(plan != nullptr && n_plan >= 0, CORTEX_EINVAL, "plan is NULL");
+        require(n_cu >= 1 && lds_per_cu >= 1024 && threads_per_cu >= 256, CORTEX_EINVAL, "bad device description");
+        validate(spec);
+        require(spec->precision == CORTEX_FP32, CORTEX_EINVAL, "plans are made for FP32 networks");
+        n = new cortex_net();
+        n->spec = *spec;
+        n->pops.assign(spec->pops, spec->pops + spec->n_pops);
+        n->projs.assign(spec->projs, spec->projs + spec->n_projs);
+        n->spec.pops = nullptr;
+        n->spec.projs = nullptr;
+        n->dd.n_cu = n_cu;
+        n->dd.lds_cu = (size_t)lds_per_cu;
+        n->dd.thr_cu = threads_per_cu;
+        n->dd.live = false;
+        n->ckpt = spec->ckpt_every;
+        make_blocks(n);
+        host_delay_range(n, &n->dmin, &n->dmax, true);
+        plan_fp32(n);
+        const int64_t out[] = {n->plan_kind, n->n_tiles, n->T, n->BS, n->NPT, n->W, n->R, n->H, n->chunk,
+                               n->ntb_max, (int64_t)n->lds_bytes, n->ring_bytes, n->dmin, n->dmax, n->xcd_map,
+                               n->thread_segments};
+        for (int i = 0; i < n_plan && i < (int)(sizeof out / sizeof out[0]); ++i) plan[i] = out[i];
+        delete n;
+        return CORTEX_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        delete n;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        delete n;
         return CORTEX_ENOMEM;
     }
 }
@@ -1183,22 +1325,24 @@ int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, in
     for (int b = 0; b < n->n_inst; ++b) off_len += (uint64_t)n->inst_N[b] * (n->inst_ntiles[b] + 1);
     auto off = download(n, n->d_off_rel, off_len);
     std::vector<uint32_t> meta(n->E);
-    if (n->meta_bytes == 2) {
+    std::vector<double> wv(n->E);
+    if (n->w_bytes == 2) {
+        // packed records: bf16 weight in the high half
+        meta = download(n, static_cast<const uint32_t*>(n->d_meta), n->E);
+        for (int64_t e = 0; e < n->E; ++e) {
+            uint32_t u = meta[e] & 0xFFFF0000u;
+            float f;
+            std::memcpy(&f, &u, 4);
+            wv[e] = f;
+            meta[e] &= 0xFFFFu;
+        }
+    } else if (n->meta_bytes == 2) {
         auto m = download(n, static_cast<const uint16_t*>(n->d_meta), n->E);
         std::copy(m.begin(), m.end(), meta.begin());
     } else {
         meta = download(n, static_cast<const uint32_t*>(n->d_meta), n->E);
     }
-    std::vector<double> wv(n->E);
-    if (n->w_bytes == 2) {
-        auto m = download(n, static_cast<const uint16_t*>(n->d_w), n->E);
-        for (int64_t e = 0; e < n->E; ++e) {
-            uint32_t u = (uint32_t)m[e] << 16;
-            float f;
-            std::memcpy(&f, &u, 4);
-            wv[e] = f;
-        }
-    } else {
+    if (n->w_bytes != 2) {
         auto m = download(n, static_cast<const float*>(n->d_w), n->E);
         for (int64_t e = 0; e < n->E; ++e) wv[e] = m[e];
     }

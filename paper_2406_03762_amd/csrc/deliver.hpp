@@ -36,10 +36,20 @@ __device__ __forceinline__ void ring_add(RING* ring, uint32_t x, int32_t iw) {
         atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
 }
 
+// Record e: meta (delay - d_min) T + target and the weight.  Two layouts:
+// META (16 or 32 bits) and an fp32 weight in separate arrays, or, for bf16
+// weights, one packed 32-bit word (weight in the high half, 16-bit record
+// below; a bf16 value is the high half of its fp32 value) in `meta`.
 template <typename META, bool WBF16>
-__device__ __forceinline__ float weight_at(const void* w, uint64_t e) {
-    if (WBF16) return __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16);
-    return static_cast<const float*>(w)[e];
+__device__ __forceinline__ void load_rec(const void* meta, const void* w, uint64_t e, uint32_t& m, float& wv) {
+    if (WBF16) {
+        const uint32_t r = static_cast<const uint32_t*>(meta)[e];
+        m = r & 0xFFFFu;
+        wv = __uint_as_float(r & 0xFFFF0000u);
+    } else {
+        m = static_cast<const META*>(meta)[e];
+        wv = static_cast<const float*>(w)[e];
+    }
 }
 
 // Long segments: wave-owned runs of whole segments [kw0, kw1).
@@ -67,8 +77,8 @@ __device__ __forceinline__ void deliver_long(const uint4* s_sg, RING* ring, int 
             const uint32_t y = __builtin_amdgcn_readfirstlane(g.y);
             const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane(g.w) << 32) |
                                 __builtin_amdgcn_readfirstlane(g.z);
-            mp[u] = static_cast<const unsigned char*>(meta) + e0 * sizeof(META);
-            wp[u] = static_cast<const unsigned char*>(w) + e0 * (WBF16 ? 2 : 4);
+            mp[u] = static_cast<const unsigned char*>(meta) + e0 * (WBF16 ? 4 : sizeof(META));
+            wp[u] = WBF16 ? nullptr : static_cast<const unsigned char*>(w) + e0 * 4;
             roff[u] = (uint32_t)(base_slot + (int)y) * T;
             len_max = max(len_max, len[u]);
         }
@@ -80,9 +90,14 @@ __device__ __forceinline__ void deliver_long(const uint4* s_sg, RING* ring, int 
             for (int u = 0; u < U8; ++u) {
                 // m[u] and wv[u] are read below under the same condition
                 if (o < len[u]) {
-                    m[u] = *reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META));
-                    wv[u] = WBF16 ? __uint_as_float((uint32_t)*reinterpret_cast<const uint16_t*>(wp[u] + o * 2u) << 16)
-                                  : *reinterpret_cast<const float*>(wp[u] + o * 4u);
+                    if (WBF16) {
+                        const uint32_t r = *reinterpret_cast<const uint32_t*>(mp[u] + o * 4u);
+                        m[u] = r & 0xFFFFu;
+                        wv[u] = __uint_as_float(r & 0xFFFF0000u);
+                    } else {
+                        m[u] = *reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META));
+                        wv[u] = *reinterpret_cast<const float*>(wp[u] + o * 4u);
+                    }
                 }
             }
 #pragma unroll
@@ -130,8 +145,7 @@ __device__ __forceinline__ void deliver_short(const uint4* s_sg, const uint32_t*
                     const uint4 g = s_sg[seg];
                     const uint64_t e = (((uint64_t)g.w << 32) | g.z) + (fu - s_len[seg]);
                     q[u] = g.y | 8u;
-                    m[u] = static_cast<const META*>(meta)[e];
-                    wv[u] = weight_at<META, WBF16>(w, e);
+                    load_rec<META, WBF16>(meta, w, e, m[u], wv[u]);
                 }
             }
 #pragma unroll

@@ -144,12 +144,12 @@ __device__ __forceinline__ uint16_t to_bf16(double x) {
 template <int MODE>
 __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_t tgt_global,
                                      int64_t tl, int64_t item, int64_t slot, const Draw& dr,
-                                     double conv) {
+                                     double conv, int& dlo, int& dhi) {
     const int64_t src_global = B.inst_n0 + B.src0_local + dr.src_in_pop;
     const double w = (conv != 1.0) ? dr.w * conv : dr.w;
     if (MODE == kCountTiles || MODE == kCountItems) {
-        atomicMin(&a.dminmax[0], dr.d);
-        atomicMax(&a.dminmax[1], dr.d);
+        dlo = min(dlo, dr.d);
+        dhi = max(dhi, dr.d);
     }
     if (MODE == kCountTiles || MODE == kFillTiles) {
         const int ntb = a.inst_ntiles[B.instance];
@@ -164,10 +164,14 @@ __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_
             const uint32_t k = atomicAdd(&a.cnt[key], 1u);
             const uint64_t pos = a.row_start[src_global] + a.off_rel[key] + k;
             const uint32_t m = (uint32_t)(tl - tile_local * Tb) + (uint32_t)(dr.d - a.dmin) * (uint32_t)a.T;
-            if (a.meta16) static_cast<uint16_t*>(a.meta)[pos] = (uint16_t)m;
-            else static_cast<uint32_t*>(a.meta)[pos] = m;
-            if (a.wbf16) static_cast<uint16_t*>(a.w)[pos] = to_bf16(w);
-            else static_cast<float*>(a.w)[pos] = (float)w;
+            if (a.wbf16) {
+                // packed record: bf16 weight in the high half, 16-bit record below
+                static_cast<uint32_t*>(a.meta)[pos] = ((uint32_t)to_bf16(w) << 16) | m;
+            } else {
+                if (a.meta16) static_cast<uint16_t*>(a.meta)[pos] = (uint16_t)m;
+                else static_cast<uint32_t*>(a.meta)[pos] = m;
+                static_cast<float*>(a.w)[pos] = (float)w;
+            }
             if (a.canon_out) a.canon_out[pos] = (uint32_t)(a.cin[tgt_global] + a.item_rel[item] + slot);
         }
     }
@@ -195,10 +199,13 @@ __global__ void __launch_bounds__(256) gen_kernel(GenArgs a, double conv) {
         const int64_t t_in_pop = item - a.blk_item0[lo];
         const int64_t tgt = B.tgt0 + t_in_pop;
         const int64_t tl = tgt - B.inst_n0;
+        // delay range of the item's synapses (count passes): kept per lane,
+        // reduced over the wave, one atomic per item
+        int dlo = 0x7FFFFFFF, dhi = 0;
         if (B.rule == CORTEX_RULE_FIXED_INDEGREE) {
             for (int64_t s = lane; s < B.k; s += 64) {
                 const Draw dr = draw_edge(B, a.seed, tl, s, t_in_pop, a.dt, -1);
-                emit<MODE>(a, B, tgt, tl, item, s, dr, conv);
+                emit<MODE>(a, B, tgt, tl, item, s, dr, conv, dlo, dhi);
             }
             if ((MODE == kCountTiles || MODE == kCountItems) && a.cnt_item && lane == 0)
                 a.cnt_item[item] = (uint32_t)B.k;
@@ -218,12 +225,23 @@ __global__ void __launch_bounds__(256) gen_kernel(GenArgs a, double conv) {
                     const uint64_t below = mask & ((1ull << lane) - 1ull);
                     const int64_t slot = run + (uint32_t)__popcll(below);
                     const Draw dr = draw_edge(B, a.seed, tl, slot, t_in_pop, a.dt, j);
-                    emit<MODE>(a, B, tgt, tl, item, slot, dr, conv);
+                    emit<MODE>(a, B, tgt, tl, item, slot, dr, conv, dlo, dhi);
                 }
                 run += (uint32_t)__popcll(mask);
             }
             if ((MODE == kCountTiles || MODE == kCountItems) && a.cnt_item && lane == 0)
                 a.cnt_item[item] = run;
+        }
+        if (MODE == kCountTiles || MODE == kCountItems) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                dlo = min(dlo, __shfl_xor(dlo, off, 64));
+                dhi = max(dhi, __shfl_xor(dhi, off, 64));
+            }
+            if (lane == 0 && dhi > 0) {
+                atomicMin(&a.dminmax[0], dlo);
+                atomicMax(&a.dminmax[1], dhi);
+            }
         }
     }
 }
@@ -257,6 +275,39 @@ __global__ void __launch_bounds__(256) row_scan_kernel(const uint32_t* cnt, uint
         if (lane == 0) {
             off_rel[base + nt] = carry;
             outdeg[j] = carry;
+        }
+    }
+}
+
+// Segment descriptors: seg[j][t] = (first synapse << 24) | length of the
+// synapses of source j into tile t, one 64-bit word per segment, so that a
+// kernel finds a segment with a single load (the entry after a row's last
+// tile is 0).  One wave per source row; *bad is set if a first synapse or a
+// length does not fit its field.
+__global__ void __launch_bounds__(256) seg_kernel(const uint64_t* row_start, const uint32_t* off_rel, uint64_t* seg,
+                                                  const int64_t* inst_n0, const uint64_t* inst_offbase,
+                                                  const int32_t* inst_ntiles, int n_inst, int64_t N, int32_t* bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < N; j += n_waves) {
+        int lo = 0, hi = n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (inst_n0[mid] <= j) lo = mid; else hi = mid;
+        }
+        const int nt = inst_ntiles[lo];
+        const uint64_t base = inst_offbase[lo] + (uint64_t)(j - inst_n0[lo]) * (uint64_t)(nt + 1);
+        const uint64_t rs = row_start[j];
+        for (int t = lane; t <= nt; t += 64) {
+            uint64_t v = 0;
+            if (t < nt) {
+                const uint64_t first = rs + off_rel[base + t];
+                const uint64_t len = off_rel[base + t + 1] - off_rel[base + t];
+                if (first >= (1ull << 40) || len >= (1ull << 24)) atomicOr(bad, 1);
+                v = (first << 24) | len;
+            }
+            seg[base + t] = v;
         }
     }
 }
@@ -509,9 +560,16 @@ __global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_star
         for (int t = 0; t < nt; ++t) {
             const int64_t g0 = inst_n0[lo] + (int64_t)t * inst_T[lo];
             for (uint64_t e = rs + off_rel[ob + t] + lane; e < rs + off_rel[ob + t + 1]; e += 64) {
-                const uint32_t m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
-                const float wv = wbf16 ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16)
-                                       : static_cast<const float*>(w)[e];
+                uint32_t m;
+                float wv;
+                if (wbf16) {
+                    const uint32_t r = static_cast<const uint32_t*>(meta)[e];
+                    m = r & 0xFFFFu;
+                    wv = __uint_as_float(r & 0xFFFF0000u);
+                } else {
+                    m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
+                    wv = static_cast<const float*>(w)[e];
+                }
                 atomicAdd(&sum[g0 + (m % (uint32_t)T)], (double)fabsf(wv));
                 atomicMax(wmax_bits, __float_as_uint(fabsf(wv)));   // non-negative floats order as integers
             }
@@ -554,11 +612,16 @@ __global__ void invert_kernel(const uint32_t* canon, uint32_t* inv, int64_t E) {
 }
 
 // Stored weight of every synapse from a canonical-order array (setup).
-__global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, void* w, int wbf16, int64_t E) {
+__global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, void* w, void* meta, int wbf16,
+                                   int64_t E) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
         const float v = w_canon[canon[e]];
-        if (wbf16) static_cast<uint16_t*>(w)[e] = to_bf16((double)v);
-        else static_cast<float*>(w)[e] = v;
+        if (wbf16) {
+            uint32_t* r = static_cast<uint32_t*>(meta) + e;
+            *r = (*r & 0xFFFFu) | ((uint32_t)to_bf16((double)v) << 16);
+        } else {
+            static_cast<float*>(w)[e] = v;
+        }
     }
 }
 }  // namespace
@@ -566,7 +629,7 @@ __global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, 
 void set_weights_fp32(cortex_net* n, const float* w_canonical) {
     if (n->E == 0) return;
     hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(n->E, 256)), dim3(256), 0, n->stream, w_canonical,
-                       n->d_canon, n->d_w, n->w_bytes == 2 ? 1 : 0, n->E);
+                       n->d_canon, n->d_w, n->d_meta, n->w_bytes == 2 ? 1 : 0, n->E);
     CX_HIP(hipGetLastError());
 }
 
@@ -607,14 +670,35 @@ void build_graph_fp32(cortex_net* n) {
     CX_HIP(hipMemcpyAsync(&E, n->d_row_start + n->N, sizeof E, hipMemcpyDeviceToHost, n->stream));
     CX_HIP(hipStreamSynchronize(n->stream));
     n->E = (int64_t)E;
+    // one-load segment descriptors for the step kernels
+    n->d_seg = dev_alloc_t<uint64_t>(n, cnt_len);
+    {
+        int32_t* bad = dev_alloc_t<int32_t>(n, 1, true);
+        dev_zero(n, bad, sizeof(int32_t));
+        hipLaunchKernelGGL(seg_kernel, dim3(grid_for(n->N * 64, 256)), dim3(256), 0, n->stream, n->d_row_start,
+                           n->d_off_rel, n->d_seg, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->n_inst,
+                           n->N, bad);
+        CX_HIP(hipGetLastError());
+        int32_t hb = 0;
+        CX_HIP(hipMemcpyAsync(&hb, bad, sizeof hb, hipMemcpyDeviceToHost, n->stream));
+        CX_HIP(hipStreamSynchronize(n->stream));
+        require(hb == 0, CORTEX_EUNSUPPORTED, "a segment is too long (2^24 synapses) or lies past 2^40");
+    }
     // record format
     // a record is (delay - dmin) T + target: every record is below R T
     const uint64_t rt = (uint64_t)n->R * (uint64_t)n->T;
     require(rt <= 0xFFFFFFFFull, CORTEX_EUNSUPPORTED, "tile size and delay range too large for 32-bit records");
     n->meta_bytes = (rt <= 65536) ? 2 : 4;
     n->w_bytes = (n->spec.weight_dtype == CORTEX_W_BF16) ? 2 : 4;
-    n->d_meta = dev_alloc(n, (size_t)n->E * n->meta_bytes + 16);
-    n->d_w = dev_alloc(n, (size_t)n->E * n->w_bytes + 16);
+    if (n->w_bytes == 2) {
+        // bf16 weights: one packed 32-bit word per synapse
+        require(n->meta_bytes == 2, CORTEX_EUNSUPPORTED, "bf16 weights need 16-bit records (R x T <= 65536)");
+        n->d_meta = dev_alloc(n, (size_t)n->E * 4 + 16);
+        n->d_w = nullptr;
+    } else {
+        n->d_meta = dev_alloc(n, (size_t)n->E * n->meta_bytes + 16);
+        n->d_w = dev_alloc(n, (size_t)n->E * n->w_bytes + 16);
+    }
     uint32_t* item_rel = nullptr;
     uint64_t* cin = nullptr;
     if (need_canon) {

@@ -68,6 +68,17 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// What the planner needs to know of the device: compute units, LDS bytes and
+// resident threads per compute unit, and whether kernel occupancy can be
+// asked of the runtime (a live device) or must be estimated from LDS and
+// threads alone (host-only planning).
+struct DeviceDesc {
+    int n_cu = 256;
+    size_t lds_cu = 163840;
+    int thr_cu = 2048;
+    bool live = false;
+};
+
 }  // namespace cortex
 
 // Network object ----------------------------------------------------------------
@@ -123,6 +134,7 @@ struct cortex_net {
     // production graph
     uint64_t* d_row_start = nullptr;   // [N+1]
     uint32_t* d_off_rel = nullptr;     // [sum_b N_b (nt_b + 1)]
+    uint64_t* d_seg = nullptr;         // same index: (first synapse << 24) | length of segment (source, tile)
     void* d_meta = nullptr;            // u16/u32 [E]
     void* d_w = nullptr;               // f32/bf16 [E]
     uint32_t* d_canon = nullptr;       // [E] canonical index of each stored synapse (adjoint)
@@ -147,7 +159,10 @@ struct cortex_net {
     uint32_t* d_spk_ids = nullptr;     // [H][N]
     int64_t* d_clock = nullptr;        // [2]
     int32_t* d_order = nullptr;        // [n_tiles]
+    std::vector<int32_t> order;        // streamed plan: tile of each workgroup
+    cortex::DeviceDesc dd;
     int clock_parity = 0;
+    int thread_segments = 0;           // streamed delivery with one thread per (short) segment
     bool use_graph = true;
     hipGraphExec_t graph_exec = nullptr;   // kGraphWindows window launches
     hipStream_t graph_stream = nullptr;    // library stream the graph is captured on and replayed on
@@ -223,6 +238,12 @@ int step_max_blocks_per_cu(cortex_net* n);
 // Resident workgroups per CU of the step kernel variant for a model, record
 // format, neurons per thread, workgroup size and LDS bytes (0 if none fit).
 int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds, int ring_bytes);
+// api.hip: advance an FP32 network by n_steps (frozen lists and traces
+// indexed from its current step; launches split at adjoint checkpoints), and
+// raise CORTEX_ETIMEOUT if a device-side wait failed (synchronising)
+void advance_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,
+                  uint64_t frz_n, float* x_trace, float* v_trace);
+void check_device_flag(cortex_net* n);
 // verify.hip
 void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits,
                       double* x_trace, double* v_trace);

@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "deliver.hpp"
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -39,7 +40,6 @@ namespace {
 
 constexpr int kMaxThr = 32;       // Poisson table entries in kernel arguments
 constexpr int kInline = 1;        // spike ids fetched together with a tile's step record
-constexpr int kBlk = 512;         // 64-synapse blocks per piece of a delivery chunk (short segments)
 
 struct StepArgs {
     const int32_t* inst_tile0;
@@ -49,8 +49,7 @@ struct StepArgs {
     const uint64_t* inst_offbase;
     const int32_t* tile_inst;
     const int32_t* tile_size;
-    const uint64_t* row_start;
-    const uint32_t* off_rel;
+    const uint64_t* seg;        // (first synapse << 24) | length per (source, tile)
     const void* meta;
     const void* w;
     float* U;
@@ -80,11 +79,6 @@ struct StepArgs {
     uint64_t seed;
     uint32_t thr[kMaxThr];
 };
-
-__device__ __forceinline__ float load_w(const void* w, uint64_t e, bool bf16) {
-    if (bf16) return __uint_as_float((uint32_t)static_cast<const uint16_t*>(w)[e] << 16);
-    return static_cast<const float*>(w)[e];
-}
 
 __device__ __forceinline__ uint64_t coherent_load(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -150,7 +144,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     uint32_t* s_frz = reinterpret_cast<uint32_t*>(s_kw + 20);      // T (bit si: frozen spike at step si)
     uint32_t* s_thr = s_frz + T;                                    // kMaxThr Poisson thresholds
     unsigned char* s_kcb = reinterpret_cast<unsigned char*>(s_thr + kMaxThr);  // 2 x 8 x T Poisson counts
-    uint32_t* s_blk = reinterpret_cast<uint32_t*>(s_kcb + (size_t)16 * T);        // kBlk
+    uint32_t* s_blk = reinterpret_cast<uint32_t*>(s_kcb + (size_t)16 * T);        // kDeliverBlk
 
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
@@ -349,12 +343,11 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         s_len[k] = 0;
                         continue;
                     }
-                    const uint64_t rs = a.row_start[j];
-                    const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-                    const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
-                    const uint64_t beg = rs + o0;
-                    s_sg[k] = make_uint4(o1 - o0, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
-                    s_len[k] = o1 - o0;
+                    const uint64_t d = a.seg[offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl];
+                    const uint32_t len = (uint32_t)(d & 0xFFFFFFu);
+                    const uint64_t beg = d >> 24;
+                    s_sg[k] = make_uint4(len, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
+                    s_len[k] = len;
                 }
                 if (bail) {
                     s_misc[1] = 1;
@@ -363,138 +356,15 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 __syncthreads();
                 if (s_misc[1]) break;
                 const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
-                const uint32_t share = (EL + n_waves - 1) / n_waves;
-                // s_kw[w] = first segment k with s_len[k] >= min(EL, w share):
-                // segment k owns the share boundaries in (s_len[k - 1], s_len[k]]
-                for (int k = tid; k <= cn; k += bs) {
-                    const int64_t lo = k == 0 ? -1 : (int64_t)s_len[k - 1];
-                    const uint32_t hi = k < cn ? s_len[k] : EL;
-                    for (int w = 0; w <= n_waves; ++w) {
-                        const uint32_t tw = min(EL, (uint32_t)w * share);
-                        if ((int64_t)tw > lo && tw <= hi) s_kw[w] = k;
-                    }
-                }
-                if (tid == 0) s_len[cn] = EL;
+                wave_runs(s_len, s_kw, cn, EL, n_waves, tid, bs);
                 __syncthreads();
-                // Each wave takes a contiguous run of whole segments holding
-                // about EL / n_waves synapses (a segment belongs to the wave
-                // whose share contains its first synapse).  It reads the
-                // descriptors of 8 segments at once; lane l handles synapses
-                // l, l + 64, ... of each, so the loads of a segment are
-                // contiguous and the spike's step offset is the same for the
-                // whole wave.
-                const int kw0 = s_kw[wave], kw1 = s_kw[wave + 1];
-                if (EL >= 32u * (uint32_t)cn) {
-                    // Long segments.  A segment's descriptor is the same for
-                    // the whole wave, so its first synapse, length and ring
-                    // row offset live in scalar registers and each lane only
-                    // adds its 32-bit position.  A record r = delta T + target
-                    // lands at (r + (base_slot + y) T) mod R T.
-                    const int kb = __builtin_amdgcn_readfirstlane(kw0);
-                    const int ke = __builtin_amdgcn_readfirstlane(kw1);
-                    for (int k0 = kb; k0 < ke; k0 += 8) {
-                        constexpr int U8 = 8;
-                        const unsigned char* mp[U8];
-                        const unsigned char* wp[U8];
-                        uint32_t len[U8], roff[U8];
-                        uint32_t len_max = 0;
-                        // all eight descriptors are read before any is used
-                        // (past the run's end the last one is re-read and
-                        // given length 0)
-                        uint4 gd[U8];
-#pragma unroll
-                        for (int u = 0; u < U8; ++u) gd[u] = s_sg[min(k0 + u, ke - 1)];
-#pragma unroll
-                        for (int u = 0; u < U8; ++u) {
-                            const uint4 g = gd[u];
-                            len[u] = k0 + u < ke ? __builtin_amdgcn_readfirstlane(g.x) : 0u;
-                            const uint32_t y = __builtin_amdgcn_readfirstlane(g.y);
-                            const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane(g.w) << 32) |
-                                                __builtin_amdgcn_readfirstlane(g.z);
-                            mp[u] = static_cast<const unsigned char*>(a.meta) + e0 * sizeof(META);
-                            wp[u] = static_cast<const unsigned char*>(a.w) + e0 * (WBF16 ? 2 : 4);
-                            roff[u] = (uint32_t)(base_slot + (int)y) * (uint32_t)T;
-                            len_max = max(len_max, len[u]);
-                        }
-                        for (uint32_t o0 = 0; o0 < len_max; o0 += 64u) {
-                            const uint32_t o = o0 + (uint32_t)lane;
-                            uint32_t m[U8];
-                            float wv[U8];
-#pragma unroll
-                            for (int u = 0; u < U8; ++u) {
-                                // m[u] and wv[u] are read below under the same condition
-                                if (o < len[u]) {
-                                    m[u] = *reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META));
-                                    wv[u] = WBF16 ? __uint_as_float((uint32_t)*reinterpret_cast<const uint16_t*>(wp[u] + o * 2u) << 16)
-                                                  : *reinterpret_cast<const float*>(wp[u] + o * 4u);
-                                }
-                            }
-#pragma unroll
-                            for (int u = 0; u < U8; ++u) {
-                                if (o < len[u]) {
-                                    uint32_t x = m[u] + roff[u];
-                                    x = min(x, x - RT);
-                                    // the weight rounded to a 32-bit fixed-point value
-                                    const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
-                                    if (sizeof(RING) == 8)
-                                        atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), (unsigned long long)(long long)iw);
-                                    else
-                                        atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
-                                }
-                            }
-                        }
-                    }
-                } else {
-                    // short segments: lanes take consecutive synapses of the
-                    // flattened space (stride 64); s_blk[b] is the segment
-                    // holding synapse 64 b, from which a lane walks forward
-                    for (uint32_t pc0 = 0; pc0 < EL; pc0 += 64u * kBlk) {
-                        const uint32_t pc1 = min(EL, pc0 + 64u * kBlk);
-                        for (int k = tid; k < cn; k += bs) {
-                            const uint32_t lo = max(s_len[k], pc0), hi = min(s_len[k + 1], pc1);
-                            for (uint32_t bb = (lo + 63u) >> 6; (bb << 6) < hi; ++bb)
-                                s_blk[bb - (pc0 >> 6)] = (uint32_t)k;
-                        }
-                        __syncthreads();
-                        const uint32_t per = ((pc1 - pc0 + n_waves - 1) / n_waves + 63) & ~63u;
-                        const uint32_t f_beg = pc0 + min(pc1 - pc0, (uint32_t)wave * per);
-                        const uint32_t f_end = min(pc1, f_beg + per);
-                        for (uint32_t f = f_beg + lane; f < f_end; f += 64u * 8u) {
-                            constexpr int U8 = 8;
-                            uint32_t m[U8], q[U8];
-                            float wv[U8];
-#pragma unroll
-                            for (int u = 0; u < U8; ++u) {
-                                const uint32_t fu = f + 64u * u;
-                                m[u] = 0;
-                                wv[u] = 0.f;
-                                q[u] = 0;
-                                if (fu < f_end) {
-                                    int seg = (int)s_blk[((fu - (uint32_t)lane) - pc0) >> 6];
-                                    while (s_len[seg + 1] <= fu) ++seg;
-                                    const uint4 g = s_sg[seg];
-                                    const uint64_t e = (((uint64_t)g.w << 32) | g.z) + (fu - s_len[seg]);
-                                    q[u] = g.y | 8u;
-                                    m[u] = static_cast<const META*>(a.meta)[e];
-                                    wv[u] = load_w(a.w, e, WBF16);
-                                }
-                            }
-#pragma unroll
-                            for (int u = 0; u < U8; ++u) {
-                                if (q[u] & 8u) {
-                                    uint32_t x = m[u] + (uint32_t)(base_slot + (int)(q[u] & 7u)) * (uint32_t)T;
-                                    x = min(x, x - RT);
-                                    const int32_t iw = __float2int_rn(wv[u] * a.fxw_scale);
-                                    if (sizeof(RING) == 8)
-                                        atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), (unsigned long long)(long long)iw);
-                                    else
-                                        atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
-                                }
-                            }
-                        }
-                        __syncthreads();   // s_blk is refilled for the next piece
-                    }
-                }
+                if (EL >= 32u * (uint32_t)cn)
+                    deliver_long<META, WBF16, RING>(s_sg, ring, s_kw[wave], s_kw[wave + 1], lane, a.meta, a.w,
+                                                    base_slot, (uint32_t)T, RT, a.fxw_scale);
+                else
+                    deliver_short<META, WBF16, RING>(s_sg, s_len, s_blk, ring, cn, EL, tid, bs, lane, wave,
+                                                     n_waves, a.meta, a.w, base_slot, (uint32_t)T, RT,
+                                                     a.fxw_scale);
                 ev += EL;
                 __syncthreads();
             }
@@ -613,12 +483,12 @@ KernelFn pick_npt(int npt) {
     return step_kernel<MODEL, META, WBF16, 4, RING>;
 }
 
+// Record formats: 16- or 32-bit records with fp32 weights, or packed 32-bit
+// words (16-bit record, bf16 weight); bf16 weights need 16-bit records.
 template <int MODEL, typename RING>
 KernelFn pick_fmt(int meta_bytes, int w_bytes, int npt) {
-    if (meta_bytes == 2) {
-        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true, RING>(npt) : pick_npt<MODEL, uint16_t, false, RING>(npt);
-    }
-    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true, RING>(npt) : pick_npt<MODEL, uint32_t, false, RING>(npt);
+    if (w_bytes == 2) return meta_bytes == 2 ? pick_npt<MODEL, uint16_t, true, RING>(npt) : nullptr;
+    return meta_bytes == 2 ? pick_npt<MODEL, uint16_t, false, RING>(npt) : pick_npt<MODEL, uint32_t, false, RING>(npt);
 }
 
 template <typename RING>
@@ -636,7 +506,9 @@ KernelFn pick_variant(int model, int meta_bytes, int w_bytes, int npt, int ring_
 }
 
 KernelFn pick_kernel(const cortex_net* n) {
-    return pick_variant(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT, n->ring_bytes);
+    KernelFn f = pick_variant(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT, n->ring_bytes);
+    require(f != nullptr, CORTEX_EUNSUPPORTED, "no step kernel for this record format");
+    return f;
 }
 
 }  // namespace
@@ -653,12 +525,13 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_b
     b += (size_t)T * 4;                           // s_frz
     b += (size_t)kMaxThr * 4;                     // s_thr
     b += (size_t)16 * T;                          // s_kcb
-    b += (size_t)kBlk * 4;                        // s_blk
+    b += (size_t)kDeliverBlk * 4;                 // s_blk
     return (b + 15) & ~(size_t)15;
 }
 
 int step_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds, int ring_bytes) {
     KernelFn f = pick_variant(model, meta_bytes, w_bytes, npt, ring_bytes);
+    if (!f) return 0;
     if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int nb = 0;
@@ -688,8 +561,7 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     a.inst_offbase = n->d_inst_offbase;
     a.tile_inst = n->d_tile_inst;
     a.tile_size = n->d_tile_size;
-    a.row_start = n->d_row_start;
-    a.off_rel = n->d_off_rel;
+    a.seg = n->d_seg;
     a.meta = n->d_meta;
     a.w = n->d_w;
     a.U = n->d_U;

@@ -47,8 +47,7 @@ struct StreamArgs {
     const int32_t* inst_T;
     const int64_t* inst_n0;
     const uint64_t* inst_offbase;
-    const uint64_t* row_start;
-    const uint32_t* off_rel;
+    const uint64_t* seg;           // (first synapse << 24) | length per (source, tile)
     const void* meta;
     const void* w;
     float* U;
@@ -75,6 +74,7 @@ struct StreamArgs {
     int64_t trace_step0;
     int64_t log_step0, log_steps, N;
     int parity, wn;
+    int thread_segments;           // segments of a few synapses: one thread per segment
     int n_tiles, n_inst, T, R, dmin, H, W, chunk, n_ref, n_thr;
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
     float fxw_scale;
@@ -102,6 +102,106 @@ size_t stream_lds_bytes(int R, int T, int W, int chunk) {
 }
 
 namespace {
+
+// Short segments (a few synapses each, e.g. two million neurons in tiles of
+// about a thousand) without workgroup-wide staging: every wave takes 64
+// spikes at a time, one per lane.  A lane loads its spike's segment
+// descriptor (one 64-bit word), a DPP scan over the wave gives the segments'
+// offsets in the wave's flattened synapse range, the lanes publish (first
+// synapse, offset, ring row) in the wave's own LDS slots, and then lane l
+// takes synapses l, l + 64, ... of the range (contiguous loads within each
+// segment), finding its segment by binary search over the 64 offsets.  No
+// workgroup barrier.  Returns the wave's synaptic events (in every lane).
+template <typename META, bool WBF16>
+__device__ __forceinline__ uint32_t deliver_waves(const StreamArgs& a, int32_t* ring, const uint32_t* s_pc, int nq,
+                                                  int64_t q_lo, int64_t n0b, uint64_t offb, int ntb, int tl,
+                                                  int base_slot, uint32_t RT, int lane, int wave, int n_waves,
+                                                  uint4* s_wv) {
+    const uint32_t S = s_pc[nq];
+    const uint32_t T = (uint32_t)a.T;
+    uint4* my = s_wv + 64 * wave;   // this wave's 64 segment slots
+    uint32_t ev = 0;
+    // D rounds of 64 spikes per wave: their ids and descriptors are loaded
+    // together before the first round's synapses
+    constexpr int D = 4;
+    const uint32_t stride = (uint32_t)n_waves * 64u;
+    for (uint32_t kd = (uint32_t)wave * 64u; kd < S; kd += D * stride) {
+        uint32_t len[D], roff[D];
+        uint64_t beg[D];
+        uint32_t j[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const uint32_t k = kd + (uint32_t)r * stride + (uint32_t)lane;
+            j[r] = 0xFFFFFFFFu;
+            roff[r] = 0;
+            if (k < S) {
+                int qi = 0;
+                while (qi + 1 < nq && s_pc[qi + 1] <= k) ++qi;
+                j[r] = a.spk_ids[(size_t)((q_lo + qi) & (a.H - 1)) * a.N + n0b + (k - s_pc[qi])];
+                roff[r] = (uint32_t)(base_slot + qi) * T;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            len[r] = 0;
+            beg[r] = 0;
+            if (j[r] != 0xFFFFFFFFu) {
+                const uint64_t d = a.seg[offb + (uint64_t)(j[r] - n0b) * (uint64_t)(ntb + 1) + tl];
+                len[r] = (uint32_t)(d & 0xFFFFFFu);
+                beg[r] = d >> 24;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const uint32_t incl = wave_incl_scan(len[r]);
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            if (total == 0) continue;   // wave-uniform
+            ev += total;
+            // the slots are rewritten only after every lane has read the
+            // previous round's (the wave executes in lockstep; the barriers
+            // and fences keep the LDS accesses of this wave in order)
+            __builtin_amdgcn_wave_barrier();
+            my[lane] = make_uint4(incl - len[r], roff[r], (uint32_t)beg[r], (uint32_t)(beg[r] >> 32));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            constexpr int U = 4;
+            for (uint32_t f0 = (uint32_t)lane; f0 < total; f0 += 64u * U) {
+                uint32_t m[U], x0[U];
+                float wv[U];
+                bool ok[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t f = f0 + 64u * u;
+                    ok[u] = f < total;
+                    m[u] = 0;
+                    wv[u] = 0.f;
+                    x0[u] = 0;
+                    if (ok[u]) {
+                        // last slot whose offset is <= f
+                        int lo = 0, hi = 64;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (my[mid].x <= f) lo = mid; else hi = mid;
+                        }
+                        const uint4 g = my[lo];
+                        x0[u] = g.y;
+                        load_rec<META, WBF16>(a.meta, a.w, (((uint64_t)g.w << 32) | g.z) + (f - g.x), m[u], wv[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (ok[u]) {
+                        uint32_t x = m[u] + x0[u];
+                        x = min(x, x - RT);
+                        ring_add(ring, x, __float2int_rn(wv[u] * a.fxw_scale));
+                    }
+                }
+            }
+        }
+    }
+    return ev;
+}
 
 template <int MODEL, typename META, bool WBF16, int NPT>
 __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
@@ -166,6 +266,7 @@ __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
     for (int i = tid; i < T; i += bs) s_frz[i] = 0;
     if (tid < kMaxThr) s_thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xFFFFFFFFu;
     if (tid < kMaxW) s_cnt[tid] = 0;
+    if (tid == 0) s_misc[7] = 0;
     // spikes of the delivered steps [q_lo, q_hi) of this instance
     const int64_t q_hi = t0 - a.dmin + wn;
     const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
@@ -195,19 +296,26 @@ __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
     const uint32_t S = s_pc[nq];
     const int base_slot = (int)((q_lo + a.dmin) % R);
     uint64_t ev = 0;
-    for (uint32_t c0 = 0; c0 < S; c0 += CH) {
+    if (a.thread_segments) {
+        // the descriptor area holds the waves' segment slots (16 x 64 x 16 B)
+        const uint32_t wev = deliver_waves<META, WBF16>(a, ring, s_pc, nq, q_lo, n0b, offb, ntb, tl, base_slot, RT,
+                                                        lane, wave, n_waves, s_sg);
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned int*>(&s_misc[7]), wev);
+        __syncthreads();
+        ev = (uint32_t)s_misc[7];
+    }
+    for (uint32_t c0 = 0; c0 < (a.thread_segments ? 0u : S); c0 += CH) {
         const int cn = (int)min((uint32_t)CH, S - c0);
         for (int k = tid; k < cn; k += bs) {
             const uint32_t kk = c0 + k;
             int qi = 0;
             while (qi + 1 < nq && s_pc[qi + 1] <= kk) ++qi;
             const uint32_t j = a.spk_ids[(size_t)((q_lo + qi) & (H - 1)) * a.N + n0b + (kk - s_pc[qi])];
-            const uint64_t rs = a.row_start[j];
-            const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-            const uint32_t o0 = a.off_rel[ob], o1 = a.off_rel[ob + 1];
-            const uint64_t beg = rs + o0;
-            s_sg[k] = make_uint4(o1 - o0, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
-            s_len[k] = o1 - o0;
+            const uint64_t d = a.seg[offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl];
+            const uint32_t len = (uint32_t)(d & 0xFFFFFFu);
+            const uint64_t beg = d >> 24;
+            s_sg[k] = make_uint4(len, (uint32_t)qi, (uint32_t)beg, (uint32_t)(beg >> 32));
+            s_len[k] = len;
         }
         __syncthreads();
         const uint32_t EL = block_excl_scan(s_len, cn, s_wsum);
@@ -338,11 +446,11 @@ StreamFn pick_npt(int npt) {
     return stream_kernel<MODEL, META, WBF16, 4>;
 }
 
+// bf16 weights come packed with 16-bit records (see deliver.hpp)
 template <int MODEL>
 StreamFn pick_fmt(int meta_bytes, int w_bytes, int npt) {
-    if (meta_bytes == 2)
-        return w_bytes == 2 ? pick_npt<MODEL, uint16_t, true>(npt) : pick_npt<MODEL, uint16_t, false>(npt);
-    return w_bytes == 2 ? pick_npt<MODEL, uint32_t, true>(npt) : pick_npt<MODEL, uint32_t, false>(npt);
+    if (w_bytes == 2) return meta_bytes == 2 ? pick_npt<MODEL, uint16_t, true>(npt) : nullptr;
+    return meta_bytes == 2 ? pick_npt<MODEL, uint16_t, false>(npt) : pick_npt<MODEL, uint32_t, false>(npt);
 }
 
 StreamFn pick_stream(int model, int meta_bytes, int w_bytes, int npt) {
@@ -357,6 +465,7 @@ StreamFn pick_stream(int model, int meta_bytes, int w_bytes, int npt) {
 
 int stream_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds) {
     StreamFn f = pick_stream(model, meta_bytes, w_bytes, npt);
+    if (!f) return 0;
     if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int nb = 0;
@@ -379,8 +488,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.inst_T = n->d_inst_T;
     a.inst_n0 = n->d_inst_n0;
     a.inst_offbase = n->d_inst_offbase;
-    a.row_start = n->d_row_start;
-    a.off_rel = n->d_off_rel;
+    a.seg = n->d_seg;
     a.meta = n->d_meta;
     a.w = n->d_w;
     a.U = n->d_U;
@@ -418,6 +526,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.chunk = n->chunk;
     a.n_ref = n->k.n_ref;
     a.n_thr = n->n_thr;
+    a.thread_segments = n->thread_segments;
     a.P22 = (float)n->k.P22;
     a.P20Ie = (float)(n->k.P20 * n->spec.I_e);
     a.P11 = (float)n->k.P11;
@@ -450,6 +559,7 @@ void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                         uint64_t frz_n, float* x_trace, float* v_trace, uint8_t* m_trace) {
     if (n_steps <= 0) return;
     StreamFn f = pick_stream(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT);
+    require(f != nullptr, CORTEX_EUNSUPPORTED, "no streamed kernel for this record format");
     CX_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds_bytes));
     const int64_t first = n->step;
     StreamArgs a = stream_args(n, frz_ids, frz_ptr, frz_n, first, x_trace, v_trace, m_trace, first);

@@ -36,7 +36,9 @@ def bf16_rne(x):
 WORKLOADS = {
     # name: (spec factory, seed, steps)
     "brunel_112k_alpha": (netspec.brunel_112k_alpha, 2, 10000),
-    "microcircuit_77k": (netspec.microcircuit_77k, 3, 10000),
+    # 5 s: the smallest population (1,543 neurons at about 3 Hz) then gives
+    # about 22,000 spikes, a rate known to 0.7 %
+    "microcircuit_77k": (netspec.microcircuit_77k, 3, 50000),
     # same in-degree as the two-million-neuron bf16 network, 1 % / 5 % of
     # its neurons (a surrogate: the full size does not fit the host)
     "brunel_2m_bf16_surrogate_20k": (lambda: netspec.brunel_2m_bf16(scale_n=0.01), 5, 10000),
@@ -65,7 +67,7 @@ def main(name: str) -> None:
         o.set_weights(bf16_rne(w))
         del w
     t0 = time.time()
-    chunk = 500
+    chunk = 2500
     for s in range(0, steps, chunk):
         o.run(min(chunk, steps - s))
         print(f"[golden] {name}: step {s + chunk}/{steps} ({time.time() - t0:.0f} s)", flush=True)

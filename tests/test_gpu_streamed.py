@@ -37,8 +37,11 @@ def _open_loop(cx, orc, spec, T, p, seed, **plan):
     return g, x.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64), xo, vo, B
 
 
+# tiles of 128 and 64: segments of about 13 and 6 synapses (one thread per
+# segment); the others: descriptor chunks
 @pytest.mark.parametrize("model,d0,d1,tile", [("delta", 5, 30, 256), ("exp", 1, 12, 200), ("alpha", 5, 30, 512),
-                                              ("alpha", 1, 1, 1024), ("delta", 3, 3, 128)])
+                                              ("alpha", 1, 1, 1024), ("delta", 3, 3, 128), ("exp", 5, 30, 64),
+                                              ("alpha", 2, 9, 128)])
 def test_streamed_open_loop_matches_oracle(cx, orc, model, d0, d1, tile):
     spec = netspec.small_brunel(model=model, n_e=2400, n_i=600, c_e=240, c_i=60, delay="uniform_int",
                                 d0=d0, d1=d1, w_rel_sd=0.1, weight_unit="psp_mV")
@@ -62,14 +65,16 @@ def test_streamed_batched_instances_open_loop(cx, orc):
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
 
 
-@pytest.mark.parametrize("steps_per_sync", [0, 1, 3])
-def test_streamed_integer_weights_exact_across_calls(cx, orc, steps_per_sync):
+# tile 300: segments of about 30 synapses (descriptor chunks); tile 100:
+# about 10 (one thread per segment)
+@pytest.mark.parametrize("steps_per_sync,tile", [(0, 300), (1, 300), (3, 300), (0, 100), (2, 100)])
+def test_streamed_integer_weights_exact_across_calls(cx, orc, steps_per_sync, tile):
     spec = netspec.small_brunel(n_e=1600, n_i=400, c_e=160, c_i=40, delay="uniform_int", d0=3, d1=17,
                                 w_rel_sd=0.0, J=1.0, g=2.0)
     T = 160
     steps, ids = netspec.synthetic_raster(2000, T, 0.02, seed=21)
     case(f"streamed integer weights, split calls, steps_per_sync={steps_per_sync}")
-    g = cx.Network(spec, 17, plan="streamed", tile_size=300, steps_per_sync=steps_per_sync)
+    g = cx.Network(spec, 17, plan="streamed", tile_size=tile, steps_per_sync=steps_per_sync)
     o = orc.OracleNet(spec, 17)
     xo, _ = o.run_frozen(steps, ids, T)
     parts = [g.run_frozen(steps, ids, k)[0].cpu().numpy() for k in (1, 63, 16, 80)]
@@ -147,7 +152,7 @@ def test_full_size_two_million_neurons_bf16(cx, orc):
     oracle surrogate (the full network does not fit the host)."""
     import json
     import os
-    from tests.golden.make_closed_loop_stats import bf16_rne, spec_hash
+    from tests.golden.make_closed_loop_stats import bf16_rne
     spec = netspec.brunel_2m_bf16()
     N, T = spec.n_neurons, 60
     case("2M neurons bf16: build (streamed plan)")
