@@ -235,6 +235,18 @@ int cortex_backward(cortex_net* net, const float* vstar, float* grad_w, double* 
    EUNSUPPORTED (FP64 networks), EINVAL (NULL). */
 int cortex_set_weights(cortex_net* net, const float* w_canonical);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   cortex_run_frozen without any device allocation.  Same arguments, results
+   and errors as cortex_run_frozen, FP32 networks only (EUNSUPPORTED for
+   FP64).  The raster and its per-step list offsets go to a fixed device
+   array of 32 MiB held by the library on each GPU until the process ends;
+   (n_steps x tiles + 1) x 8 + n_spikes x 8 bytes (each part rounded up to 256)
+   must fit it, else EINVAL.  Every call on a GPU shares that GPU's array:
+   calls that overlap on one GPU race.  Synchronising. */
+int cortex_run_frozen_noalloc(cortex_net* net, const uint32_t* r_steps, const uint32_t* r_ids,
+                              int64_t n_spikes, int64_t n_steps, void* x_trace, void* v_trace);
+
 /* Passage: the initial state of the simulation of Sec. II-B.
    Back to the build-time state (step 0, empty input rings, empty log). */
 int cortex_reset(cortex_net* net);

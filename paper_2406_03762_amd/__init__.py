@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
         L.cortex_get_spikes.argtypes = [P, i64, i64, P, P, i64, C.POINTER(i64)]
         L.cortex_clear_spikes.argtypes = [P]
         L.cortex_run_frozen.argtypes = [P, P, P, i64, i64, P, P]
+        L.cortex_run_frozen_noalloc.argtypes = [P, P, P, i64, i64, P, P]
         L.cortex_backward.argtypes = [P, P, P, C.POINTER(C.c_double)]
         L.cortex_set_weights.argtypes = [P, P]
         L.cortex_reset.argtypes = [P]
@@ -292,6 +293,18 @@ def cortex_run_frozen(h, steps, ids, n_steps: int, x_trace=None, v_trace=None, f
     vp = _dev_ptr(v_trace, "v_trace", dt, n_steps * N, device)
     _check(lib().cortex_run_frozen(h, st.ctypes.data if len(st) else None,
                                    ii.ctypes.data if len(ii) else None, len(st), n_steps, xp, vp))
+
+
+def cortex_run_frozen_noalloc(h, steps, ids, n_steps: int, x_trace=None, v_trace=None, device=None) -> None:
+    """cortex_run_frozen without device allocation (FP32 networks; the raster
+    must fit the library's fixed scratch array)."""
+    import torch
+    st, ii = _raster(steps, ids)
+    N = _net_facts(h)[0]
+    xp = _dev_ptr(x_trace, "x_trace", torch.float32, n_steps * N, device)
+    vp = _dev_ptr(v_trace, "v_trace", torch.float32, n_steps * N, device)
+    _check(lib().cortex_run_frozen_noalloc(h, st.ctypes.data if len(st) else None,
+                                           ii.ctypes.data if len(ii) else None, len(st), n_steps, xp, vp))
 
 
 def cortex_set_weights(h, w_canonical, device=None) -> None:

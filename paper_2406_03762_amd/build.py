@@ -21,6 +21,7 @@ SOURCES = [
     ("step.hip", []),
     ("adjoint.hip", []),
     ("stream.hip", []),
+    ("noalloc.hip", []),
 ]
 
 ARCH = os.environ.get("CORTEX_OFFLOAD_ARCH", "gfx950")
