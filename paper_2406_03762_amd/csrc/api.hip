@@ -567,8 +567,10 @@ static void plan_stream(cortex_net* n) {
     n->R = n->dmax - n->dmin + n->W;
     n->H = pow2_at_least(n->dmin + 2 * n->W);
     n->ring_bytes = 4;
+    // one workgroup of 1024 threads per compute unit, or several of 512
+    const int BS = s.block_size ? s.block_size : (per_cu >= 2 ? 512 : 1024);
     // descriptor slots: a chunk, or 64 per wave of the wave-flattened mapping
-    n->chunk = 1024;
+    n->chunk = std::max(512, BS);
     int Tmax = 0;
     for (int t = 4; t <= 4096; t += 4)
         if (stream_lds_bytes(n->R, t, n->W, n->chunk) * per_cu <= lds_cu) Tmax = t;
@@ -578,14 +580,13 @@ static void plan_stream(cortex_net* n) {
                 "tile_size too large for the streamed plan's workgroup-local memory");
         Tmax = s.tile_size;
     }
-    // one neuron per thread of a 1024-thread workgroup when the ring allows
-    // it: a thread with two neurons doubles the update's critical path
-    if (s.tile_size == 0 && s.block_size == 0 && Tmax > 1024 && Tmax < 2048) Tmax = 1024;
+    // one neuron per thread when the ring allows only a few more: a thread
+    // with two neurons doubles the update's critical path
+    if (s.tile_size == 0 && Tmax > BS && Tmax < 2 * BS) Tmax = BS;
     std::vector<int32_t> Tb(n->n_inst);
     for (int b = 0; b < n->n_inst; ++b) Tb[b] = (int32_t)std::min<int64_t>(Tmax, n->inst_N[b]);
     const int Tm = *std::max_element(Tb.begin(), Tb.end());
     n->T = (Tm + 3) & ~3;
-    int BS = s.block_size ? s.block_size : (n->T >= 1024 ? 1024 : (n->T >= 512 ? 512 : 256));
     int npt = (n->T + BS - 1) / BS;
     if (npt == 3) npt = 4;
     require(npt <= 4, CORTEX_EINVAL, "tile_size must be at most 4 x block_size");
