@@ -73,10 +73,14 @@ __device__ __forceinline__ void deliver_long(const uint4* s_sg, RING* ring, int 
 #pragma unroll
         for (int u = 0; u < U8; ++u) {
             const uint4 g = gd[u];
-            len[u] = k0 + u < ke ? __builtin_amdgcn_readfirstlane(g.x) : 0u;
-            const uint32_t y = __builtin_amdgcn_readfirstlane(g.y);
-            const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane(g.w) << 32) |
-                                __builtin_amdgcn_readfirstlane(g.z);
+            // readfirstlane yields a signed int: every word goes through
+            // uint32_t, or a first synapse at or past 2^31 would be
+            // sign-extended into the high half of the 64-bit index
+            len[u] = k0 + u < ke ? (uint32_t)__builtin_amdgcn_readfirstlane((int)g.x) : 0u;
+            const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.y);
+            const uint32_t e_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.z);
+            const uint32_t e_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.w);
+            const uint64_t e0 = ((uint64_t)e_hi << 32) | (uint64_t)e_lo;
             mp[u] = static_cast<const unsigned char*>(meta) + e0 * (WBF16 ? 4 : sizeof(META));
             wp[u] = WBF16 ? nullptr : static_cast<const unsigned char*>(w) + e0 * 4;
             roff[u] = (uint32_t)(base_slot + (int)y) * T;
