@@ -39,10 +39,10 @@ WORKLOADS = {
     # 5 s: the smallest population (1,543 neurons at about 3 Hz) then gives
     # about 22,000 spikes, a rate known to 0.7 %
     "microcircuit_77k": (netspec.microcircuit_77k, 3, 50000),
-    # same in-degree as the two-million-neuron bf16 network, 1 % / 5 % of
+    # same in-degree as the two-million-neuron bf16 network, 1 % / 2.5 % of
     # its neurons (a surrogate: the full size does not fit the host)
     "brunel_2m_bf16_surrogate_20k": (lambda: netspec.brunel_2m_bf16(scale_n=0.01), 5, 10000),
-    "brunel_2m_bf16_surrogate_100k": (lambda: netspec.brunel_2m_bf16(scale_n=0.05), 5, 10000),
+    "brunel_2m_bf16_surrogate_50k": (lambda: netspec.brunel_2m_bf16(scale_n=0.025), 5, 10000),
 }
 
 
