@@ -181,10 +181,12 @@ def test_full_size_two_million_neurons_bf16(cx, orc):
     """The two-million-neuron bf16 network (2.25e10 synapses): the streamed
     plan is chosen by itself; open-loop input of sampled targets matches the
     oracle (which holds only those targets' synapses, weights rounded to
-    bf16 as stored); closed-loop statistics match those of a same-in-degree
-    oracle surrogate (the full network does not fit the host)."""
-    import json
-    import os
+    bf16 as stored); in closed loop every spike of the sampled targets is a
+    threshold crossing of the oracle's potential driven by the run's own
+    raster, and every integrating step without a spike is not.  (Closed-loop
+    statistics are compared at 50,000 neurons, below: at two million the
+    oracle cannot run, and a smaller network with the same in-degree is
+    denser, so its rates and CVs are not those of the full size.)"""
     from tests.golden.make_closed_loop_stats import bf16_rne
     spec = netspec.brunel_2m_bf16()
     N, T = spec.n_neurons, 60
@@ -207,26 +209,62 @@ def test_full_size_two_million_neurons_bf16(cx, orc):
     assert np.all(np.abs(xg - xo) <= 1e-5 * B + 1e-30)
     assert np.all(np.abs(vg - vo) <= 1e-4 * (1.0 + np.abs(vo)))
     del o
-    case("2M neurons bf16: closed loop 1 s vs same-in-degree oracle surrogate")
+    case("2M neurons bf16: closed loop, spikes vs replayed oracle potentials")
     g.reset()
-    Tc = 10000
+    Tc = 3000
     g.step(Tc)
     st, sid = g.spikes(0, Tc)
+    g.step(10000 - Tc)
+    st1, sid1 = g.spikes(0, 10000)
     g.close()
-    rg = helpers.rates_and_cv(st, sid, spec, 1000, Tc)
+    rg = helpers.rates_and_cv(st1, sid1, spec, 1000, 10000)
+    print("2M closed loop 1 s: (rate Hz, CV) per population", rg, flush=True)
+    sel = netspec.sample_targets(N, 60, seed=12)
+    o = orc.OracleNet(spec, 5, sel=sel)
+    _, _, w, _ = o.graph()
+    o.set_weights(bf16_rne(w))
+    vpre = o.run_frozen_pre(st.astype(np.int64), sid.astype(np.int64), Tc)
+    theta = spec.V_th
+    eps = 1e-4 * (1.0 + abs(theta))
+    spk = np.zeros((Tc, len(sel)), bool)
+    col = {int(i): c for c, i in enumerate(sel)}
+    for s_, i in zip(st, sid):
+        if int(i) in col:
+            spk[int(s_), col[int(i)]] = True
+    integ = ~np.isnan(vpre)
+    assert np.all(integ[spk]), "a GPU spike on a refractory step"
+    assert np.all(vpre[spk] >= theta - eps)
+    assert np.all(vpre[integ & ~spk] < theta + eps)
+    n_spk = int(spk.sum())
+    near = int(np.count_nonzero(integ & (np.abs(vpre - theta) < 1.0)))
+    print(f"spikes checked {n_spk}, integrating steps within 1 mV of threshold {near}", flush=True)
+    assert n_spk >= 50 and near >= 500
+    for r, _ in rg:
+        assert 1.0 < r < 50.0   # the asynchronous irregular state, not silence or saturation
+
+
+def test_closed_loop_statistics_50k_same_indegree_streamed_bf16(cx):
+    """The 50,000-neuron network with the in-degree of the two-million-neuron
+    one (9,000 E + 2,250 I), bf16 weights, on that network's code path
+    (streamed plan, one wave per 64 spikes over segments of about 14
+    synapses): closed-loop rates within 2 % and CVs within 5 % of the
+    oracle's over 1 s (golden statistics written by the oracle alone)."""
+    import json
+    import os
+    from tests.golden.make_closed_loop_stats import spec_hash
+    spec = netspec.brunel_2m_bf16(scale_n=0.025)
     here = os.path.dirname(os.path.abspath(__file__))
-    for name in ("brunel_2m_bf16_surrogate_50k", "brunel_2m_bf16_surrogate_20k"):
-        with open(os.path.join(here, "golden", f"closed_loop_{name}.json")) as f:
-            go = json.load(f)
-        print(name, "gpu", rg, "oracle", list(zip(go["rates_hz"], go["cv"])), flush=True)
-    # the larger surrogate is the reference; the difference between the two
-    # surrogates bounds the finite-size effect that the tolerance must allow
     with open(os.path.join(here, "golden", "closed_loop_brunel_2m_bf16_surrogate_50k.json")) as f:
         go = json.load(f)
-    with open(os.path.join(here, "golden", "closed_loop_brunel_2m_bf16_surrogate_20k.json")) as f:
-        gs = json.load(f)
-    for (rate_g, cv_g), r50, c50, r20, c20 in zip(rg, go["rates_hz"], go["cv"], gs["rates_hz"], gs["cv"]):
-        fs_r = abs(r50 - r20) / r50
-        fs_c = abs(c50 - c20) / c50
-        assert abs(rate_g - r50) <= (0.02 + fs_r) * r50
-        assert abs(cv_g - c50) <= (0.05 + fs_c) * c50
+    assert go["spec_hash"] == spec_hash(spec)
+    case("50k neurons, in-degree 11,250, bf16, streamed tile 64: closed loop 1 s")
+    g = cx.Network(spec, go["seed"], record_steps=go["steps"], plan="streamed", tile_size=64)
+    assert g.query("PLAN") == cx.PLAN_STREAMED and g.query("EDGE_BYTES") == 4
+    g.step(go["steps"])
+    st, sid = g.spikes(0, go["steps"])
+    g.close()
+    rg = helpers.rates_and_cv(st, sid, spec, go["discard_steps"], go["steps"])
+    print("gpu", rg, "oracle", list(zip(go["rates_hz"], go["cv"])), flush=True)
+    for (rate_g, cv_g), rate_o, cv_o in zip(rg, go["rates_hz"], go["cv"]):
+        assert abs(rate_g - rate_o) <= 0.02 * rate_o
+        assert abs(cv_g - cv_o) <= 0.05 * cv_o
