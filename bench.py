@@ -143,18 +143,38 @@ def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
     }
 
 
+def choose_plan(cx, spec, seed, args):
+    """The launch plan request of a timed network: the command line's, else
+    a freshly measured one (--autotune), else the tuned table's entry for
+    this network on this device, else the planner's default."""
+    explicit = dict(tile_size=args.tile_size, block_size=args.block_size, wg_per_cu=args.wg_per_cu)
+    if any(explicit.values()):
+        return explicit, "command line"
+    if args.autotune:
+        best, _ = cx.autotune(spec, seed, steps=1000, warmup=100, cache=cx.TUNE_CACHE, log=log)
+        return best, "autotuned in this run"
+    req, entry = cx.lookup_plan(spec)
+    if req is not None:
+        same = entry.get("library") == cx._library_hash()
+        return req, "tuned table" + ("" if same else " (tuned with another build of the library)")
+    return {}, "planner default"
+
+
 def brunel_112k(cx, torch, netspec, args):
     """The 112,500-neuron alpha-current net on the resident persistent plan."""
     spec = netspec.brunel_112k_alpha()
-    log("[bench] brunel_112k: building")
+    req, plan_source = choose_plan(cx, spec, 2, argparse.Namespace(tile_size=0, block_size=0, wg_per_cu=0,
+                                                                   autotune=args.autotune))
+    log(f"[bench] brunel_112k: building, plan {req} ({plan_source})")
     t0 = time.perf_counter()
-    net = cx.Network(spec, 2)
+    net = cx.Network(spec, 2, **req)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     run = timed_run(net, torch, args.steps, args.warmup, SIM_STEPS_PER_BENCH_STEP, "brunel_112k")
     out = dict(run, neurons=net.N, synapses=net.E, graph_build_s=t_build, tiles=net.query("TILES"),
                tile_size=net.query("TILE_SIZE"), block_size=net.query("BLOCK_SIZE"),
-               steps_per_sync=net.query("STEPS_PER_SYNC"), plan="resident",
+               steps_per_sync=net.query("STEPS_PER_SYNC"),
+               plan="streamed" if net.query("PLAN") == 2 else "resident", plan_request=req, plan_source=plan_source,
                roofline=roofline(net, run, args.steps, SIM_STEPS_PER_BENCH_STEP))
     net.close()
     return out
@@ -303,9 +323,15 @@ def main():
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the candidate launch plans of the timed networks first (minutes for the "
+                         "two-million-neuron net) and use the fastest; without it the tuned table is used")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=400)
-    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--workload", choices=("brunel_2m_bf16", "brunel_112k_alpha"), default="brunel_2m_bf16",
+                    help="the timed network: the two-million-neuron bf16 net (streamed plan, the headline) or "
+                         "the 112,500-neuron alpha net (resident persistent plan)")
+    ap.add_argument("--cpu-targets", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
@@ -327,11 +353,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    spec = netspec.brunel_2m_bf16(scale_n=args.scale)
-    log(f"[bench] building the {spec.n_neurons:,}-neuron delta-LIF network (bf16 weights)")
+    big = args.workload == "brunel_2m_bf16"
+    spec = netspec.brunel_2m_bf16(scale_n=args.scale) if big else netspec.brunel_112k_alpha(scale_n=args.scale)
+    seed = args.seed if big else 2
+    req, plan_source = choose_plan(cx, spec, seed, args)
+    log(f"[bench] building the {spec.n_neurons:,}-neuron {spec.model}-LIF network ({spec.weight_dtype} weights), "
+        f"plan {req} ({plan_source})")
     t0 = time.perf_counter()
-    net = cx.Network(spec, args.seed, tile_size=args.tile_size, block_size=args.block_size,
-                     wg_per_cu=args.wg_per_cu)
+    net = cx.Network(spec, seed, **req)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     log(f"[bench] built: N={net.N} E={net.E} plan={'streamed' if net.query('PLAN') == 2 else 'resident'} "
@@ -351,18 +380,19 @@ def main():
 
     run = timed_run(net, torch, args.steps, args.warmup, args.sim_steps, "headline")
     roof = roofline(net, run, args.steps, args.sim_steps)
+    rec = "16-bit record + bf16 weight" if spec.weight_dtype == "bf16" else "16-bit record + fp32 weight"
     cfg = {
-        "workload": (f"balanced random net, delta-current LIF, {spec.n_neurons:,} neurons "
+        "workload": (f"balanced random net, {spec.model}-current LIF, {spec.n_neurons:,} neurons "
                      f"({spec.instances[0].pops[0].size:,} E / {spec.instances[0].pops[1].size:,} I), "
                      "in-degree 9,000 E + 2,250 I, "
-                     f"{net.E:.3e} synapses (16-bit record + bf16 weight, FP32 accumulation), "
+                     f"{net.E:.3e} synapses ({rec}, FP32 accumulation), "
                      "weights Normal(J, (0.1J)^2), J = 0.1 mV, g = 5, delays uniform 0.5-3.0 ms, "
                      f"Poisson drive eta = 2, dt 0.1 ms; one step = {args.sim_steps} time steps "
                      f"({args.sim_steps * spec.dt:.0f} ms)"),
         "neurons": net.N, "synapses": net.E, "plan": "streamed" if net.query("PLAN") == 2 else "resident",
         "tiles": net.query("TILES"), "tile_size": net.query("TILE_SIZE"),
         "block_size": net.query("BLOCK_SIZE"), "steps_per_sync": net.query("STEPS_PER_SYNC"),
-        "record_bytes": net.query("EDGE_BYTES"),
+        "record_bytes": net.query("EDGE_BYTES"), "plan_request": req, "plan_source": plan_source,
     }
     net.close()
     del net
@@ -371,12 +401,13 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(spec, run["firing_rate_hz"], args.seed, args.cpu_targets, args.cpu_steps)
+        cpu = cpu_baseline(spec, run["firing_rate_hz"], seed, args.cpu_targets, args.cpu_steps)
         log(f"[bench] cpu baseline {cpu['value']:.3e} events/s")
 
     secondary = {}
     if not args.no_secondary:
-        secondary["brunel_112k_alpha_fp32"] = brunel_112k(cx, torch, netspec, args)
+        if big:
+            secondary["brunel_112k_alpha_fp32"] = brunel_112k(cx, torch, netspec, args)
         torch.cuda.empty_cache()
         secondary.update(secondary_configs(cx, torch, netspec))
         torch.cuda.empty_cache()

@@ -461,41 +461,147 @@ class Network:
         return cortex_export_tiles(self._h, self.query("TILES"))
 
 
-def autotune(spec, seed: int, steps: int = 500, warmup: int = 100, tile_sizes=(0,), **plan):
-    """Pick the launch plan of an FP32 network spec by measurement: build it with
-    every steps-per-exchange window from its minimum delay down to 1 (and the
-    given tile sizes, 0 = the planner's balanced tiles), time ``steps``
-    closed-loop steps after ``warmup`` and return (best plan dict, timings).
-    Candidates that cannot be planned on this device are skipped."""
+# ---------------------------------------------------------------------------
+# Measuring autotuner with a disk cache
+# ---------------------------------------------------------------------------
+
+TUNED_TABLE = os.path.join(HERE, "tuned_plans.json")   # shipped, read-only
+TUNE_CACHE = os.environ.get("CORTEX_TUNE_CACHE",
+                            os.path.join(os.path.expanduser("~"), ".cache", "cortex", "tuned_plans.json"))
+PLAN_KEYS = ("plan", "wg_per_cu", "block_size", "steps_per_sync", "tile_size")
+
+
+def _device_desc():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "") or ""
+    return {"name": f"{p.name} {arch.split(':')[0]}".strip(), "n_cu": int(p.multi_processor_count)}
+
+
+def _library_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def tune_key(spec, device: dict) -> str:
+    """Cache key of a network description on a device: the description's
+    text (sizes, connectivity, delays, models, precision) and the device's
+    name and compute-unit count."""
+    import hashlib
+    return hashlib.sha256(f"{spec!r}|{device['name']}|{device['n_cu']}".encode()).hexdigest()[:24]
+
+
+def _read_table(path: str) -> dict:
+    import json
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        return t if isinstance(t, dict) and t.get("format") == 1 else {"format": 1, "entries": {}}
+    except (OSError, ValueError):
+        return {"format": 1, "entries": {}}
+
+
+def lookup_plan(spec, device: Optional[dict] = None, paths=None):
+    """The tuned plan request of ``spec`` on ``device`` (the current GPU by
+    default): the user cache first, then the table shipped with the package.
+    Returns (request dict, entry) or (None, None)."""
+    device = device or _device_desc()
+    key = tune_key(spec, device)
+    for path in (paths or (TUNE_CACHE, TUNED_TABLE)):
+        e = _read_table(path)["entries"].get(key)
+        if e:
+            return dict(e["request"]), e
+    return None, None
+
+
+def plan_candidates(spec, n_cu: int, lds_per_cu: int = 163840, threads_per_cu: int = 2048,
+                    tile_sizes=(0,), windows=None):
+    """Distinct launch plans of an FP32 network: requests over the plan kind,
+    workgroups per compute unit, block size, exchange window and tile size,
+    resolved on the host; requests that resolve to the same plan are kept
+    once, and requests the device cannot hold are dropped."""
+    base = cortex_plan(spec, n_cu, lds_per_cu, threads_per_cu)
+    w_top = min(8, base["dmin"])
+    ws = windows or sorted({w_top, max(1, w_top - 1), max(1, w_top // 2)}, reverse=True)
+    seen, out = set(), []
+    for kind in ("resident", "streamed"):
+        for pc in (1, 2):
+            for bs in (0, 512):
+                for W in ws:
+                    for T in tile_sizes:
+                        req = dict(plan=kind, wg_per_cu=pc, block_size=bs, steps_per_sync=W, tile_size=T)
+                        try:
+                            p = cortex_plan(spec, n_cu, lds_per_cu, threads_per_cu, **req)
+                        except CortexError as e:
+                            if e.status in (EUNSUPPORTED, EINVAL):
+                                continue
+                            raise
+                        sig = tuple(p[f] for f in PLAN_FIELDS)
+                        if sig not in seen:
+                            seen.add(sig)
+                            out.append((req, p))
+    return out
+
+
+def autotune(spec, seed: int, steps: int = 2000, warmup: int = 200, tile_sizes=(0,), windows=None,
+             budget_s: float = 600.0, cache: Optional[str] = TUNE_CACHE, log=None):
+    """Pick the launch plan of an FP32 network by measurement: every distinct
+    candidate plan (plan_candidates) is built on the current GPU, run
+    ``warmup`` closed-loop steps, then timed over ``steps`` steps; the fastest
+    wins.  Candidates that cannot be built on this device are skipped;
+    candidates are tried in the planner's order until ``budget_s`` seconds
+    have passed.  The result is stored in the JSON cache ``cache`` (None: not
+    stored) under tune_key(spec, device).  Returns (best request, timings:
+    list of (request, plan, seconds per step or None))."""
+    import json
     import time
     import torch
-    probe = Network(spec, seed, **plan)
-    w_max = probe.query("STEPS_PER_SYNC")
-    d_min = probe.query("MIN_DELAY")
-    probe.close()
-    results = []
-    for T in tile_sizes:
-        for W in range(min(8, d_min), 0, -1):
-            cand = dict(plan, tile_size=T, steps_per_sync=W)
-            try:
-                g = Network(spec, seed, **cand)
-            except CortexError as e:
-                if e.status in (EUNSUPPORTED, EINVAL):
-                    continue
-                raise
+    device = _device_desc()
+    cands = plan_candidates(spec, device["n_cu"], tile_sizes=tile_sizes, windows=windows)
+    t_start = time.perf_counter()
+    timings = []
+    for req, p in cands:
+        if time.perf_counter() - t_start > budget_s:
+            break
+        try:
+            g = Network(spec, seed, **req)
+        except CortexError as e:
+            if e.status in (EUNSUPPORTED, EINVAL):
+                timings.append((req, p, None))
+                continue
+            raise
+        try:
             g.step(warmup)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             g.step(steps)
             torch.cuda.synchronize()
-            results.append((time.perf_counter() - t0, cand))
+            dt = (time.perf_counter() - t0) / steps
+        finally:
             g.close()
-            if W < w_max and len(results) >= 2 and results[-1][0] > 1.5 * min(r[0] for r in results):
-                break   # shorter windows only add exchanges from here on
-    if not results:
+        timings.append((req, p, dt))
+        if log:
+            log(f"[tune] {req} -> tiles {p['tiles']} T {p['T']} W {p['W']}: {dt * 1e6:.2f} us/step")
+    done = [t for t in timings if t[2] is not None]
+    if not done:
         raise CortexError(EUNSUPPORTED, "no candidate plan fits this device")
-    best = min(results, key=lambda r: r[0])[1]
-    return best, [(c, t) for t, c in results]
+    best_req, best_plan, best_dt = min(done, key=lambda t: t[2])
+    if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        table = _read_table(cache)
+        table["entries"][tune_key(spec, device)] = {
+            "request": best_req, "plan": best_plan, "seconds_per_step": best_dt,
+            "device": device, "library": _library_hash(), "steps": steps,
+            "candidates": [{"request": r, "seconds_per_step": d} for r, _, d in timings],
+        }
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best_req, timings
 
 
 class VoltageLoss:

@@ -102,3 +102,31 @@ def test_adjoint_needs_the_resident_plan():
     with pytest.raises(cx.CortexError) as e:
         cx.cortex_plan(WORKLOADS["brunel_2m_bf16"], ckpt_every=100, adjoint_steps=1000, **MI355X)
     assert e.value.status == cx.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["brunel_112k", "brunel_2m_bf16", "batched_64"])
+def test_autotuner_candidates_are_distinct_checked_plans(name):
+    spec = WORKLOADS[name]
+    cands = cx.plan_candidates(spec, MI355X["n_cu"], MI355X["lds_per_cu"], MI355X["threads_per_cu"])
+    sigs = {tuple(p[f] for f in cx.PLAN_FIELDS) for _, p in cands}
+    assert len(sigs) == len(cands) >= 2
+    for req, p in cands:
+        check(p, spec)
+        assert set(req) == set(cx.PLAN_KEYS)
+        assert cx.cortex_plan(spec, **MI355X, **req) == p
+
+
+def test_tuned_plan_table_lookup(tmp_path):
+    import json
+    spec = WORKLOADS["small"]
+    dev = {"name": "AMD Instinct MI355X gfx950", "n_cu": 256}
+    other = {"name": "AMD Instinct MI355X gfx950", "n_cu": 128}
+    req = dict(plan="streamed", wg_per_cu=2, block_size=0, steps_per_sync=1, tile_size=0)
+    path = tmp_path / "plans.json"
+    path.write_text(json.dumps({"format": 1, "entries": {cx.tune_key(spec, dev): {"request": req}}}))
+    got, entry = cx.lookup_plan(spec, dev, paths=[str(path)])
+    assert got == req and entry["request"] == req
+    assert cx.lookup_plan(spec, other, paths=[str(path)]) == (None, None)
+    assert cx.lookup_plan(WORKLOADS["brunel_112k"], dev, paths=[str(path)]) == (None, None)
+    # a missing or foreign file is an empty table
+    assert cx.lookup_plan(spec, dev, paths=[str(tmp_path / "none.json")]) == (None, None)
