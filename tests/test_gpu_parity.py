@@ -398,13 +398,23 @@ def test_set_weights_gradient_matches_oracle_and_finite_differences(cx, orc):
         assert (lp - lm) / h_eff == pytest.approx(gr[e], rel=2e-2)
 
 
-def test_autotune_returns_the_fastest_valid_plan(cx):
+def test_autotune_returns_the_fastest_valid_plan(cx, tmp_path):
+    import json
     spec = netspec.batched_brunel([600, 1200, 2400])
     case("autotune on 3 batched instances")
-    best, timings = cx.autotune(spec, 9, steps=300, warmup=50)
-    assert timings and all(t > 0 for _, t in timings)
-    assert best == min(timings, key=lambda ct: ct[1])[0]
-    g = cx.Network(spec, 9, **best)
+    cache = str(tmp_path / "plans.json")
+    best, timings = cx.autotune(spec, 9, steps=300, warmup=50, cache=cache)
+    timed = [(r, p, t) for r, p, t in timings if t is not None]
+    assert len(timed) >= 2 and all(t > 0 for _, _, t in timed)
+    assert best == min(timed, key=lambda rpt: rpt[2])[0]
+    # both plan kinds and both occupancies were measured
+    assert {r["plan"] for r, _, _ in timed} == {"resident", "streamed"}
+    assert {r["wg_per_cu"] for r, _, _ in timed} == {1, 2}
+    # the cache holds the winner under this network and device
+    got, entry = cx.lookup_plan(spec, paths=[cache])
+    assert got == best and entry["library"] == cx._library_hash()
+    assert len(json.load(open(cache))["entries"]) == 1
+    g = cx.Network(spec, 9, **got)
     assert g.query("STEPS_PER_SYNC") == best["steps_per_sync"]
     g.step(100)
     assert g.query("SPIKES") > 0
