@@ -36,12 +36,17 @@ CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
 # size, as the summaries under profiles/ state), valid only for the sources
 # they were measured on: {kernel: (bytes per event, source hash)}.
 TRAFFIC = {
-    "step_kernel": ((3.0703e7 * 2.0 + 1.8482e6 * 1.0) * 1024 / 9.072019401e9, "4b542c1b14690f92"),
+    # 112,500-neuron alpha net, one 1000-step launch: (3.2983e6 KiB x 2.0
+    # + 2.0457e5 KiB x 1.0) x 1024 / 9.708e8 events
+    "step_kernel": (7.174, "d0432f40e622e854"),
+    # two-million-neuron bf16 net, launches 10-199 of a 1000-step run:
+    # (1.5260e6 KiB x 2.0 + 3.1359e5 KiB x 1.0) x 1024 / 8.5245e7 events
+    "stream_kernel": (40.43, "277e5d087d96aaa2"),
 }
 
 
 def source_hash(kernel: str) -> str:
-    files = {"step_kernel": ["step.hip"], "stream_kernel": ["stream.hip", "deliver.hpp"]}[kernel]
+    files = {"step_kernel": ["step.hip", "deliver.hpp"], "stream_kernel": ["stream.hip", "deliver.hpp"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         h.update(open(os.path.join(CSRC, f), "rb").read())
