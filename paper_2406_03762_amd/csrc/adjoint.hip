@@ -153,13 +153,12 @@ struct WgradArgs {
     const void* meta;
     int meta16;                 // 16-bit records (alone, or under a bf16 weight when packed)
     int packed;
-    int T, dmin;                // record = (delay - dmin) T + target in tile
+    int T, dmin, dmax;          // record = (delay - dmin) T + target in tile
     int sw, n_sub;              // steps per sub-window, sub-windows of the segment
     int n_inst;
-    const uint64_t* src_ptr;    // [n_sub][n_inst + 1] into src_id
-    const uint32_t* src_id;     // per sub-window, spiking sources grouped by instance
-    const uint64_t* spk_ptr;    // [sources + 1] into spk_step
-    const int64_t* spk_step;
+    const uint32_t* r_ids;      // the raster's ids, sorted by (step, id)
+    const uint64_t* r_ptr;      // [step * (n_inst + 1) + b]: instance b's spikes of a step
+    int64_t r_steps;            // steps of the raster
     const float* gtr;           // [len][N]
     float* grad;                // [E] storage order
     int64_t N, s0, s1;
@@ -174,10 +173,13 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int i) {
 
 // One workgroup (16 waves) per tile.  The segment's steps are taken in
 // sub-windows of sw steps; for each, the tile's dL/dx values of those steps
-// are staged in LDS ([sw][tile size]), then one wave per source whose spikes
-// can arrive in the sub-window walks the source's segment into the tile
-// (lanes over its synapses) and adds, per synapse, the staged values at the
-// arrival steps.
+// are staged in LDS ([sw][tile size]), then the spikes of the tile's
+// instance that can arrive in the sub-window (steps q with [q + d_min,
+// q + d_max] meeting it) are read from the raster, 64 at a time per wave.
+// Source j belongs to wave j mod 16: that wave walks j's segment into the
+// tile (lanes over its synapses) for each of j's spikes in turn and adds,
+// per synapse whose arrival q + d falls in the sub-window, the staged value
+// there.  A synapse's gradient therefore has one writer, with no atomics.
 __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
     extern __shared__ float s_g[];
     const int tile = blockIdx.x;
@@ -187,7 +189,9 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
     const int tsz = a.tile_size[tile];
     const int64_t n0b = a.inst_n0[b];
     const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
+    const uint64_t offb = a.inst_offbase[b];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    const uint32_t T = (uint32_t)a.T;
     for (int w = 0; w < a.n_sub; ++w) {
         const int64_t t = a.s0 + (int64_t)w * a.sw;
         const int nw = (int)min((int64_t)a.sw, a.s1 - t);
@@ -197,57 +201,54 @@ __global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
             s_g[i] = a.gtr[(t - a.s0 + k) * a.N + g0 + li];
         }
         __syncthreads();
-        const uint64_t* sp = a.src_ptr + (size_t)w * (a.n_inst + 1);
-        // a wave takes 16 consecutive sources at a time: lanes 0-15 load
-        // their segment bounds and spike ranges together, then the wave
-        // walks the 16 segments one after the other
-        constexpr int kSB = 16;
-        for (uint64_t sb = sp[b] + (uint64_t)wave * kSB; sb < sp[b + 1]; sb += (uint64_t)n_waves * kSB) {
-            const int cnt = (int)min<uint64_t>(kSB, sp[b + 1] - sb);
-            uint64_t e0l = 0, e1l = 0, p0l = 0, p1l = 0;
-            if (lane < cnt) {
-                const uint64_t s = sb + lane;
-                const uint32_t j = a.src_id[s];
-                const uint64_t ob = a.inst_offbase[b] + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + tl;
-                const uint64_t rs = a.row_start[j];
-                e0l = rs + a.off_rel[ob];
-                e1l = rs + a.off_rel[ob + 1];
-                p0l = a.spk_ptr[s];
-                p1l = a.spk_ptr[s + 1];
-            }
-            for (int i = 0; i < cnt; ++i) {
-                const uint64_t e0 = lane_u64(e0l, i), e1 = lane_u64(e1l, i);
-                const uint64_t p0 = lane_u64(p0l, i), p1 = lane_u64(p1l, i);
-                // four synapses per lane at a time; a synapse's record and its
-                // gradient so far are loaded together (this wave is the only
-                // writer of the segment's gradients in this sub-window)
-                for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
-                    uint32_t m[4];
-                    float g[4];
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint64_t e = eb + 64u * u;
-                        m[u] = 0;
-                        g[u] = 0.f;
-                        if (e < e1) {
-                            m[u] = a.packed ? (static_cast<const uint32_t*>(a.meta)[e] & 0xFFFFu)
-                                   : a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                              : static_cast<const uint32_t*>(a.meta)[e];
-                            g[u] = a.grad[e];
-                        }
+        const int64_t q_lo = max((int64_t)0, t - a.dmax);
+        const int64_t q_hi = min(a.r_steps, t + nw - a.dmin);
+        for (int64_t q = q_lo; q < q_hi; ++q) {
+            const uint64_t p0 = a.r_ptr[q * (a.n_inst + 1) + b], p1 = a.r_ptr[q * (a.n_inst + 1) + b + 1];
+            for (uint64_t pc = p0; pc < p1; pc += 64) {
+                // this wave's spikes among the next 64: their segment bounds
+                // are loaded by their own lanes, together
+                const uint64_t p = pc + (uint64_t)lane;
+                uint32_t j = 0;
+                bool own = false;
+                uint64_t e0l = 0, e1l = 0;
+                if (p < p1) {
+                    j = a.r_ids[p];
+                    own = (int)(j % (uint32_t)n_waves) == wave;
+                    if (own) {
+                        const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + (uint64_t)tl;
+                        const uint64_t rs = a.row_start[j];
+                        e0l = rs + a.off_rel[ob];
+                        e1l = rs + a.off_rel[ob + 1];
                     }
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint64_t e = eb + 64u * u;
-                        if (e >= e1) continue;
-                        const int64_t d = a.dmin + (int64_t)(m[u] / (uint32_t)a.T);
-                        const int li = (int)(m[u] % (uint32_t)a.T);
-                        float acc = 0.f;
-                        for (uint64_t p = p0; p < p1; ++p) {
-                            const int64_t tau = a.spk_step[p] + d;
-                            if (tau >= t && tau < t + nw) acc += s_g[(tau - t) * tsz + li];
+                }
+                uint64_t mask = __ballot(own);
+                while (mask) {
+                    const int i = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    const uint64_t e0 = lane_u64(e0l, i), e1 = lane_u64(e1l, i);
+                    // four synapses per lane at a time: records first, then
+                    // the gradients of those arriving in the sub-window
+                    for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
+                        int32_t at[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint64_t e = eb + 64u * u;
+                            at[u] = -1;
+                            if (e < e1) {
+                                const uint32_t m = a.packed ? (static_cast<const uint32_t*>(a.meta)[e] & 0xFFFFu)
+                                                   : a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
+                                                              : static_cast<const uint32_t*>(a.meta)[e];
+                                const int64_t tau = q + a.dmin + (int64_t)(m / T);
+                                if (tau >= t && tau < t + nw) at[u] = (int32_t)((tau - t) * tsz + (int64_t)(m % T));
+                            }
                         }
-                        if (acc != 0.f) a.grad[e] = g[u] + acc;
+                        float g[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) g[u] = at[u] >= 0 ? a.grad[eb + 64u * u] : 0.f;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (at[u] >= 0) a.grad[eb + 64u * u] = g[u] + s_g[at[u]];
                     }
                 }
             }
@@ -287,8 +288,6 @@ namespace cortex {
 
 // Helpers defined in api.hip.
 std::vector<std::pair<uint32_t, uint32_t>> collect_spikes(cortex_net* n, int64_t s0, int64_t s1, bool* trunc);
-void frozen_lists_at(cortex_net* n, int64_t step0, const std::vector<std::pair<uint32_t, uint32_t>>& spikes,
-                     int64_t n_steps, std::vector<uint32_t>& ids, std::vector<uint64_t>& ptr);
 void restore_checkpoint(cortex_net* n, int k);
 
 void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss_out) {
@@ -338,8 +337,9 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     double* dloss_part = dev_alloc_t<double>(n, rev_grid, true);
     float* grad = dev_alloc_t<float>(n, n->E, true);
     int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
-    // weight-gradient sub-windows: sw steps of a tile's dL/dx in 128 KB of LDS
-    const int sw = (int)std::max<int64_t>(1, std::min<int64_t>(C, 32768 / std::max(1, n->T)));
+    // weight-gradient sub-windows: sw steps of a tile's dL/dx in at most
+    // 160 KB of LDS
+    const int sw = (int)std::max<int64_t>(1, std::min<int64_t>(C, 40960 / std::max(1, n->T)));
     const size_t wgrad_lds = (size_t)sw * n->T * sizeof(float);
     CX_HIP(hipFuncSetAttribute((const void*)wgrad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)wgrad_lds));
@@ -352,82 +352,36 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     dev_zero(n, grad, (size_t)n->E * 4);
     const int64_t saved_log_steps = n->log_steps;
     n->log_steps = 0;   // the replays must not append to the spike log
-    // raster index by step
-    std::vector<size_t> first(T + 1, raster.size());
-    for (size_t q = raster.size(); q-- > 0;) first[raster[q].first] = q;
-    for (int64_t s = T - 1; s >= 0; --s) first[s] = std::min(first[s], first[s + 1]);
-    auto slice = [&](int64_t a, int64_t b) {
-        a = std::max<int64_t>(0, a);
-        b = std::min<int64_t>(T, b);
-        std::vector<std::pair<uint32_t, uint32_t>> v;
-        if (b > a) v.assign(raster.begin() + first[a], raster.begin() + first[b]);
-        return v;
-    };
+    // The raster on the device, with its offsets per (step, tile) (the
+    // replays' frozen lists and the republished steps) and per (step,
+    // instance) (the weight gradient's spikes), built once for all segments.
+    const int64_t n_spk = (int64_t)raster.size();
+    uint32_t* r_steps = dev_alloc_t<uint32_t>(n, std::max<int64_t>(1, n_spk), true);
+    uint32_t* r_ids = dev_alloc_t<uint32_t>(n, std::max<int64_t>(1, n_spk), true);
+    uint64_t* r_tile_ptr = dev_alloc_t<uint64_t>(n, (size_t)T * n->n_tiles + 1, true);
+    uint64_t* r_inst_ptr = dev_alloc_t<uint64_t>(n, (size_t)T * (n->n_inst + 1) + 1, true);
+    int64_t* inst_keys = dev_alloc_t<int64_t>(n, n->n_inst + 1, true);
+    {
+        std::vector<uint32_t> hs((size_t)n_spk), hi((size_t)n_spk);
+        for (int64_t q = 0; q < n_spk; ++q) {
+            hs[q] = raster[q].first;
+            hi[q] = raster[q].second;
+        }
+        std::vector<int64_t> keys(n->inst_n0.begin(), n->inst_n0.end());
+        keys.push_back(N);
+        if (n_spk > 0) {
+            CX_HIP(hipMemcpyAsync(r_steps, hs.data(), n_spk * 4, hipMemcpyHostToDevice, n->stream));
+            CX_HIP(hipMemcpyAsync(r_ids, hi.data(), n_spk * 4, hipMemcpyHostToDevice, n->stream));
+        }
+        CX_HIP(hipMemcpyAsync(inst_keys, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, n->stream));
+        raster_index(n, r_steps, r_ids, n_spk, 0, T, n->d_tile_start, n->n_tiles, r_tile_ptr);
+        raster_index(n, r_steps, r_ids, n_spk, 0, T, inst_keys, n->n_inst + 1, r_inst_ptr);
+        CX_HIP(hipStreamSynchronize(n->stream));   // before the staging vectors go away
+    }
     const int K = (int)((T + C - 1) / C);
-    // Host lists of a segment: the pending spikes to republish, the frozen
-    // raster of the replay and, per sub-window of sw steps, the sources
-    // whose arrivals may land in it (a spike at q arrives in [q + d_min,
-    // q + d_max]), grouped by instance, each with its spike steps.  They
-    // depend only on the raster, so the lists of segment k - 1 are built
-    // while the device works on segment k.  Two sets alternate; a set is
-    // refilled only after the stream has drained the uploads that read it.
-    struct SegLists {
-        std::vector<uint32_t> rp_ids, fr_ids, src_id;
-        std::vector<uint64_t> rp_ptr, fr_ptr, src_ptr, spk_ptr;
-        std::vector<int64_t> spk_step;
-    };
-    SegLists lists[2];
-    auto build_lists = [&](int k, SegLists& L) {
-        const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
-        const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
-        L.rp_ids.clear();
-        L.rp_ptr.clear();
-        if (s0 > r0) frozen_lists_at(n, r0, slice(r0, s0), s0 - r0, L.rp_ids, L.rp_ptr);
-        frozen_lists_at(n, s0, slice(s0, s1), len, L.fr_ids, L.fr_ptr);
-        const int n_sub = (int)((len + sw - 1) / sw);
-        const auto spk = slice(s0 - n->dmax, s1 - n->dmin);
-        std::vector<std::vector<std::pair<uint32_t, int64_t>>> bucket((size_t)n_sub * n->n_inst);
-        for (const auto& sp : spk) {
-            int lo = 0, hi = n->n_inst;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) / 2;
-                if (n->inst_n0[mid] <= (int64_t)sp.second) lo = mid; else hi = mid;
-            }
-            const int64_t q = (int64_t)sp.first;
-            const int64_t a0 = q + n->dmin - s0, a1 = q + n->dmax - s0;   // arrivals, relative to s0
-            if (a1 < 0 || a0 >= len) continue;
-            const int w0 = (int)(std::max<int64_t>(0, a0) / sw);
-            const int w1 = (int)(std::min<int64_t>(len - 1, a1) / sw);
-            for (int w = w0; w <= w1; ++w) bucket[(size_t)w * n->n_inst + lo].emplace_back(sp.second, q);
-        }
-        // CSR: sub-window -> instance -> distinct sources -> their spike steps
-        L.src_ptr.assign((size_t)n_sub * (n->n_inst + 1), 0);
-        L.spk_ptr.clear();
-        L.src_id.clear();
-        L.spk_step.clear();
-        for (int w = 0; w < n_sub; ++w) {
-            L.src_ptr[(size_t)w * (n->n_inst + 1)] = L.src_id.size();
-            for (int b = 0; b < n->n_inst; ++b) {
-                auto& v = bucket[(size_t)w * n->n_inst + b];
-                std::sort(v.begin(), v.end());
-                for (size_t q = 0; q < v.size(); ++q) {
-                    if (q == 0 || v[q].first != v[q - 1].first) {
-                        L.src_id.push_back(v[q].first);
-                        L.spk_ptr.push_back(L.spk_step.size());
-                    }
-                    L.spk_step.push_back(v[q].second);
-                }
-                L.src_ptr[(size_t)w * (n->n_inst + 1) + b + 1] = L.src_id.size();
-            }
-        }
-        L.spk_ptr.push_back(L.spk_step.size());
-    };
     try {
-        if (K > 0) build_lists(K - 1, lists[(K - 1) & 1]);
         for (int k = K - 1; k >= 0; --k) {
             const int64_t s0 = (int64_t)k * C, s1 = std::min<int64_t>(T, s0 + C), len = s1 - s0;
-            SegLists& L = lists[k & 1];
-            const size_t seg_mark = n->scratch.size();
             restore_checkpoint(n, k);
             n->step = s0;
             // Records left in the publication buffer by the forward run or a
@@ -438,30 +392,13 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             dev_zero(n, n->d_pub, pub_n * 8);
             // spikes of [s0 - d_min, s0) are published but not yet delivered at s0
             const int64_t r0 = std::max<int64_t>(0, s0 - n->dmin);
-            if (s0 > r0) {
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, L.rp_ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, L.rp_ptr.size(), true);
-                if (!L.rp_ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, L.rp_ids.data(), L.rp_ids.size() * 4, hipMemcpyHostToDevice,
-                                          n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, L.rp_ptr.data(), L.rp_ptr.size() * 8, hipMemcpyHostToDevice,
-                                      n->stream));
-                republish(n, r0, s0, d_ids, d_ptr, L.rp_ids.size());
-            }
-            // bit-exact replay of the segment on the frozen raster; its error
-            // flag is read at the end of the segment (the kernels in between
-            // index only by lists and records, so a failed replay leaves them
-            // in bounds)
-            {
-                uint32_t* d_ids = dev_alloc_t<uint32_t>(n, std::max<size_t>(1, L.fr_ids.size()), true);
-                uint64_t* d_ptr = dev_alloc_t<uint64_t>(n, L.fr_ptr.size(), true);
-                if (!L.fr_ids.empty())
-                    CX_HIP(hipMemcpyAsync(d_ids, L.fr_ids.data(), L.fr_ids.size() * 4, hipMemcpyHostToDevice,
-                                          n->stream));
-                CX_HIP(hipMemcpyAsync(d_ptr, L.fr_ptr.data(), L.fr_ptr.size() * 8, hipMemcpyHostToDevice,
-                                      n->stream));
-                launch_step_fp32(n, len, d_ids, d_ptr, L.fr_ids.size(), nullptr, vtr, mtr);
-            }
+            if (s0 > r0) republish(n, r0, s0, r_ids, r_tile_ptr + (size_t)r0 * n->n_tiles, (uint64_t)n_spk);
+            // bit-exact replay of the segment on the frozen raster; the error
+            // flag is read after the last segment (the kernels in between
+            // index only by the raster and the records, so a failed replay
+            // leaves them in bounds)
+            launch_step_fp32(n, len, r_ids, r_tile_ptr + (size_t)s0 * n->n_tiles, (uint64_t)n_spk, nullptr, vtr,
+                             mtr);
             // reverse recursion over the segment
             ReverseArgs ra{};
             ra.vtr = vtr; ra.mtr = mtr; ra.vstar = vstar; ra.gtr = gtr;
@@ -475,47 +412,29 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, n->stream, dloss_part, rev_grid, dloss);
             CX_HIP(hipGetLastError());
             // weight gradient of the synapses whose arrivals land in the segment
-            if (!L.src_id.empty()) {
-                const int n_sub = (int)((len + sw - 1) / sw);
-                uint64_t* d_sp = dev_alloc_t<uint64_t>(n, L.src_ptr.size(), true);
-                uint32_t* d_si = dev_alloc_t<uint32_t>(n, L.src_id.size(), true);
-                uint64_t* d_pp = dev_alloc_t<uint64_t>(n, L.spk_ptr.size(), true);
-                int64_t* d_ss = dev_alloc_t<int64_t>(n, L.spk_step.size(), true);
-                CX_HIP(hipMemcpyAsync(d_sp, L.src_ptr.data(), L.src_ptr.size() * 8, hipMemcpyHostToDevice,
-                                      n->stream));
-                CX_HIP(hipMemcpyAsync(d_si, L.src_id.data(), L.src_id.size() * 4, hipMemcpyHostToDevice,
-                                      n->stream));
-                CX_HIP(hipMemcpyAsync(d_pp, L.spk_ptr.data(), L.spk_ptr.size() * 8, hipMemcpyHostToDevice,
-                                      n->stream));
-                CX_HIP(hipMemcpyAsync(d_ss, L.spk_step.data(), L.spk_step.size() * 8, hipMemcpyHostToDevice,
-                                      n->stream));
+            if (n_spk > 0) {
                 WgradArgs wa{};
                 wa.tile_inst = n->d_tile_inst; wa.tile_size = n->d_tile_size; wa.inst_tile0 = n->d_inst_tile0;
                 wa.inst_ntiles = n->d_inst_ntiles; wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0;
                 wa.inst_offbase = n->d_inst_offbase;
                 wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
-                wa.meta16 = n->meta_bytes == 2; wa.packed = n->w_bytes == 2; wa.T = n->T; wa.dmin = n->dmin;
-                wa.sw = sw; wa.n_sub = n_sub; wa.n_inst = n->n_inst;
-                wa.src_ptr = d_sp; wa.src_id = d_si; wa.spk_ptr = d_pp; wa.spk_step = d_ss;
+                wa.meta16 = n->meta_bytes == 2; wa.packed = n->w_bytes == 2; wa.T = n->T;
+                wa.dmin = n->dmin; wa.dmax = n->dmax;
+                wa.sw = sw; wa.n_sub = (int)((len + sw - 1) / sw); wa.n_inst = n->n_inst;
+                wa.r_ids = r_ids; wa.r_ptr = r_inst_ptr; wa.r_steps = T;
                 wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
                 hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(1024), wgrad_lds, n->stream, wa);
                 CX_HIP(hipGetLastError());
             }
-            // the previous segment's lists, into the other set, while the
-            // device runs this one
-            if (k > 0) build_lists(k - 1, lists[(k - 1) & 1]);
-            CX_HIP(hipStreamSynchronize(n->stream));
-            {
-                int32_t e = 0;
-                CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
-                if (e != 0) {
-                    n->failed = true;
-                    throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
-                }
+        }
+        CX_HIP(hipStreamSynchronize(n->stream));
+        {
+            int32_t e = 0;
+            CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
+            if (e != 0) {
+                n->failed = true;
+                throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
             }
-            // the segment's device lists go back to the allocator (the stream
-            // has drained); the large buffers above stay for the whole pass
-            free_scratch_from(n, seg_mark);
         }
         hipLaunchKernelGGL(gather_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad,
                            n->d_canon_inv, grad_w, n->E);

@@ -537,61 +537,86 @@ void delay_range(cortex_net* n, int* dmin, int* dmax) {
 namespace {
 
 // Per target, the sum of |w| over its stored in-synapses (the largest value
-// any of its input sums can reach).  One wave per source row walks the row's
-// segments tile by tile.  Setup only.
-__global__ void __launch_bounds__(256) abs_input_kernel(const uint64_t* row_start, const uint32_t* off_rel,
-                                                        const void* meta, int meta16, const void* w, int wbf16,
-                                                        int T, const int64_t* inst_n0,
-                                                        const uint64_t* inst_offbase, const int32_t* inst_ntiles,
-                                                        const int32_t* inst_T, int n_inst, int64_t N,
-                                                        double* sum, unsigned int* wmax_bits) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t j = wave; j < N; j += n_waves) {
-        int lo = 0, hi = n_inst;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (inst_n0[mid] <= j) lo = mid; else hi = mid;
-        }
-        const int nt = inst_ntiles[lo];
-        const uint64_t ob = inst_offbase[lo] + (uint64_t)(j - inst_n0[lo]) * (uint64_t)(nt + 1);
-        const uint64_t rs = row_start[j];
-        for (int t = 0; t < nt; ++t) {
-            const int64_t g0 = inst_n0[lo] + (int64_t)t * inst_T[lo];
-            for (uint64_t e = rs + off_rel[ob + t] + lane; e < rs + off_rel[ob + t + 1]; e += 64) {
-                uint32_t m;
-                float wv;
-                if (wbf16) {
-                    const uint32_t r = static_cast<const uint32_t*>(meta)[e];
-                    m = r & 0xFFFFu;
-                    wv = __uint_as_float(r & 0xFFFF0000u);
-                } else {
-                    m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
-                    wv = static_cast<const float*>(w)[e];
-                }
-                atomicAdd(&sum[g0 + (m % (uint32_t)T)], (double)fabsf(wv));
-                atomicMax(wmax_bits, __float_as_uint(fabsf(wv)));   // non-negative floats order as integers
+// any of its input sums can reach), and the largest |w|.  One workgroup per
+// tile (the tile owns its targets' in-synapses, so the sums stay in LDS):
+// lanes take the instance's sources, each walks its segment into the tile
+// through the one-load segment descriptors; LDS FP64 atomics per synapse,
+// one global maximum per workgroup.  Setup only.
+__global__ void __launch_bounds__(1024) abs_input_kernel(const uint64_t* seg, const void* meta, int meta16,
+                                                         const void* w, int wbf16, int T,
+                                                         const int32_t* tile_inst, const int32_t* tile_size,
+                                                         const int32_t* inst_tile0, const int32_t* inst_ntiles,
+                                                         const int32_t* inst_T, const int64_t* inst_n0,
+                                                         const int64_t* inst_N, const uint64_t* inst_offbase,
+                                                         double* tile_max, unsigned int* wmax_bits) {
+    extern __shared__ double s_sum[];   // [T]
+    __shared__ unsigned int s_wmax;
+    const int tile = blockIdx.x;
+    const int b = tile_inst[tile];
+    const int tl = tile - inst_tile0[b];
+    const int ntb = inst_ntiles[b];
+    const int tsz = tile_size[tile];
+    const int64_t n0b = inst_n0[b], Nb = inst_N[b];
+    const uint64_t offb = inst_offbase[b];
+    for (int i = threadIdx.x; i < T; i += blockDim.x) s_sum[i] = 0.0;
+    if (threadIdx.x == 0) s_wmax = 0u;
+    __syncthreads();
+    unsigned int my_max = 0u;
+    for (int64_t j = threadIdx.x; j < Nb; j += blockDim.x) {
+        const uint64_t d = seg[offb + (uint64_t)j * (uint64_t)(ntb + 1) + (uint64_t)tl];
+        const uint64_t e0 = d >> 24, e1 = e0 + (d & 0xFFFFFFu);
+        for (uint64_t e = e0; e < e1; ++e) {
+            uint32_t m;
+            float wv;
+            if (wbf16) {
+                const uint32_t r = static_cast<const uint32_t*>(meta)[e];
+                m = r & 0xFFFFu;
+                wv = __uint_as_float(r & 0xFFFF0000u);
+            } else {
+                m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
+                wv = static_cast<const float*>(w)[e];
             }
+            const float aw = fabsf(wv);
+            atomicAdd(&s_sum[m % (uint32_t)T], (double)aw);
+            my_max = max(my_max, __float_as_uint(aw));   // non-negative floats order as integers
         }
+    }
+    atomicMax(&s_wmax, my_max);
+    __syncthreads();
+    // the tile's largest sum: per thread, per wave, then over the waves
+    __shared__ double s_wave[16];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < tsz; i += blockDim.x) mx = fmax(mx, s_sum[i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t = fmax(t, s_wave[k]);
+        tile_max[tile] = t;
+        atomicMax(wmax_bits, s_wmax);
     }
 }
 
 }  // namespace
 
 double max_abs_input(cortex_net* n, double* wmax) {
-    double* sum = dev_alloc_t<double>(n, std::max<int64_t>(1, n->N), true);
+    double* tmax = dev_alloc_t<double>(n, std::max(1, n->n_tiles), true);
     unsigned int* wbits = dev_alloc_t<unsigned int>(n, 1, true);
-    dev_zero(n, sum, (size_t)n->N * sizeof(double));
+    int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
     dev_zero(n, wbits, sizeof(unsigned int));
-    hipLaunchKernelGGL(abs_input_kernel, dim3(grid_for(n->N * 64, 256)), dim3(256), 0, n->stream, n->d_row_start,
-                       n->d_off_rel, n->d_meta, n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0,
-                       n->T, n->d_inst_n0, n->d_inst_offbase, n->d_inst_ntiles, n->d_inst_T, n->n_inst, n->N,
-                       sum, wbits);
+    CX_HIP(hipMemcpyAsync(inst_N, n->inst_N.data(), n->n_inst * sizeof(int64_t), hipMemcpyHostToDevice, n->stream));
+    const size_t lds = (size_t)n->T * sizeof(double);
+    require(lds <= n->dd.lds_cu, CORTEX_EUNSUPPORTED, "tile too large for the input-bound pass");
+    CX_HIP(hipFuncSetAttribute((const void*)abs_input_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(abs_input_kernel, dim3(n->n_tiles), dim3(1024), lds, n->stream, n->d_seg, n->d_meta,
+                       n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0, n->T, n->d_tile_inst,
+                       n->d_tile_size, n->d_inst_tile0, n->d_inst_ntiles, n->d_inst_T, n->d_inst_n0, inst_N,
+                       n->d_inst_offbase, tmax, wbits);
     CX_HIP(hipGetLastError());
-    std::vector<double> h((size_t)n->N);
+    std::vector<double> h((size_t)n->n_tiles);
     unsigned int wb = 0;
-    CX_HIP(hipMemcpyAsync(h.data(), sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    CX_HIP(hipMemcpyAsync(h.data(), tmax, h.size() * sizeof(double), hipMemcpyDeviceToHost, n->stream));
     CX_HIP(hipMemcpyAsync(&wb, wbits, sizeof wb, hipMemcpyDeviceToHost, n->stream));
     CX_HIP(hipStreamSynchronize(n->stream));
     double m = 0.0;

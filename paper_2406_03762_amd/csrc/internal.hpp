@@ -220,6 +220,11 @@ void init_state(cortex_net* n);
 // step.hip
 // Frozen runs pass the per-(step, tile) id lists (frz_ptr into frz_ids,
 // frz_n ids in all); the kernel clamps every list to [0, frz_n).
+// Offsets of a raster sorted by (step, id) (noalloc.hip): ptr[s * n_keys + k]
+// = first entry with (step, id) >= (step0 + s, keys[k]), and ptr[n_steps *
+// n_keys] = first entry past step0 + n_steps; on n->stream.
+void raster_index(cortex_net* n, const uint32_t* steps, const uint32_t* ids, int64_t n_spk, int64_t step0,
+                  int64_t n_steps, const int64_t* keys, int n_keys, uint64_t* ptr);
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                       const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
                       uint8_t* m_trace = nullptr);

@@ -13,6 +13,7 @@
 // The fixed array (kScratchBytes, one copy per GPU, kept until the process
 // ends) is shared by every call on that GPU: calls that overlap on one GPU
 // race, and each call overwrites what the previous one left.
+#include <algorithm>
 #include <mutex>
 
 #include "internal.hpp"
@@ -47,12 +48,13 @@ void* scratch_on(int device) {
     return g_scratch_ptr[device];
 }
 
-// ptr[s * n_tiles + t] = first raster entry with (step, id) >= (step0 + s,
-// tile_start[t]); ptr[n_steps * n_tiles] = first entry with step >= step0 +
-// n_steps.
-__global__ void frozen_index_kernel(const uint32_t* steps, const uint32_t* ids, int64_t n_spk, int64_t step0,
-                                    int64_t n_steps, const int64_t* tile_start, int n_tiles, uint64_t* ptr) {
-    const int64_t total = n_steps * n_tiles + 1;
+// ptr[s * n_keys + k] = first raster entry with (step, id) >= (step0 + s,
+// keys[k]); ptr[n_steps * n_keys] = first entry with step >= step0 +
+// n_steps.  With keys = the tiles' first neurons, [ptr[i], ptr[i + 1]) is
+// the list of (step, tile) i.
+__global__ void raster_index_kernel(const uint32_t* steps, const uint32_t* ids, int64_t n_spk, int64_t step0,
+                                    int64_t n_steps, const int64_t* keys, int n_keys, uint64_t* ptr) {
+    const int64_t total = n_steps * n_keys + 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t key_step, key_id;
@@ -60,8 +62,8 @@ __global__ void frozen_index_kernel(const uint32_t* steps, const uint32_t* ids, 
             key_step = step0 + n_steps;
             key_id = 0;
         } else {
-            key_step = step0 + i / n_tiles;
-            key_id = tile_start[i % n_tiles];
+            key_step = step0 + i / n_keys;
+            key_id = keys[i % n_keys];
         }
         int64_t lo = 0, hi = n_spk;
         while (lo < hi) {
@@ -75,6 +77,16 @@ __global__ void frozen_index_kernel(const uint32_t* steps, const uint32_t* ids, 
 }
 
 }  // namespace
+
+void raster_index(cortex_net* n, const uint32_t* steps, const uint32_t* ids, int64_t n_spk, int64_t step0,
+                  int64_t n_steps, const int64_t* keys, int n_keys, uint64_t* ptr) {
+    const int64_t total = n_steps * n_keys + 1;
+    const int grid = (int)std::min<int64_t>(4096, (total + 255) / 256);
+    hipLaunchKernelGGL(raster_index_kernel, dim3(grid), dim3(256), 0, n->stream, steps, ids, n_spk, step0, n_steps,
+                       keys, n_keys, ptr);
+    CX_HIP(hipGetLastError());
+}
+
 }  // namespace cortex
 
 using namespace cortex;
@@ -112,11 +124,7 @@ extern "C" int cortex_run_frozen_noalloc(cortex_net* n, const uint32_t* r_steps,
             CX_HIP(hipMemcpyAsync(d_steps, r_steps, ras_bytes, hipMemcpyHostToDevice, n->stream));
             CX_HIP(hipMemcpyAsync(d_ids, r_ids, ras_bytes, hipMemcpyHostToDevice, n->stream));
         }
-        const int64_t total = n_steps * n->n_tiles + 1;
-        const int grid = (int)std::min<int64_t>(4096, (total + 255) / 256);
-        hipLaunchKernelGGL(frozen_index_kernel, dim3(grid), dim3(256), 0, n->stream, d_steps, d_ids, n_spikes,
-                           n->step, n_steps, n->d_tile_start, n->n_tiles, d_ptr);
-        CX_HIP(hipGetLastError());
+        raster_index(n, d_steps, d_ids, n_spikes, n->step, n_steps, n->d_tile_start, n->n_tiles, d_ptr);
         advance_fp32(n, n_steps, d_ids, d_ptr, (uint64_t)n_spikes, static_cast<float*>(x_trace),
                      static_cast<float*>(v_trace));
         check_device_flag(n);
