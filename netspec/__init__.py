@@ -70,6 +70,23 @@ class Instance:
         return sum(p.size for p in self.pops)
 
 
+@dataclass(frozen=True)
+class Stdp:
+    """Spike-timing dependent plasticity of the synapses whose source and
+    target both belong to population ``pop`` (global index, instance after
+    instance): power-law potentiation and multiplicative depression with
+    all-to-all pairing, every delay dendritic (the rule is stated in
+    oracle/oracle.h).  ``w0`` and ``wmax`` are in the weights' unit."""
+    pop: int = 0
+    lam: float = 0.05
+    alpha: float = 1.0
+    mu: float = 0.4
+    tau_plus: float = 15.0
+    tau_minus: float = 30.0
+    w0: float = 0.1
+    wmax: float = 0.5
+
+
 @dataclass
 class NetSpec:
     """One or more independent network instances sharing a neuron model.
@@ -99,6 +116,9 @@ class NetSpec:
     instances: List[Instance] = field(default_factory=list)
     precision: str = "fp32"      # "fp32" production or "fp64" verification
     weight_dtype: str = "fp32"   # storage type of weights in fp32 mode: fp32 | bf16
+    # plasticity (None: static synapses); left out of repr() so that the
+    # description of a static network does not change with this option
+    stdp: Optional[Stdp] = field(default=None, repr=False)
 
     @property
     def n_neurons(self) -> int:

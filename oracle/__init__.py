@@ -51,7 +51,10 @@ class _Spec(C.Structure):
                 ("n_instances", C.c_int32), ("n_pops", C.c_int32),
                 ("pops", C.POINTER(_Pop)), ("n_projs", C.c_int32),
                 ("projs", C.POINTER(_Proj)), ("n_sel", C.c_int64),
-                ("sel", C.POINTER(C.c_int64))]
+                ("sel", C.POINTER(C.c_int64)), ("stdp_pop", C.c_int32),
+                ("stdp_lambda", C.c_double), ("stdp_alpha", C.c_double), ("stdp_mu", C.c_double),
+                ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
+                ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double)]
 
 
 _lib = None
@@ -135,6 +138,12 @@ class _SpecHolder:
                        len(spec.instances), len(pops), self.pops, len(projs), self.projs,
                        0 if self.sel is None else len(self.sel),
                        None if self.sel is None else self.sel.ctypes.data_as(C.POINTER(C.c_int64)))
+        st = spec.stdp
+        self.c.stdp_pop = -1 if st is None else st.pop
+        if st is not None:
+            self.c.stdp_lambda, self.c.stdp_alpha, self.c.stdp_mu = st.lam, st.alpha, st.mu
+            self.c.stdp_tau_plus, self.c.stdp_tau_minus = st.tau_plus, st.tau_minus
+            self.c.stdp_w0, self.c.stdp_wmax = st.w0, st.wmax
 
 
 def philox4x64_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:

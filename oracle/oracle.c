@@ -226,6 +226,17 @@ struct orc_net {
     /* spike log */
     int64_t *log_step, *log_id;
     int64_t n_log, cap_log;
+    /* plasticity */
+    int stdp;
+    double dt;
+    int64_t stdp_lo, stdp_hi;               /* plastic population [lo, hi) */
+    double s_lambda, s_alpha, s_mu, s_tp, s_tm, s_w0, s_wmax;
+    unsigned char* plastic;                 /* [E] */
+    double* x_last;                         /* [N] x_j just after its last spike */
+    int64_t* q_last;                        /* [N] last spike step, -1: none */
+    int64_t** hp;                           /* [N] post spike steps, ascending */
+    double** hy;                            /* [N] y_i just after each of them */
+    int64_t *hn, *hcap;                     /* [N] */
 };
 
 void orc_free(orc_net* n) {
@@ -235,6 +246,9 @@ void orc_free(orc_net* n) {
     free(n->U); free(n->y1); free(n->y2); free(n->ring); free(n->r);
     free(n->U0); free(n->y10); free(n->y20); free(n->r0);
     free(n->log_step); free(n->log_id);
+    if (n->hp) for (int64_t i = 0; i < n->N; ++i) { free(n->hp[i]); free(n->hy[i]); }
+    free(n->hp); free(n->hy); free(n->hn); free(n->hcap);
+    free(n->plastic); free(n->x_last); free(n->q_last);
     free(n);
 }
 
@@ -514,6 +528,40 @@ orc_net* orc_build(const orc_spec* s, uint64_t seed) {
         n->U[i] = v - s->E_L;
         n->U0[i] = n->U[i];
     }
+    /* plasticity: the synapses inside population stdp_pop */
+    if (s->stdp_pop >= 0) {
+        if (s->stdp_pop >= s->n_pops) { set_err("stdp_pop out of range"); goto fail; }
+        if (!(s->stdp_lambda >= 0.0 && s->stdp_alpha >= 0.0 && s->stdp_tau_plus > 0.0 &&
+              s->stdp_tau_minus > 0.0 && s->stdp_w0 > 0.0 && s->stdp_wmax > 0.0)) {
+            set_err("bad plasticity parameters"); goto fail;
+        }
+        double cw = (s->weight_unit == ORC_UNIT_PSP_MV) ? k.conv : 1.0;
+        n->stdp = 1;
+        n->dt = s->dt;
+        n->stdp_lo = pop_off[s->stdp_pop];
+        n->stdp_hi = pop_off[s->stdp_pop + 1];
+        n->s_lambda = s->stdp_lambda;
+        n->s_alpha = s->stdp_alpha;
+        n->s_mu = s->stdp_mu;
+        n->s_tp = s->stdp_tau_plus;
+        n->s_tm = s->stdp_tau_minus;
+        n->s_w0 = s->stdp_w0 * cw;
+        n->s_wmax = s->stdp_wmax * cw;
+        n->plastic = (unsigned char*)calloc((size_t)(n->E > 0 ? n->E : 1), 1);
+        n->x_last = (double*)calloc((size_t)n->N, sizeof(double));
+        n->q_last = (int64_t*)malloc((size_t)n->N * sizeof(int64_t));
+        n->hp = (int64_t**)calloc((size_t)n->N, sizeof(int64_t*));
+        n->hy = (double**)calloc((size_t)n->N, sizeof(double*));
+        n->hn = (int64_t*)calloc((size_t)n->N, sizeof(int64_t));
+        n->hcap = (int64_t*)calloc((size_t)n->N, sizeof(int64_t));
+        if (!n->plastic || !n->x_last || !n->q_last || !n->hp || !n->hy || !n->hn || !n->hcap) {
+            set_err("out of memory"); goto fail;
+        }
+        for (int64_t i = 0; i < n->N; ++i) n->q_last[i] = -1;
+        for (int64_t e = 0; e < n->E; ++e)
+            n->plastic[e] = n->src[e] >= n->stdp_lo && n->src[e] < n->stdp_hi &&
+                            n->tgt[e] >= n->stdp_lo && n->tgt[e] < n->stdp_hi;
+    }
     free(pop_off);
     free(pop_local);
     return n;
@@ -562,6 +610,13 @@ int orc_reset(orc_net* n) {
     n->t = 0;
     n->events = 0.0;
     n->n_log = 0;
+    if (n->stdp) {   /* traces and histories restart; the weights stay */
+        for (int64_t i = 0; i < n->N; ++i) {
+            n->x_last[i] = 0.0;
+            n->q_last[i] = -1;
+            n->hn[i] = 0;
+        }
+    }
     return 0;
 }
 
@@ -643,13 +698,77 @@ static int log_spike(orc_net* n, int64_t step, int64_t id) {
     return 0;
 }
 
+/* Plasticity bookkeeping of a postsynaptic spike of i at step p: the
+   trace y_i just after it, appended to i's history. */
+static int stdp_post(orc_net* n, int64_t i, int64_t p) {
+    if (!n->stdp) return 0;
+    int64_t m = n->hn[i];
+    double y = 1.0;
+    if (m > 0) y += n->hy[i][m - 1] * exp(-(double)(p - n->hp[i][m - 1]) * n->dt / n->s_tm);
+    if (m == n->hcap[i]) {
+        int64_t nc = m ? 2 * m : 16;
+        int64_t* a = (int64_t*)realloc(n->hp[i], (size_t)nc * sizeof(int64_t));
+        if (!a) return -1;
+        n->hp[i] = a;
+        double* b = (double*)realloc(n->hy[i], (size_t)nc * sizeof(double));
+        if (!b) return -1;
+        n->hy[i] = b;
+        n->hcap[i] = nc;
+    }
+    n->hp[i][m] = p;
+    n->hy[i][m] = y;
+    n->hn[i] = m + 1;
+    return 0;
+}
+
+/* New weight of plastic synapse e (source j, target i, delay d) when the
+   spike of j at step q is delivered (the rule of oracle.h). */
+static double stdp_weight(const orc_net* n, int64_t e, int64_t j, int64_t q) {
+    const double dt = n->dt;
+    const int64_t i = n->tgt[e], d = n->d[e];
+    const int64_t m = n->hn[i];
+    const int64_t* hp = n->hp[i];
+    double w = n->w[e];
+    if (n->q_last[j] >= 0) {
+        const int64_t ql = n->q_last[j];
+        const double c = n->s_lambda * pow(n->s_w0, 1.0 - n->s_mu);
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t a = hp[k] + d;   /* arrival of the post spike at the synapse */
+            if (a <= ql) continue;
+            if (a > q) break;
+            const double x = n->x_last[j] * exp(-(double)(a - ql) * dt / n->s_tp);
+            w = w + c * pow(w, n->s_mu) * x;
+            if (w > n->s_wmax) w = n->s_wmax;
+        }
+    }
+    /* y_i at q - d: the latest post spike strictly before it */
+    double y = 0.0;
+    for (int64_t k = m - 1; k >= 0; --k) {
+        if (hp[k] < q - d) {
+            y = n->hy[i][k] * exp(-(double)(q - d - hp[k]) * dt / n->s_tm);
+            break;
+        }
+    }
+    w = w - n->s_lambda * n->s_alpha * w * y;
+    if (w < 0.0) w = 0.0;
+    return w;
+}
+
 static void push_spike(orc_net* n, int64_t step, int64_t j) {
     for (int64_t q = n->outptr[j]; q < n->outptr[j + 1]; ++q) {
         int64_t e = n->outidx[q];
+        if (n->stdp && n->plastic[e]) n->w[e] = stdp_weight(n, e, j, step);
         int64_t slot = (step + n->d[e]) % n->D;
         int64_t tg = n->tgt[e];
         n->ring[tg * n->D + slot] += n->w[e];
         n->events += 1.0;
+    }
+    if (n->stdp) {
+        /* the presynaptic trace just after this spike */
+        double x = 1.0;
+        if (n->q_last[j] >= 0) x += n->x_last[j] * exp(-(double)(step - n->q_last[j]) * n->dt / n->s_tp);
+        n->x_last[j] = x;
+        n->q_last[j] = step;
     }
 }
 
@@ -669,7 +788,9 @@ int orc_run(orc_net* n, int64_t n_steps) {
                 n->U[i] = n->Ur;
                 n->r[i] = n->k.n_ref;
                 spk[ns++] = i;
-                if (log_spike(n, step, i)) { free(spk); set_err("out of memory"); return -1; }
+                if (log_spike(n, step, i) || stdp_post(n, i, step)) {
+                    free(spk); set_err("out of memory"); return -1;
+                }
             }
         }
         for (int64_t q = 0; q < ns; ++q) push_spike(n, step, spk[q]);
@@ -726,7 +847,11 @@ static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t
             /* the membrane potential the threshold test of a closed-loop run
                would see (NaN on refractory steps, which take no test) */
             if (vpre && c >= 0) vpre[s * n->n_rec + c] = integ ? n->U[i] + n->E_L : NAN;
-            if (spk) { n->U[i] = n->Ur; n->r[i] = n->k.n_ref; }
+            if (spk) {
+                n->U[i] = n->Ur;
+                n->r[i] = n->k.n_ref;
+                if (stdp_post(n, i, step)) { set_err("out of memory"); return -1; }
+            }
             if (c >= 0) {
                 if (xt) xt[s * n->n_rec + c] = x;
                 if (vt) vt[s * n->n_rec + c] = n->U[i] + n->E_L;

@@ -59,7 +59,30 @@ typedef struct {
        traces and target voltages then have n_sel columns */
     int64_t n_sel;
     const int64_t* sel;
+    /* optional spike-timing dependent plasticity (orc_stdp_* below) of the
+       synapses whose source and target both belong to population stdp_pop
+       (global index; -1: none) */
+    int32_t stdp_pop;
+    double stdp_lambda, stdp_alpha, stdp_mu;   /* step size, depression ratio, potentiation exponent */
+    double stdp_tau_plus, stdp_tau_minus;      /* pre- and postsynaptic trace time constants (ms) */
+    double stdp_w0, stdp_wmax;                 /* reference and largest weight (the weights' unit) */
 } orc_spec;
+
+/* Plasticity rule (read from the paper's verification network: E->E
+   synapses with multiplicative depression and power-law potentiation).
+   All of a synapse's delay d is dendritic: a presynaptic spike at step q is
+   at the synapse at q, a postsynaptic spike at step p reaches it at p + d.
+   Traces (all-to-all pairing, time in ms = steps x dt):
+     x_j(t) = sum over spikes q' <= t of source j of exp(-(t - q') / tau_plus)
+     y_i(t) = sum over spikes p < t of target i of exp(-(t - p) / tau_minus)
+   When the spike of j at step q is delivered, each plastic synapse (j, i, d)
+   first takes, in ascending p, the postsynaptic spikes p of i with
+   q_last < p + d <= q (q_last: j's previous spike; none before j's first):
+     w <- min(w_max, w + lambda w0^(1 - mu) w^mu x_j(p + d)),
+   with x_j(p + d) counting the spikes up to q_last only; then
+     w <- max(0, w - lambda alpha w y_i(q - d)),
+   and the spike is delivered with the new w.  Weights are not restored by
+   orc_reset. */
 
 typedef struct orc_net orc_net;
 
