@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CORTEX_ABI_VERSION 2
+#define CORTEX_ABI_VERSION 3
 
 typedef enum {
     CORTEX_OK = 0,
@@ -123,6 +123,29 @@ typedef struct {
     int32_t steps_per_sync;   /* FP32: time steps per exchange of spikes, 1..min(d_min, 8) (0 = auto) */
     int32_t plan_kind;        /* FP32: CORTEX_PLAN_* */
     int32_t wg_per_cu;        /* FP32 resident plan: workgroups per compute unit, 1, 2, 4, 8 (0 = auto) */
+    /* Spike-timing dependent plasticity (the E->E plasticity of the paper's
+       verification network, Sec. IV-A) of the synapses whose source and
+       target both belong to population stdp_pop (global index), when
+       stdp_enable != 0.  FP32 weights and the streamed plan only; the
+       exchange window is cut to at most n_ref + 1 steps, so that a source
+       spikes at most once per window.  Rule (all-to-all pairing, every delay
+       dendritic: a presynaptic spike at step q is at the synapse at q, a
+       postsynaptic spike at step p reaches it at p + d; times in ms):
+         x_j(t) = sum over spikes q' <= t of source j of exp(-(t - q') / tau_plus)
+         y_i(t) = sum over spikes p < t of target i of exp(-(t - p) / tau_minus)
+       When the spike of j at step q is delivered, each plastic synapse
+       (j, i, d) takes, in ascending p, the spikes p of i with
+       q_last < p + d <= q (q_last: j's previous spike):
+         w <- min(w_max, w + lambda w0^(1 - mu) w^mu x_j(p + d))
+       (x_j counting j's spikes up to q_last), then
+         w <- max(0, w - lambda alpha w y_i(q - d)),
+       and the spike is delivered with the new w.  A neuron keeps its last
+       32 spikes for this; a synapse that would need an older one makes the
+       call fail with CORTEX_ETRUNC.  w0 and w_max are in the weights' unit.
+       cortex_reset keeps the weights. */
+    int32_t stdp_enable;
+    int32_t stdp_pop;
+    double stdp_lambda, stdp_alpha, stdp_mu, stdp_tau_plus, stdp_tau_minus, stdp_w0, stdp_wmax;
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device

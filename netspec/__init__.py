@@ -374,6 +374,26 @@ def target_trace(n_neurons: int, n_steps: int, lo: float, hi: float,
     return rng.uniform(lo, hi, size=(n_steps, n_neurons))
 
 
+def refractory_raster(n_neurons: int, n_steps: int, p_spike: float, n_ref: int, seed: int,
+                      step0: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """A raster in which every neuron spikes with probability ``p_spike`` per
+    step but never within ``n_ref`` steps of its previous spike (as a
+    refractory neuron would); sorted by (step, id)."""
+    rng = np.random.default_rng(seed)
+    last = np.full(n_neurons, -10 ** 9, np.int64)
+    steps_l, ids_l = [], []
+    for s in range(n_steps):
+        cand = np.nonzero(rng.random(n_neurons) < p_spike)[0]
+        ok = cand[s - last[cand] > n_ref]
+        if len(ok):
+            last[ok] = s
+            ids_l.append(ok.astype(np.uint32))
+            steps_l.append(np.full(len(ok), s + step0, np.uint32))
+    if not steps_l:
+        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    return np.concatenate(steps_l), np.concatenate(ids_l)
+
+
 def sample_targets(n_neurons: int, n_sample: int, seed: int) -> np.ndarray:
     """Sorted distinct neuron ids for sampled checks at full size."""
     rng = np.random.default_rng(seed)

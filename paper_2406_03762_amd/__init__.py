@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcortex.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cortex.h")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
 Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
          STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
@@ -56,7 +56,10 @@ class cortex_spec(C.Structure):
                 ("tile_size", C.c_int32), ("block_size", C.c_int32), ("record_steps", C.c_int64),
                 ("ckpt_every", C.c_int32), ("adjoint_steps", C.c_int64),
                 ("spin_limit_log2", C.c_int32), ("steps_per_sync", C.c_int32),
-                ("plan_kind", C.c_int32), ("wg_per_cu", C.c_int32)]
+                ("plan_kind", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("stdp_enable", C.c_int32), ("stdp_pop", C.c_int32), ("stdp_lambda", C.c_double),
+                ("stdp_alpha", C.c_double), ("stdp_mu", C.c_double), ("stdp_tau_plus", C.c_double),
+                ("stdp_tau_minus", C.c_double), ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -186,6 +189,11 @@ def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 
     s.spin_limit_log2 = spin_limit_log2
     s.steps_per_sync = steps_per_sync
     s.plan_kind = _PLAN[plan]
+    st = getattr(net, "stdp", None)
+    if st is not None:
+        s.stdp_enable, s.stdp_pop = 1, st.pop
+        s.stdp_lambda, s.stdp_alpha, s.stdp_mu = st.lam, st.alpha, st.mu
+        s.stdp_tau_plus, s.stdp_tau_minus, s.stdp_w0, s.stdp_wmax = st.tau_plus, st.tau_minus, st.w0, st.wmax
     s.wg_per_cu = wg_per_cu
     return s, (pa, qa)
 
@@ -491,7 +499,9 @@ def tune_key(spec, device: dict) -> str:
     text (sizes, connectivity, delays, models, precision) and the device's
     name and compute-unit count."""
     import hashlib
-    return hashlib.sha256(f"{spec!r}|{device['name']}|{device['n_cu']}".encode()).hexdigest()[:24]
+    plastic = getattr(spec, "stdp", None)
+    extra = "" if plastic is None else f"|{plastic!r}"
+    return hashlib.sha256(f"{spec!r}{extra}|{device['name']}|{device['n_cu']}".encode()).hexdigest()[:24]
 
 
 def _read_table(path: str) -> dict:

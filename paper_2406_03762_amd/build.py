@@ -22,6 +22,7 @@ SOURCES = [
     ("adjoint.hip", []),
     ("stream.hip", []),
     ("noalloc.hip", []),
+    ("stdp.hip", []),
 ]
 
 ARCH = os.environ.get("CORTEX_OFFLOAD_ARCH", "gfx950")

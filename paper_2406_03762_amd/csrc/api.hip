@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -211,6 +212,17 @@ static void validate(const cortex_spec* s) {
     require(s->wg_per_cu == 0 || s->wg_per_cu == 1 || s->wg_per_cu == 2 || s->wg_per_cu == 4 || s->wg_per_cu == 8,
             CORTEX_EINVAL, "wg_per_cu must be 0, 1, 2, 4 or 8");
     require(s->n_projs >= 0 && (s->n_projs == 0 || s->projs), CORTEX_EINVAL, "projection list is NULL");
+    if (s->stdp_enable) {
+        require(s->stdp_pop >= 0 && s->stdp_pop < s->n_pops, CORTEX_EINVAL, "stdp_pop out of range");
+        require(s->stdp_lambda >= 0 && s->stdp_alpha >= 0 && s->stdp_tau_plus > 0 && s->stdp_tau_minus > 0 &&
+                    s->stdp_w0 > 0 && s->stdp_wmax > 0,
+                CORTEX_EINVAL, "bad plasticity parameters");
+        require(s->precision == CORTEX_FP32 && s->weight_dtype == CORTEX_W_FP32, CORTEX_EUNSUPPORTED,
+                "plasticity needs FP32 precision and FP32 weights");
+        require(s->ckpt_every == 0, CORTEX_EUNSUPPORTED, "the adjoint of a plastic network is not supported");
+        require(s->plan_kind != CORTEX_PLAN_RESIDENT, CORTEX_EUNSUPPORTED,
+                "plasticity runs on the streamed plan only");
+    }
     int prev = 0;
     std::vector<int> seen(s->n_instances, 0);
     int64_t N = 0;
@@ -564,6 +576,13 @@ static void plan_stream(cortex_net* n) {
     const size_t lds_cu = n->dd.lds_cu;
     const int per_cu = s.wg_per_cu > 0 ? s.wg_per_cu : 1;
     n->W = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(n->dmin, 8);
+    if (s.stdp_enable) {
+        // a source spikes at most once per window, so that the plasticity
+        // pass updates each synapse at most once per launch
+        require(s.steps_per_sync == 0 || s.steps_per_sync <= n->k.n_ref + 1, CORTEX_EINVAL,
+                "with plasticity steps_per_sync must be at most n_ref + 1");
+        n->W = std::min(n->W, n->k.n_ref + 1);
+    }
     n->R = n->dmax - n->dmin + n->W;
     n->H = pow2_at_least(n->dmin + 2 * n->W);
     n->ring_bytes = 4;
@@ -697,7 +716,7 @@ static void plan_fp32(cortex_net* n) {
     const int W0 = s.steps_per_sync > 0 ? s.steps_per_sync : std::min(dmin, 8);
     require(W0 >= 1 && W0 <= dmin && W0 <= 8, CORTEX_EINVAL, "steps_per_sync must lie in [1, min(d_min, 8)]");
     bool planned = false;
-    if (s.plan_kind != CORTEX_PLAN_STREAMED) {
+    if (s.plan_kind != CORTEX_PLAN_STREAMED && !s.stdp_enable) {
         n->plan_kind = CORTEX_PLAN_RESIDENT;
         for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
             n->ring_bytes = rb;
@@ -769,6 +788,13 @@ static void alloc_state_fp32(cortex_net* n) {
         n->d_spk_ids = dev_alloc_t<uint32_t>(n, (size_t)n->H * n->N);
         n->d_clock = dev_alloc_t<int64_t>(n, 2);
         n->use_graph = true;
+        if (n->stdp) {
+            n->d_seg_state = dev_alloc_t<uint64_t>(n, std::max<uint64_t>(1, n->n_seg));
+            n->d_hist_step = dev_alloc_t<int32_t>(n, (size_t)n->N * kHistLen);
+            n->d_hist_y = dev_alloc_t<float>(n, (size_t)n->N * kHistLen);
+            n->d_hist_cnt = dev_alloc_t<uint32_t>(n, n->N);
+            n->d_hist_upto = dev_alloc_t<int64_t>(n, n->n_tiles);
+        }
     } else {
         // (+8 words: a reader fetches a few id words past a record without bounds checks)
         n->d_pub = dev_alloc_t<uint64_t>(n, (size_t)n->H * n->n_tiles * (n->T + 1) + 8);
@@ -810,6 +836,11 @@ static void zero_dynamic_fp32(cortex_net* n) {
         dev_zero(n, n->d_clock, 2 * sizeof(int64_t));
         n->clock_parity = 0;
         drop_graph(n);
+        if (n->stdp) {   // traces and histories restart; the weights stay
+            dev_zero(n, n->d_seg_state, std::max<uint64_t>(1, n->n_seg) * sizeof(uint64_t));
+            dev_zero(n, n->d_hist_cnt, (size_t)n->N * sizeof(uint32_t));
+            dev_zero(n, n->d_hist_upto, (size_t)n->n_tiles * sizeof(int64_t));
+        }
     } else {
         dev_zero(n, n->d_pub, (size_t)n->H * n->n_tiles * (n->T + 1) * sizeof(uint64_t));
     }
@@ -851,11 +882,16 @@ static void zero_dynamic_fp64(cortex_net* n) {
 // Device error flag raised by a kernel (a wait that exceeded its limit).
 void check_device_flag(cortex_net* n) {
     CX_HIP(hipStreamSynchronize(n->stream));
-    int32_t e = 0;
-    CX_HIP(hipMemcpy(&e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
-    if (e != 0) {
+    int32_t e[2] = {0, 0};
+    CX_HIP(hipMemcpy(e, n->d_err, sizeof e, hipMemcpyDeviceToHost));
+    if (e[0] != 0) {
         n->failed = true;
         throw Error{CORTEX_ETIMEOUT, "a device-side wait exceeded its spin limit; network state is invalid"};
+    }
+    if (e[1] != 0) {
+        n->failed = true;
+        throw Error{CORTEX_ETRUNC, "a plastic synapse needed a postsynaptic spike older than the 32 a neuron "
+                                   "keeps; weights are invalid"};
     }
 }
 
@@ -865,6 +901,20 @@ static void build(cortex_net* n) {
     n->n_thr = poisson_thresholds(s.poisson_lambda, n->thr, 64);
     require(n->n_thr >= 0, CORTEX_EINVAL, "Poisson table too long");
     n->w_ext_native = (s.weight_unit == CORTEX_UNIT_PSP_MV && n->k.conv != 1.0) ? s.w_ext * n->k.conv : s.w_ext;
+    if (s.stdp_enable && s.precision == CORTEX_FP32) {
+        const double cw = (s.weight_unit == CORTEX_UNIT_PSP_MV && n->k.conv != 1.0) ? n->k.conv : 1.0;
+        int64_t off = 0;
+        for (int p = 0; p < s.stdp_pop; ++p) off += n->pops[p].size;
+        n->stdp = true;
+        n->stdp_lo = off;
+        n->stdp_hi = off + n->pops[s.stdp_pop].size;
+        n->stdp_c = s.stdp_lambda * std::pow(s.stdp_w0 * cw, 1.0 - s.stdp_mu);
+        n->stdp_lam_alpha = s.stdp_lambda * s.stdp_alpha;
+        n->stdp_mu = s.stdp_mu;
+        n->stdp_tp = s.stdp_tau_plus;
+        n->stdp_tm = s.stdp_tau_minus;
+        n->stdp_wmax = s.stdp_wmax * cw;
+    }
     make_blocks(n);
     n->d_inst_n0 = dev_alloc_t<int64_t>(n, n->n_inst);
     upload(n, n->d_inst_n0, n->inst_n0);
@@ -1060,6 +1110,23 @@ using namespace cortex;
         return CORTEX_EDEVICE;                               \
     }
 
+// A frozen raster given to a plastic network keeps the refractory period of
+// the plastic neurons (consecutive spikes at least n_ref + 1 steps apart),
+// as closed-loop spikes do: then no source spikes twice in one window, and
+// the plasticity pass updates each synapse at most once per launch.
+void cortex::check_plastic_raster(const cortex_net* n, const uint32_t* st, const uint32_t* id, int64_t ns) {
+    if (!n->stdp) return;
+    std::unordered_map<uint32_t, uint32_t> last;
+    for (int64_t q = 0; q < ns; ++q) {
+        if ((int64_t)id[q] < n->stdp_lo || (int64_t)id[q] >= n->stdp_hi) continue;
+        auto it = last.find(id[q]);
+        if (it != last.end())
+            require((int64_t)st[q] - (int64_t)it->second >= (int64_t)n->k.n_ref + 1, CORTEX_EINVAL,
+                    "a plastic neuron spikes twice within its refractory period in the raster");
+        last[id[q]] = st[q];
+    }
+}
+
 static void require_net(cortex_net* n) {
     require(n != nullptr, CORTEX_EINVAL, "network handle is NULL");
     require(!n->failed, CORTEX_ESTATE, "network failed earlier; destroy it");
@@ -1124,6 +1191,7 @@ int cortex_plan(const cortex_spec* spec, int32_t n_cu, int64_t lds_per_cu, int32
         n->dd.thr_cu = threads_per_cu;
         n->dd.live = false;
         n->ckpt = spec->ckpt_every;
+        n->k = model_constants(n->spec);
         make_blocks(n);
         host_delay_range(n, &n->dmin, &n->dmax, true);
         plan_fp32(n);
@@ -1201,6 +1269,7 @@ int cortex_run_frozen(cortex_net* n, const uint32_t* r_steps, const uint32_t* r_
                 CORTEX_EINVAL, "raster must be sorted by (step, id) without duplicates");
     }
     if (n_steps == 0) return CORTEX_OK;
+    check_plastic_raster(n, r_steps, r_ids, n_spikes);
     if (n->spec.precision == CORTEX_FP64_VERIFY) {
         std::vector<uint64_t> bits((size_t)n_steps * n->W64, 0);
         for (int64_t q = 0; q < n_spikes; ++q) {
@@ -1307,6 +1376,7 @@ int cortex_get_state(cortex_net* n, double* V, int32_t* r, double* y1, double* y
 int cortex_export_graph(cortex_net* n, int64_t* src, int64_t* tgt, double* w, int32_t* d) {
     CX_API_BEGIN
     require_net(n);
+    if (n->stdp) check_device_flag(n);   // plastic weights are valid only if no history ran short
     if (n->spec.precision == CORTEX_FP64_VERIFY) {
         auto ptr = download(n, n->d_in_ptr, n->N + 1);
         auto s = download(n, n->d_in_src, n->E);

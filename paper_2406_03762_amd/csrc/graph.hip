@@ -548,6 +548,7 @@ __global__ void __launch_bounds__(1024) abs_input_kernel(const uint64_t* seg, co
                                                          const int32_t* inst_tile0, const int32_t* inst_ntiles,
                                                          const int32_t* inst_T, const int64_t* inst_n0,
                                                          const int64_t* inst_N, const uint64_t* inst_offbase,
+                                                         int64_t plo, int64_t phi, float w_plastic,
                                                          double* tile_max, unsigned int* wmax_bits) {
     extern __shared__ double s_sum[];   // [T]
     __shared__ unsigned int s_wmax;
@@ -558,6 +559,7 @@ __global__ void __launch_bounds__(1024) abs_input_kernel(const uint64_t* seg, co
     const int tsz = tile_size[tile];
     const int64_t n0b = inst_n0[b], Nb = inst_N[b];
     const uint64_t offb = inst_offbase[b];
+    const int64_t g0 = n0b + (int64_t)tl * inst_T[b];
     for (int i = threadIdx.x; i < T; i += blockDim.x) s_sum[i] = 0.0;
     if (threadIdx.x == 0) s_wmax = 0u;
     __syncthreads();
@@ -576,7 +578,10 @@ __global__ void __launch_bounds__(1024) abs_input_kernel(const uint64_t* seg, co
                 m = meta16 ? static_cast<const uint16_t*>(meta)[e] : static_cast<const uint32_t*>(meta)[e];
                 wv = static_cast<const float*>(w)[e];
             }
-            const float aw = fabsf(wv);
+            // a plastic synapse (source and target in [plo, phi)) may grow to w_plastic
+            const int64_t tg = g0 + (int64_t)(m % (uint32_t)T);
+            const bool plastic = n0b + j >= plo && n0b + j < phi && tg >= plo && tg < phi;
+            const float aw = plastic ? fmaxf(w_plastic, fabsf(wv)) : fabsf(wv);
             atomicAdd(&s_sum[m % (uint32_t)T], (double)aw);
             my_max = max(my_max, __float_as_uint(aw));   // non-negative floats order as integers
         }
@@ -612,7 +617,8 @@ double max_abs_input(cortex_net* n, double* wmax) {
     hipLaunchKernelGGL(abs_input_kernel, dim3(n->n_tiles), dim3(1024), lds, n->stream, n->d_seg, n->d_meta,
                        n->meta_bytes == 2 ? 1 : 0, n->d_w, n->w_bytes == 2 ? 1 : 0, n->T, n->d_tile_inst,
                        n->d_tile_size, n->d_inst_tile0, n->d_inst_ntiles, n->d_inst_T, n->d_inst_n0, inst_N,
-                       n->d_inst_offbase, tmax, wbits);
+                       n->d_inst_offbase, n->stdp ? n->stdp_lo : (int64_t)0, n->stdp ? n->stdp_hi : (int64_t)0,
+                       (float)n->stdp_wmax, tmax, wbits);
     CX_HIP(hipGetLastError());
     std::vector<double> h((size_t)n->n_tiles);
     unsigned int wb = 0;
@@ -697,6 +703,7 @@ void build_graph_fp32(cortex_net* n) {
     n->E = (int64_t)E;
     // one-load segment descriptors for the step kernels
     n->d_seg = dev_alloc_t<uint64_t>(n, cnt_len);
+    n->n_seg = cnt_len;
     {
         int32_t* bad = dev_alloc_t<int32_t>(n, 1, true);
         dev_zero(n, bad, sizeof(int32_t));

@@ -164,6 +164,19 @@ struct cortex_net {
     int clock_parity = 0;
     int thread_segments = 0;           // streamed delivery with one thread per (short) segment
     bool use_graph = true;
+    // plasticity (streamed plan): per (source, tile) segment the presynaptic
+    // trace just after the source's last spike and that spike's step + 1
+    // (0: none); per neuron the steps and traces of its last kHistLen
+    // spikes; per tile the first step not yet in its targets' histories
+    bool stdp = false;
+    int64_t stdp_lo = 0, stdp_hi = 0;     // plastic population, global ids [lo, hi)
+    double stdp_c = 0, stdp_lam_alpha = 0, stdp_mu = 0, stdp_tp = 0, stdp_tm = 0, stdp_wmax = 0;
+    uint64_t n_seg = 0;                   // entries of d_seg
+    uint64_t* d_seg_state = nullptr;      // [n_seg] float x | (q + 1) << 32
+    int32_t* d_hist_step = nullptr;       // [N][kHistLen]
+    float* d_hist_y = nullptr;            // [N][kHistLen]
+    uint32_t* d_hist_cnt = nullptr;       // [N] spikes recorded so far
+    int64_t* d_hist_upto = nullptr;       // [n_tiles]
     hipGraphExec_t graph_exec = nullptr;   // kGraphWindows window launches
     hipStream_t graph_stream = nullptr;    // library stream the graph is captured on and replayed on
     hipEvent_t fence_in = nullptr, fence_out = nullptr;   // order it after / before the caller's stream
@@ -225,6 +238,12 @@ void init_state(cortex_net* n);
 // n_keys] = first entry past step0 + n_steps; on n->stream.
 void raster_index(cortex_net* n, const uint32_t* steps, const uint32_t* ids, int64_t n_spk, int64_t step0,
                   int64_t n_steps, const int64_t* keys, int n_keys, uint64_t* ptr);
+// Rejects (EINVAL) a frozen raster in which a plastic neuron spikes twice
+// within its refractory period (api.hip).
+void check_plastic_raster(const cortex_net* n, const uint32_t* st, const uint32_t* id, int64_t ns);
+// Plasticity pass of one window of the streamed plan (stdp.hip): on `stream`,
+// before the window's delivery launch with the same clock parity and length.
+void launch_stdp(cortex_net* n, int parity, int wn, hipStream_t stream);
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                       const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
                       uint8_t* m_trace = nullptr);
@@ -234,7 +253,8 @@ void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const
                uint64_t n_ids);
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_bytes);
 // stream.hip: window launches of the streamed plan
-constexpr int kGraphWindows = 32;   // window launches per captured graph (even)
+constexpr int kGraphWindows = 32;
+constexpr int kHistLen = 32;   // postsynaptic spikes a neuron keeps for plasticity   // window launches per captured graph (even)
 size_t stream_lds_bytes(int R, int T, int W, int chunk);
 int stream_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds);
 void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids, const uint64_t* frz_ptr,

@@ -107,6 +107,7 @@ extern "C" int cortex_run_frozen_noalloc(cortex_net* n, const uint32_t* r_steps,
                     CORTEX_EINVAL, "raster must be sorted by (step, id) without duplicates");
         }
         if (n_steps == 0) return CORTEX_OK;
+        check_plastic_raster(n, r_steps, r_ids, n_spikes);
         // layout: list offsets [n_steps * n_tiles + 1] u64, raster steps and ids u32
         const size_t ptr_bytes = ((size_t)n_steps * n->n_tiles + 1) * sizeof(uint64_t);
         const size_t ras_bytes = (size_t)n_spikes * sizeof(uint32_t);

@@ -548,6 +548,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
 }
 
 static void launch_window(cortex_net* n, StreamFn f, StreamArgs& a, int wn, hipStream_t stream) {
+    if (n->stdp) launch_stdp(n, n->clock_parity, wn, stream);   // weights first, then their delivery
     a.parity = n->clock_parity;
     a.wn = wn;
     hipLaunchKernelGGL(f, dim3(n->n_tiles), dim3(n->BS), n->lds_bytes, stream, a);

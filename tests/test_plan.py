@@ -130,3 +130,28 @@ def test_tuned_plan_table_lookup(tmp_path):
     assert cx.lookup_plan(WORKLOADS["brunel_112k"], dev, paths=[str(path)]) == (None, None)
     # a missing or foreign file is an empty table
     assert cx.lookup_plan(spec, dev, paths=[str(tmp_path / "none.json")]) == (None, None)
+
+
+def test_plasticity_plans_are_streamed_with_short_windows():
+    base = netspec.small_brunel(n_e=800, n_i=200, c_e=80, c_i=20, delay="const", d0=3.0, J=0.2)
+    spec = netspec.NetSpec(**{**base.__dict__, "stdp": netspec.Stdp(pop=0, w0=0.2, wmax=0.6)})
+    p = cx.cortex_plan(spec, **MI355X)
+    check(p, spec)
+    # a source spikes at most once per window: W <= n_ref + 1 = 21
+    assert p["plan"] == cx.PLAN_STREAMED and p["W"] == 8
+    short = netspec.NetSpec(**{**spec.__dict__, "t_ref": 0.3})   # n_ref = 3
+    assert cx.cortex_plan(short, **MI355X)["W"] == 4
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(short, steps_per_sync=8, **MI355X)
+    assert e.value.status == cx.EINVAL
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(spec, plan="resident", **MI355X)
+    assert e.value.status == cx.EUNSUPPORTED
+    bf16 = netspec.NetSpec(**{**spec.__dict__, "weight_dtype": "bf16"})
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(bf16, **MI355X)
+    assert e.value.status == cx.EUNSUPPORTED
+    bad = netspec.NetSpec(**{**spec.__dict__, "stdp": netspec.Stdp(pop=5)})
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(bad, **MI355X)
+    assert e.value.status == cx.EINVAL
