@@ -22,7 +22,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-MODELS = ("delta", "exp", "alpha")
+MODELS = ("delta", "exp", "alpha", "cond")
 RULES = ("fixed_indegree", "pairwise")
 DELAYS = ("const", "uniform_int", "normal")
 WEIGHT_UNITS = ("native", "psp_mV")
@@ -116,6 +116,10 @@ class NetSpec:
     instances: List[Instance] = field(default_factory=list)
     precision: str = "fp32"      # "fp32" production or "fp64" verification
     weight_dtype: str = "fp32"   # storage type of weights in fp32 mode: fp32 | bf16
+    # reversal potentials (mV) of the conductance model ("cond"); like stdp,
+    # left out of repr() so that other models' descriptions do not change
+    E_ex: float = field(default=0.0, repr=False)
+    E_in: float = field(default=-85.0, repr=False)
     # plasticity (None: static synapses); left out of repr() so that the
     # description of a static network does not change with this option
     stdp: Optional[Stdp] = field(default=None, repr=False)

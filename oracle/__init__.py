@@ -54,7 +54,8 @@ class _Spec(C.Structure):
                 ("sel", C.POINTER(C.c_int64)), ("stdp_pop", C.c_int32),
                 ("stdp_lambda", C.c_double), ("stdp_alpha", C.c_double), ("stdp_mu", C.c_double),
                 ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
-                ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double)]
+                ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double),
+                ("E_ex", C.c_double), ("E_in", C.c_double)]
 
 
 _lib = None
@@ -107,7 +108,7 @@ def _err(rc: int, what: str) -> None:
         raise RuntimeError(f"oracle {what} failed ({rc}): {lib().orc_last_error().decode()}")
 
 
-_MODEL = {"delta": 0, "exp": 1, "alpha": 2}
+_MODEL = {"delta": 0, "exp": 1, "alpha": 2, "cond": 3}
 _RULE = {"fixed_indegree": 0, "pairwise": 1}
 _DELAY = {"const": 0, "uniform_int": 1, "normal": 2}
 _UNIT = {"native": 0, "psp_mV": 1}
@@ -138,6 +139,7 @@ class _SpecHolder:
                        len(spec.instances), len(pops), self.pops, len(projs), self.projs,
                        0 if self.sel is None else len(self.sel),
                        None if self.sel is None else self.sel.ctypes.data_as(C.POINTER(C.c_int64)))
+        self.c.E_ex, self.c.E_in = spec.E_ex, spec.E_in
         st = spec.stdp
         self.c.stdp_pop = -1 if st is None else st.pop
         if st is not None:

@@ -135,6 +135,9 @@ static int constants(const orc_spec* s, consts_t* k) {
     double dt = s->dt, tm = s->tau_m, ts = s->tau_syn, C = s->C_m;
     if (!(dt > 0) || !(tm > 0) || !(C > 0)) { set_err("dt, tau_m, C_m must be > 0"); return -1; }
     if (s->model != ORC_DELTA && !(ts > 0)) { set_err("tau_syn must be > 0"); return -1; }
+    if (s->model == ORC_COND && s->weight_unit != ORC_UNIT_NATIVE) {
+        set_err("conductance synapses take native weights (nS)"); return -1;
+    }
     memset(k, 0, sizeof *k);
     /* dU/dt = -U/tm + I/C: over dt, U -> e^{-dt/tm} U, and a constant
        current I_e adds (tm/C)(1 - e^{-dt/tm}) I_e. */
@@ -142,7 +145,9 @@ static int constants(const orc_spec* s, consts_t* k) {
     k->P20 = -(tm / C) * expm1(-dt / tm);
     k->jump = 1.0;
     k->conv = 1.0;
-    if (s->model != ORC_DELTA) {
+    if (s->model == ORC_COND) {
+        k->P11 = exp(-dt / ts);   /* conductance decay per step */
+    } else if (s->model != ORC_DELTA) {
         /* synaptic kernel decays with e^{-dt/ts}; a current I present at the
            start of the step adds int_0^dt e^{-(dt-s)/tm} e^{-s/ts} ds / C
            = e^{-dt/tm}(1 - e^{-a dt})/(C a) to U (a = 1/ts - 1/tm). */
@@ -192,6 +197,8 @@ int orc_constants(const orc_spec* s, double out[12]) {
 struct orc_net {
     int model;
     consts_t k;
+    double gL, dt_C, Eex, Ein, I_e;          /* conductance model (Eex, Ein relative to E_L) */
+    double* ring_in;                         /* conductance model: inhibitory arrivals, like ring */
     double E_L, theta, Ur, P20Ie, w_ext;     /* theta, Ur relative to E_L */
     int64_t N, E;
     int32_t n_inst;
@@ -243,7 +250,7 @@ void orc_free(orc_net* n) {
     if (!n) return;
     free(n->inst_off); free(n->inst_of); free(n->inptr); free(n->src); free(n->w);
     free(n->d); free(n->tgt); free(n->outptr); free(n->outidx); free(n->sel); free(n->col_of);
-    free(n->U); free(n->y1); free(n->y2); free(n->ring); free(n->r);
+    free(n->U); free(n->y1); free(n->y2); free(n->ring); free(n->ring_in); free(n->r);
     free(n->U0); free(n->y10); free(n->y20); free(n->r0);
     free(n->log_step); free(n->log_id);
     if (n->hp) for (int64_t i = 0; i < n->N; ++i) { free(n->hp[i]); free(n->hy[i]); }
@@ -328,7 +335,7 @@ static int is_selected(const orc_spec* s, int64_t g, int64_t* cursor) {
 orc_net* orc_build(const orc_spec* s, uint64_t seed) {
     consts_t k;
     if (constants(s, &k)) return NULL;
-    if (s->model < 0 || s->model > 2) { set_err("bad model"); return NULL; }
+    if (s->model < 0 || s->model > 3) { set_err("bad model"); return NULL; }
     if (s->n_instances < 1 || s->n_pops < 1) { set_err("need at least one instance and population"); return NULL; }
     if (!(s->V_reset < s->V_th)) { set_err("V_reset must be below V_th"); return NULL; }
     orc_net* n = (orc_net*)calloc(1, sizeof(orc_net));
@@ -515,6 +522,15 @@ orc_net* orc_build(const orc_spec* s, uint64_t seed) {
     if (!n->U || !n->y1 || !n->y2 || !n->r || !n->U0 || !n->y10 || !n->y20 || !n->r0 || !n->ring) {
         set_err("out of memory"); goto fail;
     }
+    if (s->model == ORC_COND) {
+        n->ring_in = (double*)calloc((size_t)n->N * (size_t)n->D, sizeof(double));
+        if (!n->ring_in) { set_err("out of memory"); goto fail; }
+        n->gL = s->C_m / s->tau_m;
+        n->dt_C = s->dt / s->C_m;
+        n->Eex = s->E_ex - s->E_L;
+        n->Ein = s->E_in - s->E_L;
+        n->I_e = s->I_e;
+    }
     /* initial membrane potential uniform on [v0_lo, v0_hi): word 0 of the
        block (neuron, 0, 0, 3) */
     for (int64_t i = 0; i < n->N; ++i) {
@@ -607,6 +623,7 @@ int orc_reset(orc_net* n) {
     memcpy(n->y2, n->y20, (size_t)n->N * sizeof(double));
     memcpy(n->r, n->r0, (size_t)n->N * sizeof(int32_t));
     memset(n->ring, 0, (size_t)n->N * (size_t)n->D * sizeof(double));
+    if (n->ring_in) memset(n->ring_in, 0, (size_t)n->N * (size_t)n->D * sizeof(double));
     n->t = 0;
     n->events = 0.0;
     n->n_log = 0;
@@ -646,11 +663,35 @@ static int poisson_count(const orc_net* n, int64_t i, int64_t step) {
 
 /* One neuron update at step n with summed synaptic input x.
    Returns 1 if the neuron integrated (was not refractory). */
-static int update_neuron(orc_net* n, int64_t i, double x, int k) {
+static int update_neuron(orc_net* n, int64_t i, double x, double xin, int k) {
     const consts_t* c = &n->k;
     double ext = n->w_ext * (double)k;
     int integ = 0;
     double U = n->U[i];
+    if (n->model == ORC_COND) {
+        /* y1 = g_ex, y2 = g_in (nS); x, xin: this step's arrivals */
+        if (n->r[i] > 0) {
+            n->r[i] -= 1;
+            U = n->Ur;
+        } else {
+            integ = 1;
+            double G = n->gL + n->y1[i];
+            G = G + n->y2[i];
+            double num = n->y1[i] * n->Eex;
+            num = num + n->y2[i] * n->Ein;
+            num = num + n->I_e;
+            double Uinf = num / G;
+            double e = exp(-n->dt_C * G);
+            U = Uinf + (U - Uinf) * e;
+        }
+        double gex = c->P11 * n->y1[i];
+        double gin = c->P11 * n->y2[i];
+        if (ext >= 0.0) gex = gex + ext; else gin = gin - ext;
+        n->y1[i] = gex + x;
+        n->y2[i] = gin + xin;
+        n->U[i] = U;
+        return integ;
+    }
     if (n->r[i] > 0) {
         n->r[i] -= 1;
         U = n->Ur;
@@ -760,7 +801,8 @@ static void push_spike(orc_net* n, int64_t step, int64_t j) {
         if (n->stdp && n->plastic[e]) n->w[e] = stdp_weight(n, e, j, step);
         int64_t slot = (step + n->d[e]) % n->D;
         int64_t tg = n->tgt[e];
-        n->ring[tg * n->D + slot] += n->w[e];
+        if (n->ring_in && n->w[e] < 0.0) n->ring_in[tg * n->D + slot] += -n->w[e];
+        else n->ring[tg * n->D + slot] += n->w[e];
         n->events += 1.0;
     }
     if (n->stdp) {
@@ -782,8 +824,13 @@ int orc_run(orc_net* n, int64_t n_steps) {
         for (int64_t i = 0; i < n->N; ++i) {
             double x = n->ring[i * n->D + slot];
             n->ring[i * n->D + slot] = 0.0;
+            double xin = 0.0;
+            if (n->ring_in) {
+                xin = n->ring_in[i * n->D + slot];
+                n->ring_in[i * n->D + slot] = 0.0;
+            }
             int kc = poisson_count(n, i, step);
-            int integ = update_neuron(n, i, x, kc);
+            int integ = update_neuron(n, i, x, xin, kc);
             if (integ && n->U[i] >= n->theta) {
                 n->U[i] = n->Ur;
                 n->r[i] = n->k.n_ref;
@@ -838,8 +885,14 @@ static int frozen_core(orc_net* n, const int64_t* st, const int64_t* id, int64_t
             if (n->sel && n->col_of[i] < 0) continue;
             double x = n->ring[i * n->D + slot];
             n->ring[i * n->D + slot] = 0.0;
+            double xin = 0.0;
+            if (n->ring_in) {
+                xin = n->ring_in[i * n->D + slot];
+                n->ring_in[i * n->D + slot] = 0.0;
+            }
             int kc = poisson_count(n, i, step);
-            int integ = update_neuron(n, i, x, kc);
+            int integ = update_neuron(n, i, x, xin, kc);
+            x = x - xin;   /* the trace records the signed sum of the arrivals */
             int spk = 0;
             while (qs < q && id[qs] < i) qs++;
             if (qs < q && id[qs] == i) spk = 1;
@@ -890,6 +943,7 @@ int orc_run_frozen_pre(orc_net* n, const int64_t* st, const int64_t* id, int64_t
 int orc_backward(orc_net* n, const int64_t* st, const int64_t* id, int64_t nspk,
                  int64_t T, const double* vstar, double* grad, double* loss) {
     if (T < 1) { set_err("need at least one step"); return -1; }
+    if (n->model == ORC_COND) { set_err("no adjoint for conductance synapses"); return -1; }
     if (check_raster(n, st, id, nspk)) return -1;
     orc_reset(n);    /* restart from the build-time state */
     size_t cells = (size_t)T * (size_t)n->n_rec;

@@ -24,7 +24,7 @@
 extern "C" {
 #endif
 
-enum { ORC_DELTA = 0, ORC_EXP = 1, ORC_ALPHA = 2 };
+enum { ORC_DELTA = 0, ORC_EXP = 1, ORC_ALPHA = 2, ORC_COND = 3 };
 enum { ORC_FIXED_INDEGREE = 0, ORC_PAIRWISE = 1 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM_INT = 1, ORC_DELAY_NORMAL = 2 };
 enum { ORC_UNIT_NATIVE = 0, ORC_UNIT_PSP_MV = 1 };
@@ -66,7 +66,25 @@ typedef struct {
     double stdp_lambda, stdp_alpha, stdp_mu;   /* step size, depression ratio, potentiation exponent */
     double stdp_tau_plus, stdp_tau_minus;      /* pre- and postsynaptic trace time constants (ms) */
     double stdp_w0, stdp_wmax;                 /* reference and largest weight (the weights' unit) */
+    /* conductance-based synapses (model ORC_COND): reversal potentials (mV)
+       of the excitatory channel (weights >= 0, in nS) and the inhibitory
+       channel (weights < 0, |w| in nS) */
+    double E_ex, E_in;
 } orc_spec;
+
+/* Model ORC_COND (the conductance form of the synaptic current, Sec. I-A
+   Eq. 3, with an exponential conductance): a spike arriving through a
+   synapse of weight w adds |w| to the target's excitatory (w >= 0) or
+   inhibitory (w < 0) conductance, each decaying with tau_syn, and
+     C dV/dt = -g_L (V - E_L) + g_ex (E_ex - V) + g_in (E_in - V) + I_e,
+   g_L = C / tau_m.  A step holds the conductances at their values at its
+   start, for which the membrane's solution is exact:
+     G = g_L + g_ex + g_in,  V_inf = (g_L E_L + g_ex E_ex + g_in E_in + I_e) / G,
+     V <- V_inf + (V - V_inf) exp(-dt G / C);
+   then g <- g exp(-dt / tau_syn) + (the step's arrivals), so that V feels
+   an input from the next step on (as with current-based exponential
+   synapses).  External Poisson events of weight w_ext enter the channel of
+   w_ext's sign.  Weights are in nS (native units only). */
 
 /* Plasticity rule (read from the paper's verification network: E->E
    synapses with multiplicative depression and power-law potentiation).

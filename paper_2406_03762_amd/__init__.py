@@ -501,6 +501,8 @@ def tune_key(spec, device: dict) -> str:
     import hashlib
     plastic = getattr(spec, "stdp", None)
     extra = "" if plastic is None else f"|{plastic!r}"
+    if spec.model == "cond":
+        extra += f"|E_ex={spec.E_ex}|E_in={spec.E_in}"
     return hashlib.sha256(f"{spec!r}{extra}|{device['name']}|{device['n_cu']}".encode()).hexdigest()[:24]
 
 

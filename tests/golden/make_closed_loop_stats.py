@@ -47,7 +47,12 @@ WORKLOADS = {
 
 
 def spec_hash(spec) -> str:
-    return hashlib.sha256(repr(spec).encode()).hexdigest()[:16]
+    text = repr(spec)
+    if spec.model == "cond":   # fields repr() leaves out
+        text += f"|E_ex={spec.E_ex}|E_in={spec.E_in}"
+    if spec.stdp is not None:
+        text += f"|{spec.stdp!r}"
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def path_of(name: str) -> str:
