@@ -8,17 +8,21 @@
 // weights and dL/dw_e = sum_{m : src(e) spiked at m} g_tgt(e)(m + d_e), with
 // g_i(n) = dL/dx_i(n) from a backward recursion through the exact
 // propagators.  The forward stores the raster and, every C steps, the neuron
-// state and the input rings.  The backward walks the segments last to first:
-//  1. restore the segment's checkpoint and re-run it on the frozen raster with
-//     the step kernel (integer input sums make this a bit-exact replay), which
-//     yields V(n) and the mask m(n) = "integrated and did not spike";
-//  2. one thread per neuron runs the reverse recursion and writes g(n);
-//  3. one workgroup per tile walks, for every source that spiked in the
-//     window, the segment of its synapses into the tile -- the same spiking
-//     sub-graph (Eq. 11) that delivery reads -- and adds the g values at the
-//     arrival steps; each synapse has a single writer (the tile's workgroup,
-//     one wave per source), so no atomics are needed.
-// A final scatter writes the gradient in canonical synapse order.
+// state and the input rings.  The backward
+//  1. puts the raster on the device once, indexed per (step, tile) for the
+//     replays and regrouped by source (each source's spike steps, ascending)
+//     for the gradient;
+//  2. walks the segments last to first: restores the segment's checkpoint
+//     and re-runs it on the frozen raster with the step kernel (integer input
+//     sums make this a bit-exact replay), which yields V(n) and the mask
+//     m(n) = "integrated and did not spike"; then one thread per neuron runs
+//     the reverse recursion and writes g for the segment's steps into the
+//     neuron's row of g over the whole window;
+//  3. computes every weight's gradient in canonical order (the in-synapses
+//     of each target, Eq. 5's indegree sub-graph read target by target): one
+//     wave per target, a lane per synapse sums g of the target at the
+//     arrivals of its source's spikes; each gradient is written once, in
+//     order, with no atomics.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -53,7 +57,7 @@ struct ReverseArgs {
     const float* vtr;      // [len][N] V after each step of the segment
     const uint8_t* mtr;    // [len][N]
     const float* vstar;    // [T][N]
-    float* gtr;            // [len][N] dL/dx
+    float* gT;             // [N][T] dL/dx, one row per neuron over the whole window
     double* aU;            // carried adjoint state at step s1
     double* a1;
     double* a2;
@@ -73,44 +77,75 @@ struct ReverseArgs {
 // alpha: a2_n = m_{n+1} P32 aU_{n+1} + P22s a2_{n+1},
 //        a1_n = m_{n+1} P31 aU_{n+1} + P21s a2_{n+1} + P11 a1_{n+1}, g_n = jump a1_n;
 // delta: g_n = m_n aU_n.
+// A workgroup takes 256 consecutive neurons; the steps are walked backwards
+// in chunks of up to 16 (aligned to multiples of 16), whose g values go
+// through LDS so that each neuron's row of g is written as whole lines.
+constexpr int kRevChunk = 16;
+
 __global__ void __launch_bounds__(256) reverse_kernel(ReverseArgs a) {
+    __shared__ float s_g[kRevChunk][257];
     double lsum = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int lo = 0, hi = a.n_inst;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.inst_n0[mid] <= i) lo = mid; else hi = mid;
-        }
-        const double scale = 1.0 / ((double)a.inst_N[lo] * (double)a.T);
-        double aU = a.aU[i], a1 = a.a1[i], a2 = a.a2[i];
-        int mn = a.m_next[i];
-        for (int64_t k = a.len - 1; k >= 0; --k) {
-            const double diff = (double)a.vtr[k * a.N + i] - (double)a.vstar[(a.s0 + k) * a.N + i];
-            lsum += scale * diff * diff;
-            const double l = 2.0 * scale * diff;
-            const double naU = l + (mn ? a.P22 * aU : 0.0);
-            double na1 = 0.0, na2 = 0.0;
-            if (a.model == CORTEX_MODEL_EXP) {
-                na1 = (mn ? a.P21 * aU : 0.0) + a.P11 * a1;
-            } else if (a.model == CORTEX_MODEL_ALPHA) {
-                na2 = (mn ? a.P32 * aU : 0.0) + a.P22s * a2;
-                na1 = (mn ? a.P31 * aU : 0.0) + a.P21s * a2 + a.P11 * a1;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.N; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool ok = i < a.N;
+        double scale = 0.0, aU = 0.0, a1 = 0.0, a2 = 0.0;
+        int mn = 0;
+        if (ok) {
+            int lo = 0, hi = a.n_inst;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (a.inst_n0[mid] <= i) lo = mid; else hi = mid;
             }
-            aU = naU;
-            a1 = na1;
-            a2 = na2;
-            mn = a.mtr[k * a.N + i];
-            double g;
-            if (a.model == CORTEX_MODEL_DELTA) g = mn ? aU : 0.0;
-            else if (a.model == CORTEX_MODEL_EXP) g = a1;
-            else g = a.jump * a1;
-            a.gtr[k * a.N + i] = (float)g;
+            scale = 1.0 / ((double)a.inst_N[lo] * (double)a.T);
+            aU = a.aU[i];
+            a1 = a.a1[i];
+            a2 = a.a2[i];
+            mn = a.m_next[i];
         }
-        a.aU[i] = aU;
-        a.a1[i] = a1;
-        a.a2[i] = a2;
-        a.m_next[i] = (uint8_t)mn;
+        for (int64_t n_hi = a.s0 + a.len; n_hi > a.s0;) {
+            const int64_t n_lo = max(a.s0, ((n_hi - 1) / kRevChunk) * kRevChunk);
+            for (int64_t n = n_hi - 1; n >= n_lo; --n) {
+                float gv = 0.f;
+                if (ok) {
+                    const int64_t k = n - a.s0;
+                    const double diff = (double)a.vtr[k * a.N + i] - (double)a.vstar[n * a.N + i];
+                    lsum += scale * diff * diff;
+                    const double l = 2.0 * scale * diff;
+                    const double naU = l + (mn ? a.P22 * aU : 0.0);
+                    double na1 = 0.0, na2 = 0.0;
+                    if (a.model == CORTEX_MODEL_EXP) {
+                        na1 = (mn ? a.P21 * aU : 0.0) + a.P11 * a1;
+                    } else if (a.model == CORTEX_MODEL_ALPHA) {
+                        na2 = (mn ? a.P32 * aU : 0.0) + a.P22s * a2;
+                        na1 = (mn ? a.P31 * aU : 0.0) + a.P21s * a2 + a.P11 * a1;
+                    }
+                    aU = naU;
+                    a1 = na1;
+                    a2 = na2;
+                    mn = a.mtr[k * a.N + i];
+                    double g;
+                    if (a.model == CORTEX_MODEL_DELTA) g = mn ? aU : 0.0;
+                    else if (a.model == CORTEX_MODEL_EXP) g = a1;
+                    else g = a.jump * a1;
+                    gv = (float)g;
+                }
+                s_g[n - n_lo][threadIdx.x] = gv;
+            }
+            __syncthreads();
+            const int w = (int)(n_hi - n_lo);
+            for (int idx = threadIdx.x; idx < 256 * kRevChunk; idx += 256) {
+                const int r = idx / kRevChunk, c = idx % kRevChunk;
+                if (c < w && base + r < a.N) a.gT[(base + r) * a.T + n_lo + c] = s_g[c][r];
+            }
+            __syncthreads();
+            n_hi = n_lo;
+        }
+        if (ok) {
+            a.aU[i] = aU;
+            a.a1[i] = a1;
+            a.a2[i] = a2;
+            a.m_next[i] = (uint8_t)mn;
+        }
     }
     // block reduction of the loss into this block's slot; the slots are
     // summed in a fixed order afterwards, so the loss is reproducible
@@ -140,127 +175,169 @@ __global__ void __launch_bounds__(256) loss_sum_kernel(const double* part, int n
     if (threadIdx.x == 0) *loss += red[0];
 }
 
-struct WgradArgs {
-    const int32_t* tile_inst;
-    const int32_t* tile_size;
-    const int32_t* inst_tile0;
-    const int32_t* inst_ntiles;
-    const int32_t* inst_T;
-    const int64_t* inst_n0;
-    const uint64_t* inst_offbase;
-    const uint64_t* row_start;
-    const uint32_t* off_rel;
-    const void* meta;
-    int meta16;                 // 16-bit records (alone, or under a bf16 weight when packed)
-    int packed;
-    int T, dmin, dmax;          // record = (delay - dmin) T + target in tile
-    int sw, n_sub;              // steps per sub-window, sub-windows of the segment
-    int n_inst;
-    const uint32_t* r_ids;      // the raster's ids, sorted by (step, id)
-    const uint64_t* r_ptr;      // [step * (n_inst + 1) + b]: instance b's spikes of a step
-    int64_t r_steps;            // steps of the raster
-    const float* gtr;           // [len][N]
-    float* grad;                // [E] storage order
-    int64_t N, s0, s1;
-};
-
-// Lane i's value of v, for a wave-uniform i.
-__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int i) {
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
-    return ((uint64_t)hi << 32) | lo;
+// Spikes of the raster regrouped by source: cnt[j] = spikes of j; after a
+// scan into sptr, steps of j's spikes in sstep[sptr[j] .. sptr[j + 1]),
+// ascending.
+__global__ void src_count_kernel(const uint32_t* r_ids, int64_t n_spk, uint32_t* cnt) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_spk; q += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[r_ids[q]], 1u);
 }
 
-// One workgroup (16 waves) per tile.  The segment's steps are taken in
-// sub-windows of sw steps; for each, the tile's dL/dx values of those steps
-// are staged in LDS ([sw][tile size]), then the spikes of the tile's
-// instance that can arrive in the sub-window (steps q with [q + d_min,
-// q + d_max] meeting it) are read from the raster, 64 at a time per wave.
-// Source j belongs to wave j mod 16: that wave walks j's segment into the
-// tile (lanes over its synapses) for each of j's spikes in turn and adds,
-// per synapse whose arrival q + d falls in the sub-window, the staged value
-// there.  A synapse's gradient therefore has one writer, with no atomics.
-__global__ void __launch_bounds__(1024) wgrad_kernel(WgradArgs a) {
-    extern __shared__ float s_g[];
-    const int tile = blockIdx.x;
-    const int b = a.tile_inst[tile];
-    const int tl = tile - a.inst_tile0[b];
-    const int ntb = a.inst_ntiles[b];
-    const int tsz = a.tile_size[tile];
-    const int64_t n0b = a.inst_n0[b];
-    const int64_t g0 = n0b + (int64_t)tl * a.inst_T[b];
-    const uint64_t offb = a.inst_offbase[b];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    const uint32_t T = (uint32_t)a.T;
-    for (int w = 0; w < a.n_sub; ++w) {
-        const int64_t t = a.s0 + (int64_t)w * a.sw;
-        const int nw = (int)min((int64_t)a.sw, a.s1 - t);
-        __syncthreads();   // the previous sub-window's readers are done
-        for (int i = threadIdx.x; i < nw * tsz; i += blockDim.x) {
-            const int k = i / tsz, li = i - k * tsz;
-            s_g[i] = a.gtr[(t - a.s0 + k) * a.N + g0 + li];
+__global__ void src_fill_kernel(const uint32_t* r_steps, const uint32_t* r_ids, int64_t n_spk, const uint64_t* sptr,
+                                uint32_t* cur, int32_t* sstep) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_spk; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = r_ids[q];
+        sstep[sptr[j] + atomicAdd(&cur[j], 1u)] = (int32_t)r_steps[q];
+    }
+}
+
+// The fill's order is that of its atomics: sort each source's few steps.
+__global__ void src_sort_kernel(const uint64_t* sptr, int32_t* sstep, int64_t N) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = sptr[j], e = sptr[j + 1];
+        for (uint64_t k = b + 1; k < e; ++k) {
+            const int32_t v = sstep[k];
+            uint64_t m = k;
+            while (m > b && sstep[m - 1] > v) {
+                sstep[m] = sstep[m - 1];
+                --m;
+            }
+            sstep[m] = v;
         }
-        __syncthreads();
-        const int64_t q_lo = max((int64_t)0, t - a.dmax);
-        const int64_t q_hi = min(a.r_steps, t + nw - a.dmin);
-        for (int64_t q = q_lo; q < q_hi; ++q) {
-            const uint64_t p0 = a.r_ptr[q * (a.n_inst + 1) + b], p1 = a.r_ptr[q * (a.n_inst + 1) + b + 1];
-            for (uint64_t pc = p0; pc < p1; pc += 64) {
-                // this wave's spikes among the next 64: their segment bounds
-                // are loaded by their own lanes, together
-                const uint64_t p = pc + (uint64_t)lane;
-                uint32_t j = 0;
-                bool own = false;
-                uint64_t e0l = 0, e1l = 0;
-                if (p < p1) {
-                    j = a.r_ids[p];
-                    own = (int)(j % (uint32_t)n_waves) == wave;
-                    if (own) {
-                        const uint64_t ob = offb + (uint64_t)(j - n0b) * (uint64_t)(ntb + 1) + (uint64_t)tl;
-                        const uint64_t rs = a.row_start[j];
-                        e0l = rs + a.off_rel[ob];
-                        e1l = rs + a.off_rel[ob + 1];
+    }
+}
+
+// Each source's spikes in one 16-byte word when the window is shorter than
+// 65536 steps: eight 16-bit fields, the spike count (saturated) and its
+// first seven steps; further spikes stay in the sorted list.
+__global__ void src_pack_kernel(const uint64_t* sptr, const int32_t* sstep, int64_t N, uint4* s8) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = sptr[j], n = sptr[j + 1] - b;
+        uint32_t f[8] = {(uint32_t)min<uint64_t>(n, 0xFFFF), 0, 0, 0, 0, 0, 0, 0};
+        for (uint64_t k = 0; k < min<uint64_t>(n, 7); ++k) f[1 + k] = (uint32_t)sstep[b + k];
+        s8[j] = make_uint4(f[0] | (f[1] << 16), f[2] | (f[3] << 16), f[4] | (f[5] << 16), f[6] | (f[7] << 16));
+    }
+}
+
+// dL/dw_c = sum over the spikes q of src_c with q + d_c < T of
+// g_tgt(q + d_c), for every synapse c in canonical order (target, then
+// projection and slot): one wave per target, a lane per synapse, four
+// synapses per lane at a time (independent loads in flight).  The target's
+// row of g (T values) is read from cache by every lane; each gradient is
+// written once, in order, straight into the caller's buffer.
+__global__ void __launch_bounds__(256) pull_grad_kernel(const uint64_t* cin, const uint32_t* csrc,
+                                                        const uint16_t* cdel, const uint4* s8,
+                                                        const uint64_t* sptr, const int32_t* sstep,
+                                                        const float* gT, int64_t N, int64_t T, float* grad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    constexpr int U = 4;
+    for (int64_t i = wave; i < N; i += n_waves) {
+        const float* g = gT + i * T;
+        const uint64_t c1 = cin[i + 1];
+        for (uint64_t cb = cin[i] + lane; cb < c1; cb += 64 * U) {
+            uint32_t j[U];
+            int64_t d[U];
+            uint4 sp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t c = cb + 64u * u;
+                j[u] = c < c1 ? csrc[c] : 0u;
+                d[u] = c < c1 ? (int64_t)cdel[c] : T;   // past the window: contributes nothing
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) sp[u] = s8[j[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t c = cb + 64u * u;
+                if (c >= c1) continue;
+                const uint32_t f[8] = {sp[u].x & 0xFFFFu, sp[u].x >> 16, sp[u].y & 0xFFFFu, sp[u].y >> 16,
+                                       sp[u].z & 0xFFFFu, sp[u].z >> 16, sp[u].w & 0xFFFFu, sp[u].w >> 16};
+                const uint32_t cnt = f[0];
+                float acc = 0.f;
+                bool more = true;
+#pragma unroll
+                for (int k = 0; k < 7; ++k) {
+                    if ((uint32_t)k < cnt && more) {
+                        const int64_t arr = (int64_t)f[1 + k] + d[u];
+                        if (arr < T) acc += g[arr];
+                        else more = false;   // ascending steps
                     }
                 }
-                uint64_t mask = __ballot(own);
-                while (mask) {
-                    const int i = __ffsll((unsigned long long)mask) - 1;
-                    mask &= mask - 1;
-                    const uint64_t e0 = lane_u64(e0l, i), e1 = lane_u64(e1l, i);
-                    // four synapses per lane at a time: records first, then
-                    // the gradients of those arriving in the sub-window
-                    for (uint64_t eb = e0 + lane; eb < e1; eb += 256) {
-                        int32_t at[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const uint64_t e = eb + 64u * u;
-                            at[u] = -1;
-                            if (e < e1) {
-                                const uint32_t m = a.packed ? (static_cast<const uint32_t*>(a.meta)[e] & 0xFFFFu)
-                                                   : a.meta16 ? static_cast<const uint16_t*>(a.meta)[e]
-                                                              : static_cast<const uint32_t*>(a.meta)[e];
-                                const int64_t tau = q + a.dmin + (int64_t)(m / T);
-                                if (tau >= t && tau < t + nw) at[u] = (int32_t)((tau - t) * tsz + (int64_t)(m % T));
-                            }
-                        }
-                        float g[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) g[u] = at[u] >= 0 ? a.grad[eb + 64u * u] : 0.f;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (at[u] >= 0) a.grad[eb + 64u * u] = g[u] + s_g[at[u]];
+                if (cnt > 7 && more) {   // spikes past the seventh (or a saturated count)
+                    const uint64_t p1 = sptr[j[u] + 1];
+                    for (uint64_t p = sptr[j[u]] + 7; p < p1; ++p) {
+                        const int64_t arr = (int64_t)sstep[p] + d[u];
+                        if (arr >= T) break;
+                        acc += g[arr];
                     }
                 }
+                grad[c] = acc;
             }
         }
     }
 }
 
-// dst in canonical order from src in storage order: dst[c] = src[inv[c]].
-__global__ void gather_kernel(const float* src, const uint32_t* inv, float* dst, int64_t E) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < E;
-         c += (int64_t)gridDim.x * blockDim.x)
-        dst[c] = src[inv[c]];
+// The raster of steps [0, T) from the spike log, sorted by (step, id), on
+// the device.  The log holds, per tile, its spikes step after step, and
+// cnt[s][t] per (step, tile) (0xFFFFFFFF: the tile's log overflowed).
+// 1. per tile, the offset of each step's spikes inside its log (a scan
+//    along the steps, one wave per tile); flag overflow marks;
+__global__ void log_offsets_kernel(const uint32_t* cnt, int64_t T, int n_tiles, uint64_t* tile_off, int32_t* bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= n_tiles) return;
+    const int t = (int)wave;
+    uint64_t carry = 0;
+    for (int64_t s0 = 0; s0 < T; s0 += 64) {
+        const int64_t s = s0 + lane;
+        uint32_t c = s < T ? cnt[s * n_tiles + t] : 0u;
+        if (c == 0xFFFFFFFFu) {
+            atomicOr(bad, 1);
+            c = 0;
+        }
+        const uint32_t inc = wave_incl_scan(c);
+        if (s < T) tile_off[s * n_tiles + t] = carry + inc - c;
+        carry += (uint32_t)__shfl((int)inc, 63, 64);
+    }
+}
+
+// 2. (after a scan of cnt in step-major order into gpos) one thread per
+//    (step, tile) copies its spikes to their place and sorts them by id;
+//    flag ids out of range.
+__global__ void log_copy_kernel(const uint32_t* cnt, const uint64_t* tile_off, const uint64_t* gpos,
+                                const uint64_t* log_base, const uint32_t* log_ids, int64_t T, int n_tiles,
+                                int64_t N, uint32_t* r_steps, uint32_t* r_ids, int32_t* bad) {
+    const int64_t pairs = T * n_tiles;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cnt[p];
+        if (c == 0xFFFFFFFFu || c == 0) continue;
+        const int t = (int)(p % n_tiles);
+        const uint32_t s = (uint32_t)(p / n_tiles);
+        const uint32_t* src = log_ids + log_base[t] + tile_off[p];
+        const uint64_t o = gpos[p];
+        for (uint32_t k = 0; k < c; ++k) {
+            uint32_t v = src[k];
+            if (v >= (uint64_t)N) {
+                atomicOr(bad, 2);
+                v = 0;
+            }
+            uint32_t m = k;   // insertion into the sorted prefix
+            while (m > 0 && r_ids[o + m - 1] > v) {
+                r_ids[o + m] = r_ids[o + m - 1];
+                --m;
+            }
+            r_ids[o + m] = v;
+            r_steps[o + k] = s;
+        }
+    }
+}
+
+// The counts of overflowed pairs enter the step-major scan as 0.
+__global__ void log_clean_counts_kernel(const uint32_t* cnt, int64_t pairs, uint32_t* clean) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += (int64_t)gridDim.x * blockDim.x)
+        clean[p] = cnt[p] == 0xFFFFFFFFu ? 0u : cnt[p];
 }
 
 int grid_of(int64_t work, int bs) {
@@ -286,8 +363,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
 
 namespace cortex {
 
-// Helpers defined in api.hip.
-std::vector<std::pair<uint32_t, uint32_t>> collect_spikes(cortex_net* n, int64_t s0, int64_t s1, bool* trunc);
+// Helper defined in api.hip.
 void restore_checkpoint(cortex_net* n, int k);
 
 void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* loss_out) {
@@ -297,11 +373,8 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     require(T >= 1 && T <= n->adj_steps, CORTEX_ESTATE, "forward window empty or longer than adjoint_steps");
     require(n->log_step0 == 0, CORTEX_ESTATE, "spike log was cleared since the build; the raster is incomplete");
     require(vstar != nullptr && grad_w != nullptr && loss_out != nullptr, CORTEX_EINVAL, "NULL argument");
-    bool trunc = false;
-    const auto raster = collect_spikes(n, 0, T, &trunc);
-    require(!trunc, CORTEX_ESTATE, "spike log overflowed; the raster is incomplete");
-    for (const auto& sp : raster)
-        require((int64_t)sp.first < T && (int64_t)sp.second < n->N, CORTEX_EDEVICE, "spike log holds an invalid entry");
+    require(n->log_steps >= T, CORTEX_ESTATE, "the spike log does not cover the forward window");
+    require(T <= 0xFFFF, CORTEX_EUNSUPPORTED, "the adjoint covers at most 65535 steps");
     const int64_t N = n->N;
     const size_t ring_n = (size_t)n->n_tiles * n->R * n->T;
     const size_t pub_n = (size_t)n->H * n->n_tiles * (n->T + 1) + 8;
@@ -327,7 +400,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     // segment buffers
     float* vtr = dev_alloc_t<float>(n, (size_t)C * N, true);
     uint8_t* mtr = dev_alloc_t<uint8_t>(n, (size_t)C * N, true);
-    float* gtr = dev_alloc_t<float>(n, (size_t)C * N, true);
+    float* gT = dev_alloc_t<float>(n, (size_t)N * T, true);   // dL/dx over the whole window, per neuron
     double* aU = dev_alloc_t<double>(n, N, true);
     double* a1 = dev_alloc_t<double>(n, N, true);
     double* a2 = dev_alloc_t<double>(n, N, true);
@@ -335,48 +408,71 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
     double* dloss = dev_alloc_t<double>(n, 1, true);
     const int rev_grid = grid_of(N, 256);
     double* dloss_part = dev_alloc_t<double>(n, rev_grid, true);
-    float* grad = dev_alloc_t<float>(n, n->E, true);
     int64_t* inst_N = dev_alloc_t<int64_t>(n, n->n_inst, true);
-    // weight-gradient sub-windows: sw steps of a tile's dL/dx in at most
-    // 160 KB of LDS
-    const int sw = (int)std::max<int64_t>(1, std::min<int64_t>(C, 40960 / std::max(1, n->T)));
-    const size_t wgrad_lds = (size_t)sw * n->T * sizeof(float);
-    CX_HIP(hipFuncSetAttribute((const void*)wgrad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)wgrad_lds));
     CX_HIP(hipMemcpyAsync(inst_N, n->inst_N.data(), n->n_inst * 8, hipMemcpyHostToDevice, n->stream));
     dev_zero(n, aU, N * 8);
     dev_zero(n, a1, N * 8);
     dev_zero(n, a2, N * 8);
     dev_zero(n, mnext, N);
     dev_zero(n, dloss, 8);
-    dev_zero(n, grad, (size_t)n->E * 4);
     const int64_t saved_log_steps = n->log_steps;
     n->log_steps = 0;   // the replays must not append to the spike log
-    // The raster on the device, with its offsets per (step, tile) (the
-    // replays' frozen lists and the republished steps) and per (step,
-    // instance) (the weight gradient's spikes), built once for all segments.
-    const int64_t n_spk = (int64_t)raster.size();
+    // The raster on the device, from the spike log, with its offsets per
+    // (step, tile) (the replays' frozen lists and the republished steps) and
+    // regrouped by source (the weight gradient), built once for all
+    // segments.
+    const int64_t pairs = T * n->n_tiles;
+    uint64_t* tile_off = dev_alloc_t<uint64_t>(n, (size_t)pairs, true);
+    uint32_t* clean = dev_alloc_t<uint32_t>(n, (size_t)pairs, true);
+    uint64_t* gpos = dev_alloc_t<uint64_t>(n, (size_t)pairs + 1, true);
+    int32_t* bad = dev_alloc_t<int32_t>(n, 1, true);
+    dev_zero(n, bad, sizeof(int32_t));
+    hipLaunchKernelGGL(log_offsets_kernel, dim3(grid_of((int64_t)n->n_tiles * 64, 256)), dim3(256), 0, n->stream,
+                       n->d_log_cnt, T, n->n_tiles, tile_off, bad);
+    CX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(log_clean_counts_kernel, dim3(grid_of(pairs, 256)), dim3(256), 0, n->stream, n->d_log_cnt,
+                       pairs, clean);
+    CX_HIP(hipGetLastError());
+    scan_counts(n, clean, gpos, pairs);
+    int64_t n_spk = 0;
+    {
+        uint64_t tot = 0;
+        int32_t hb = 0;
+        CX_HIP(hipMemcpyAsync(&tot, gpos + pairs, sizeof tot, hipMemcpyDeviceToHost, n->stream));
+        CX_HIP(hipMemcpyAsync(&hb, bad, sizeof hb, hipMemcpyDeviceToHost, n->stream));
+        CX_HIP(hipStreamSynchronize(n->stream));
+        require(hb == 0, CORTEX_ESTATE, "spike log overflowed; the raster is incomplete");
+        n_spk = (int64_t)tot;
+    }
     uint32_t* r_steps = dev_alloc_t<uint32_t>(n, std::max<int64_t>(1, n_spk), true);
     uint32_t* r_ids = dev_alloc_t<uint32_t>(n, std::max<int64_t>(1, n_spk), true);
     uint64_t* r_tile_ptr = dev_alloc_t<uint64_t>(n, (size_t)T * n->n_tiles + 1, true);
-    uint64_t* r_inst_ptr = dev_alloc_t<uint64_t>(n, (size_t)T * (n->n_inst + 1) + 1, true);
-    int64_t* inst_keys = dev_alloc_t<int64_t>(n, n->n_inst + 1, true);
+    uint32_t* s_cnt = dev_alloc_t<uint32_t>(n, N, true);
+    uint32_t* s_cur = dev_alloc_t<uint32_t>(n, N, true);
+    uint64_t* sptr = dev_alloc_t<uint64_t>(n, N + 1, true);
+    int32_t* sstep = dev_alloc_t<int32_t>(n, std::max<int64_t>(1, n_spk), true);
+    uint4* s8 = dev_alloc_t<uint4>(n, N, true);
     {
-        std::vector<uint32_t> hs((size_t)n_spk), hi((size_t)n_spk);
-        for (int64_t q = 0; q < n_spk; ++q) {
-            hs[q] = raster[q].first;
-            hi[q] = raster[q].second;
-        }
-        std::vector<int64_t> keys(n->inst_n0.begin(), n->inst_n0.end());
-        keys.push_back(N);
-        if (n_spk > 0) {
-            CX_HIP(hipMemcpyAsync(r_steps, hs.data(), n_spk * 4, hipMemcpyHostToDevice, n->stream));
-            CX_HIP(hipMemcpyAsync(r_ids, hi.data(), n_spk * 4, hipMemcpyHostToDevice, n->stream));
-        }
-        CX_HIP(hipMemcpyAsync(inst_keys, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, n->stream));
+        hipLaunchKernelGGL(log_copy_kernel, dim3(grid_of(pairs, 256)), dim3(256), 0, n->stream, n->d_log_cnt, tile_off,
+                           gpos, n->d_log_base, n->d_log_ids, T, n->n_tiles, N, r_steps, r_ids, bad);
+        CX_HIP(hipGetLastError());
         raster_index(n, r_steps, r_ids, n_spk, 0, T, n->d_tile_start, n->n_tiles, r_tile_ptr);
-        raster_index(n, r_steps, r_ids, n_spk, 0, T, inst_keys, n->n_inst + 1, r_inst_ptr);
-        CX_HIP(hipStreamSynchronize(n->stream));   // before the staging vectors go away
+        dev_zero(n, s_cnt, N * 4);
+        dev_zero(n, s_cur, N * 4);
+        hipLaunchKernelGGL(src_count_kernel, dim3(grid_of(n_spk, 256)), dim3(256), 0, n->stream, r_ids, n_spk, s_cnt);
+        CX_HIP(hipGetLastError());
+        scan_counts(n, s_cnt, sptr, N);
+        hipLaunchKernelGGL(src_fill_kernel, dim3(grid_of(n_spk, 256)), dim3(256), 0, n->stream, r_steps, r_ids, n_spk,
+                           sptr, s_cur, sstep);
+        CX_HIP(hipGetLastError());
+        hipLaunchKernelGGL(src_sort_kernel, dim3(grid_of(N, 256)), dim3(256), 0, n->stream, sptr, sstep, N);
+        CX_HIP(hipGetLastError());
+        hipLaunchKernelGGL(src_pack_kernel, dim3(grid_of(N, 256)), dim3(256), 0, n->stream, sptr, sstep, N, s8);
+        CX_HIP(hipGetLastError());
+        int32_t hb = 0;
+        CX_HIP(hipMemcpyAsync(&hb, bad, sizeof hb, hipMemcpyDeviceToHost, n->stream));
+        CX_HIP(hipStreamSynchronize(n->stream));
+        require(hb == 0, CORTEX_EDEVICE, "spike log holds an invalid entry");
     }
     const int K = (int)((T + C - 1) / C);
     try {
@@ -401,7 +497,7 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                              mtr);
             // reverse recursion over the segment
             ReverseArgs ra{};
-            ra.vtr = vtr; ra.mtr = mtr; ra.vstar = vstar; ra.gtr = gtr;
+            ra.vtr = vtr; ra.mtr = mtr; ra.vstar = vstar; ra.gT = gT;
             ra.aU = aU; ra.a1 = a1; ra.a2 = a2; ra.m_next = mnext; ra.loss_part = dloss_part;
             ra.inst_n0 = n->d_inst_n0; ra.inst_N = inst_N; ra.n_inst = n->n_inst;
             ra.N = N; ra.s0 = s0; ra.len = len; ra.T = T; ra.model = n->spec.model;
@@ -411,21 +507,6 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
             CX_HIP(hipGetLastError());
             hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, n->stream, dloss_part, rev_grid, dloss);
             CX_HIP(hipGetLastError());
-            // weight gradient of the synapses whose arrivals land in the segment
-            if (n_spk > 0) {
-                WgradArgs wa{};
-                wa.tile_inst = n->d_tile_inst; wa.tile_size = n->d_tile_size; wa.inst_tile0 = n->d_inst_tile0;
-                wa.inst_ntiles = n->d_inst_ntiles; wa.inst_T = n->d_inst_T; wa.inst_n0 = n->d_inst_n0;
-                wa.inst_offbase = n->d_inst_offbase;
-                wa.row_start = n->d_row_start; wa.off_rel = n->d_off_rel; wa.meta = n->d_meta;
-                wa.meta16 = n->meta_bytes == 2; wa.packed = n->w_bytes == 2; wa.T = n->T;
-                wa.dmin = n->dmin; wa.dmax = n->dmax;
-                wa.sw = sw; wa.n_sub = (int)((len + sw - 1) / sw); wa.n_inst = n->n_inst;
-                wa.r_ids = r_ids; wa.r_ptr = r_inst_ptr; wa.r_steps = T;
-                wa.gtr = gtr; wa.grad = grad; wa.N = N; wa.s0 = s0; wa.s1 = s1;
-                hipLaunchKernelGGL(wgrad_kernel, dim3(n->n_tiles), dim3(1024), wgrad_lds, n->stream, wa);
-                CX_HIP(hipGetLastError());
-            }
         }
         CX_HIP(hipStreamSynchronize(n->stream));
         {
@@ -436,8 +517,9 @@ void adjoint_backward(cortex_net* n, const float* vstar, float* grad_w, double* 
                 throw Error{CORTEX_ETIMEOUT, "a device-side wait in the adjoint replay exceeded its spin limit"};
             }
         }
-        hipLaunchKernelGGL(gather_kernel, dim3(grid_of(n->E, 256)), dim3(256), 0, n->stream, grad,
-                           n->d_canon_inv, grad_w, n->E);
+        // the weight gradient, in canonical order, into the caller's buffer
+        hipLaunchKernelGGL(pull_grad_kernel, dim3(grid_of(N * 64, 256)), dim3(256), 0, n->stream, n->d_cin,
+                           n->d_csrc, n->d_cdel, s8, sptr, sstep, gT, N, T, grad_w);
         CX_HIP(hipGetLastError());
         CX_HIP(hipMemcpyAsync(loss_out, dloss, 8, hipMemcpyDeviceToHost, n->stream));
     } catch (...) {

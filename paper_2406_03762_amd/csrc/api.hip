@@ -212,6 +212,8 @@ static void validate(const cortex_spec* s) {
     require(s->wg_per_cu == 0 || s->wg_per_cu == 1 || s->wg_per_cu == 2 || s->wg_per_cu == 4 || s->wg_per_cu == 8,
             CORTEX_EINVAL, "wg_per_cu must be 0, 1, 2, 4 or 8");
     require(s->n_projs >= 0 && (s->n_projs == 0 || s->projs), CORTEX_EINVAL, "projection list is NULL");
+    require(s->ckpt_every == 0 || s->adjoint_steps <= 0xFFFF, CORTEX_EUNSUPPORTED,
+            "the adjoint covers at most 65535 steps");
     if (s->stdp_enable) {
         require(s->stdp_pop >= 0 && s->stdp_pop < s->n_pops, CORTEX_EINVAL, "stdp_pop out of range");
         require(s->stdp_lambda >= 0 && s->stdp_alpha >= 0 && s->stdp_tau_plus > 0 && s->stdp_tau_minus > 0 &&

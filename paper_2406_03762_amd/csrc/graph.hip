@@ -62,6 +62,8 @@ struct GenArgs {
     const uint32_t* item_rel;   // [n_items] offset of the item inside its target
     const uint64_t* cin;        // [N + 1] canonical start of each target
     uint32_t* canon_out;        // [E] canonical index of each stored synapse
+    uint32_t* csrc_out;         // [E] source of each canonical synapse
+    uint16_t* cdel_out;         // [E] delay (steps) of each canonical synapse
     // FP64 verify arrays (canonical order)
     uint32_t* in_src;
     double* in_w;
@@ -172,7 +174,12 @@ __device__ __forceinline__ void emit(const GenArgs& a, const GenBlock& B, int64_
                 else static_cast<uint32_t*>(a.meta)[pos] = m;
                 static_cast<float*>(a.w)[pos] = (float)w;
             }
-            if (a.canon_out) a.canon_out[pos] = (uint32_t)(a.cin[tgt_global] + a.item_rel[item] + slot);
+            if (a.canon_out) {
+                const uint64_t c = a.cin[tgt_global] + a.item_rel[item] + slot;
+                a.canon_out[pos] = (uint32_t)c;
+                a.csrc_out[c] = (uint32_t)src_global;
+                a.cdel_out[c] = (uint16_t)dr.d;
+            }
         }
     }
     if (MODE == kFillCanon) {
@@ -636,12 +643,6 @@ double max_abs_input(cortex_net* n, double* wmax) {
 }
 
 namespace {
-// inv[canon[e]] = e (setup).
-__global__ void invert_kernel(const uint32_t* canon, uint32_t* inv, int64_t E) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
-        inv[canon[e]] = (uint32_t)e;
-}
-
 // Stored weight of every synapse from a canonical-order array (setup).
 __global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, void* w, void* meta, int wbf16,
                                    int64_t E) {
@@ -656,6 +657,11 @@ __global__ void set_weights_kernel(const float* w_canon, const uint32_t* canon, 
     }
 }
 }  // namespace
+
+void scan_counts(cortex_net* n, const uint32_t* in, uint64_t* out, int64_t count) {
+    hipLaunchKernelGGL(scan_u32_to_u64, dim3(1), dim3(1024), 0, n->stream, in, out, count);
+    CX_HIP(hipGetLastError());
+}
 
 void set_weights_fp32(cortex_net* n, const float* w_canonical) {
     if (n->E == 0) return;
@@ -735,11 +741,15 @@ void build_graph_fp32(cortex_net* n) {
     uint64_t* cin = nullptr;
     if (need_canon) {
         require(n->E < (int64_t)0xFFFFFFFFll, CORTEX_EUNSUPPORTED, "adjoint needs fewer than 2^32 synapses");
+        require(n->dmax <= 0xFFFF, CORTEX_EUNSUPPORTED, "adjoint needs delays below 65536 steps");
         item_rel = dev_alloc_t<uint32_t>(n, t.n_items, true);
-        cin = dev_alloc_t<uint64_t>(n, n->N + 1, true);
+        n->d_cin = dev_alloc_t<uint64_t>(n, n->N + 1);
+        cin = n->d_cin;
         const int64_t Ec = canonical_offsets(n, t, cnt_item, item_rel, cin);
         require(Ec == n->E, CORTEX_EDEVICE, "canonical edge count mismatch");
         n->d_canon = dev_alloc_t<uint32_t>(n, n->E);
+        n->d_csrc = dev_alloc_t<uint32_t>(n, n->E);
+        n->d_cdel = dev_alloc_t<uint16_t>(n, n->E);
     }
     dev_zero(n, cnt, cnt_len * sizeof(uint32_t));
     a.row_start = n->d_row_start;
@@ -754,16 +764,9 @@ void build_graph_fp32(cortex_net* n) {
     a.item_rel = item_rel;
     a.cin = cin;
     a.canon_out = n->d_canon;
+    a.csrc_out = n->d_csrc;
+    a.cdel_out = n->d_cdel;
     run_gen<kFillTiles>(n, a);
-    if (need_canon && n->E > 0) {
-        // the inverse permutation, so that canonical-order outputs are
-        // written in order (gathered) rather than scattered
-        n->d_canon_inv = dev_alloc_t<uint32_t>(n, n->E);
-        dev_zero(n, n->d_canon_inv, (size_t)n->E * sizeof(uint32_t));   // in range even if not a permutation
-        hipLaunchKernelGGL(invert_kernel, dim3(grid_for(n->E, 256)), dim3(256), 0, n->stream, n->d_canon,
-                           n->d_canon_inv, n->E);
-        CX_HIP(hipGetLastError());
-    }
     CX_HIP(hipStreamSynchronize(n->stream));
 }
 

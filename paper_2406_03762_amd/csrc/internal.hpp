@@ -138,7 +138,9 @@ struct cortex_net {
     void* d_meta = nullptr;            // u16/u32 [E]
     void* d_w = nullptr;               // f32/bf16 [E]
     uint32_t* d_canon = nullptr;       // [E] canonical index of each stored synapse (adjoint)
-    uint32_t* d_canon_inv = nullptr;   // [E] stored index of each canonical synapse (adjoint)
+    uint64_t* d_cin = nullptr;         // [N + 1] first canonical synapse of each target (adjoint)
+    uint32_t* d_csrc = nullptr;        // [E] source of each canonical synapse (adjoint)
+    uint16_t* d_cdel = nullptr;        // [E] delay in steps of each canonical synapse (adjoint)
     // FP32 state
     float *d_U = nullptr, *d_y1 = nullptr, *d_y2 = nullptr;
     int32_t* d_r = nullptr;
@@ -233,6 +235,9 @@ void init_state(cortex_net* n);
 // step.hip
 // Frozen runs pass the per-(step, tile) id lists (frz_ptr into frz_ids,
 // frz_n ids in all); the kernel clamps every list to [0, frz_n).
+// out[k] = in[0] + ... + in[k - 1] for k <= count (graph.hip; one workgroup,
+// on n->stream; setup-sized counts).
+void scan_counts(cortex_net* n, const uint32_t* in, uint64_t* out, int64_t count);
 // Offsets of a raster sorted by (step, id) (noalloc.hip): ptr[s * n_keys + k]
 // = first entry with (step, id) >= (step0 + s, keys[k]), and ptr[n_steps *
 // n_keys] = first entry past step0 + n_steps; on n->stream.
