@@ -259,10 +259,17 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
     out["speedup_streamed_vs_sequential"] = eps / (ev_s / dt_s)
     out["speedup_resident_vs_sequential"] = eps_r / (ev_s / dt_s)
     log(f"[bench] one instance per launch: {ev_s / dt_s:.3e} events/s")
-    # adjoint over all 64 instances: one checkpointed network per co-resident
-    # group (the adjoint runs on the resident plan), forward then the
-    # gradient of the voltage loss; the second backward call is timed (the
-    # first one also allocates its buffers)
+    out["adjoint"] = adjoint_all(cx, torch, seed, sim_steps)
+    return out
+
+
+def adjoint_all(cx, torch, seed, sim_steps):
+    """The adjoint over all 64 instances: one checkpointed network per
+    co-resident group (the adjoint runs on the resident plan), forward then
+    the gradient of the voltage loss; the second backward call is timed
+    (the first one also allocates its buffers)."""
+    import netspec
+    spec = netspec.batched_brunel()
     log("[bench] adjoint: forward with checkpoints, per group")
     groups = _pack_instances(cx, netspec, spec, seed)
     specs = [g for g, _ in groups]
@@ -305,8 +312,7 @@ def batched_and_adjoint(cx, torch, seed, sim_steps):
         del vstar, grad
         torch.cuda.empty_cache()
     adj["backward_over_forward"] = adj["backward_s"] / adj["forward_s"]
-    out["adjoint"] = adj
-    return out
+    return adj
 
 
 def secondary_configs(cx, torch, netspec):
@@ -363,6 +369,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size before the timed region "
                          "(a known-size reference for HBM byte counters)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint over the 64 batched instances and print its figures "
+                         "(a profiling aid; not the benchmark line)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -378,6 +387,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_all(cx, torch, 4, args.batched_steps)}), flush=True)
+        return
     big = args.workload == "brunel_2m_bf16"
     spec = netspec.brunel_2m_bf16(scale_n=args.scale) if big else netspec.brunel_112k_alpha(scale_n=args.scale)
     seed = args.seed if big else 2

@@ -52,7 +52,7 @@ typedef enum {
     CORTEX_ETRUNC = -7        /* output truncated (buffer or log capacity) */
 } cortex_status;
 
-enum { CORTEX_MODEL_DELTA = 0, CORTEX_MODEL_EXP = 1, CORTEX_MODEL_ALPHA = 2 };
+enum { CORTEX_MODEL_DELTA = 0, CORTEX_MODEL_EXP = 1, CORTEX_MODEL_ALPHA = 2, CORTEX_MODEL_COND = 3 };
 enum { CORTEX_RULE_FIXED_INDEGREE = 0, CORTEX_RULE_PAIRWISE = 1 };
 enum { CORTEX_DELAY_CONST = 0, CORTEX_DELAY_UNIFORM_INT = 1, CORTEX_DELAY_NORMAL = 2 };
 enum { CORTEX_UNIT_NATIVE = 0, CORTEX_UNIT_PSP_MV = 1 };
@@ -146,6 +146,20 @@ typedef struct {
     int32_t stdp_enable;
     int32_t stdp_pop;
     double stdp_lambda, stdp_alpha, stdp_mu, stdp_tau_plus, stdp_tau_minus, stdp_w0, stdp_wmax;
+    /* CORTEX_MODEL_COND, the conductance form of the synaptic current (Sec.
+       I-A Eq. 3) with exponential conductances: a spike through a synapse of
+       weight w (nS, native units only) adds |w| to the target's excitatory
+       (w >= 0, reversal potential E_ex) or inhibitory (w < 0, E_in)
+       conductance, each decaying with tau_syn;
+         C dV/dt = -(C / tau_m)(V - E_L) + g_ex (E_ex - V) + g_in (E_in - V) + I_e.
+       A step holds the conductances at their values at its start, for which
+       the membrane's solution is exact (V relaxes towards the conductance-
+       weighted mean of the reversal potentials with rate G / C); the step's
+       arrivals then join the conductances (V feels them from the next step).
+       External Poisson events enter the channel of w_ext's sign.  Resident
+       plan with 64-bit rings (the two channels in two 32-bit halves); no
+       plasticity and no adjoint. */
+    double E_ex, E_in;
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device

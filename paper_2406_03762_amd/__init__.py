@@ -59,7 +59,8 @@ class cortex_spec(C.Structure):
                 ("plan_kind", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("stdp_enable", C.c_int32), ("stdp_pop", C.c_int32), ("stdp_lambda", C.c_double),
                 ("stdp_alpha", C.c_double), ("stdp_mu", C.c_double), ("stdp_tau_plus", C.c_double),
-                ("stdp_tau_minus", C.c_double), ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double)]
+                ("stdp_tau_minus", C.c_double), ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double),
+                ("E_ex", C.c_double), ("E_in", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -142,7 +143,7 @@ def _dev_ptr(t, name: str, dtype, numel: int, device=None) -> Optional[int]:
     return t.data_ptr()
 
 
-_MODEL = {"delta": 0, "exp": 1, "alpha": 2}
+_MODEL = {"delta": 0, "exp": 1, "alpha": 2, "cond": 3}
 _RULE = {"fixed_indegree": 0, "pairwise": 1}
 _DELAY = {"const": 0, "uniform_int": 1, "normal": 2}
 _UNIT = {"native": 0, "psp_mV": 1}
@@ -189,6 +190,7 @@ def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 
     s.spin_limit_log2 = spin_limit_log2
     s.steps_per_sync = steps_per_sync
     s.plan_kind = _PLAN[plan]
+    s.E_ex, s.E_in = getattr(net, "E_ex", 0.0), getattr(net, "E_in", -85.0)
     st = getattr(net, "stdp", None)
     if st is not None:
         s.stdp_enable, s.stdp_pop = 1, st.pop

@@ -46,7 +46,9 @@ Consts model_constants(const cortex_spec& s) {
     k.P20 = -(tm / C) * std::expm1(-dt / tm);
     k.jump = 1.0;
     k.conv = 1.0;
-    if (s.model != CORTEX_MODEL_DELTA) {
+    if (s.model == CORTEX_MODEL_COND) {
+        k.P11 = std::exp(-dt / ts);   // conductance decay per step
+    } else if (s.model != CORTEX_MODEL_DELTA) {
         const double a = 1.0 / ts - 1.0 / tm;
         k.P11 = std::exp(-dt / ts);
         k.P21 = (a == 0.0) ? k.P22 * dt / C : k.P22 * (-std::expm1(-a * dt)) / (C * a);
@@ -192,7 +194,14 @@ static void validate(const cortex_spec* s) {
     require(s != nullptr, CORTEX_EINVAL, "spec is NULL");
     require(s->abi_version == CORTEX_ABI_VERSION, CORTEX_EINVAL, "spec ABI version mismatch");
     require(s->struct_size == sizeof(cortex_spec), CORTEX_EINVAL, "spec struct size mismatch");
-    require(s->model >= 0 && s->model <= 2, CORTEX_EINVAL, "unknown neuron model");
+    require(s->model >= 0 && s->model <= 3, CORTEX_EINVAL, "unknown neuron model");
+    if (s->model == CORTEX_MODEL_COND) {
+        require(s->weight_unit == CORTEX_UNIT_NATIVE, CORTEX_EINVAL, "conductance synapses take native weights (nS)");
+        require(s->weight_dtype == CORTEX_W_FP32 && !s->stdp_enable && s->ckpt_every == 0 &&
+                    s->plan_kind != CORTEX_PLAN_STREAMED,
+                CORTEX_EUNSUPPORTED,
+                "conductance synapses run on the resident plan with FP32 weights, without plasticity or adjoint");
+    }
     require(s->precision == CORTEX_FP32 || s->precision == CORTEX_FP64_VERIFY, CORTEX_EINVAL, "unknown precision");
     require(s->weight_dtype == CORTEX_W_FP32 || s->weight_dtype == CORTEX_W_BF16, CORTEX_EINVAL, "unknown weight dtype");
     require(s->weight_unit == CORTEX_UNIT_NATIVE || s->weight_unit == CORTEX_UNIT_PSP_MV, CORTEX_EINVAL, "unknown weight unit");
@@ -720,7 +729,8 @@ static void plan_fp32(cortex_net* n) {
     bool planned = false;
     if (s.plan_kind != CORTEX_PLAN_STREAMED && !s.stdp_enable) {
         n->plan_kind = CORTEX_PLAN_RESIDENT;
-        for (int rb = 8; rb >= 4 && !planned; rb -= 4) {
+        const int rb_min = s.model == CORTEX_MODEL_COND ? 8 : 4;   // two 32-bit channels per cell
+        for (int rb = 8; rb >= rb_min && !planned; rb -= 4) {
             n->ring_bytes = rb;
             for (int W = W0;; W = std::max(1, W / 2)) {
                 n->W = W;
@@ -731,7 +741,7 @@ static void plan_fp32(cortex_net* n) {
                     planned = true;
                     break;
                 } catch (const Error& e) {
-                    const bool last = rb == 4 && (W == 1 || s.steps_per_sync > 0);
+                    const bool last = rb == rb_min && (W == 1 || s.steps_per_sync > 0);
                     if (e.status != CORTEX_EUNSUPPORTED || (last && s.plan_kind == CORTEX_PLAN_RESIDENT)) throw;
                     if (W == 1 || s.steps_per_sync > 0) break;
                 }
@@ -739,6 +749,8 @@ static void plan_fp32(cortex_net* n) {
         }
     }
     if (!planned) {
+        require(s.model != CORTEX_MODEL_COND, CORTEX_EUNSUPPORTED,
+                "conductance synapses need the resident plan, and this network does not fit it");
         n->plan_kind = CORTEX_PLAN_STREAMED;
         require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "the adjoint needs the resident plan (the network is too "
                                                      "large for workgroup-local input rings)");
@@ -943,7 +955,8 @@ static void build(cortex_net* n) {
         n->fx_shift = fixed_point_shift(n, n->fx);
         upload_tables_fp32(n);
         build_graph_fp32(n);
-        if (n->ring_bytes == 4) {
+        if (n->ring_bytes == 4 || s.model == CORTEX_MODEL_COND) {
+            // (conductances: each 32-bit half of a cell holds one channel's sum)
             const double bound = max_abs_input(n) * (1.0 + 1e-4) + 1e-30;
             n->fx = std::max(0, std::min(52, 30 - (int)std::ceil(std::log2(bound))));
             n->fx_shift = 0;

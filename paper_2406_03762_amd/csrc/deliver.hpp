@@ -23,17 +23,29 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace cortex {
 
 constexpr int kDeliverBlk = 512;   // 64-synapse blocks per piece of the short-segment mapping
 
+// Ring cells: 64-bit (long long) or 32-bit (int) signed sums; or, for the
+// conductance model (unsigned long long), two 32-bit channels in one cell:
+// excitatory weights (>= 0) in the low half, inhibitory ones (< 0, as |w|)
+// in the high half.  Each half stays below 2^31 (the fixed-point scale is
+// set from the largest sum of |w| a target can receive), so no carry ever
+// crosses from one channel into the other.
 template <typename RING>
 __device__ __forceinline__ void ring_add(RING* ring, uint32_t x, int32_t iw) {
-    if (sizeof(RING) == 8)
+    if (std::is_same<RING, unsigned long long>::value) {
+        const unsigned long long v = iw >= 0 ? (unsigned long long)(uint32_t)iw
+                                             : (unsigned long long)(uint32_t)(-iw) << 32;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), v);
+    } else if (sizeof(RING) == 8) {
         atomicAdd(reinterpret_cast<unsigned long long*>(&ring[x]), (unsigned long long)(long long)iw);
-    else
+    } else {
         atomicAdd(reinterpret_cast<unsigned int*>(&ring[x]), (unsigned int)iw);
+    }
 }
 
 // Record e: meta (delay - d_min) T + target and the weight.  Two layouts:

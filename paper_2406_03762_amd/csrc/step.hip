@@ -76,6 +76,7 @@ struct StepArgs {
     float P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
     float fxw_scale;            // 2^fw: synaptic weight to its 32-bit fixed-point value
     double fx_inv;              // 2^-fw: ring sum to input
+    float gL, Eex, Ein, Ie, dt_C;   // conductance model (reversal potentials relative to E_L)
     uint64_t seed;
     uint32_t thr[kMaxThr];
 };
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             U[k] = a.U[g0 + li];
             RF[k] = a.r[g0 + li];
             if (MODEL != CORTEX_MODEL_DELTA) Y1[k] = a.y1[g0 + li];
-            if (MODEL == CORTEX_MODEL_ALPHA) Y2[k] = a.y2[g0 + li];
+            if (MODEL == CORTEX_MODEL_ALPHA || MODEL == CORTEX_MODEL_COND) Y2[k] = a.y2[g0 + li];
         }
     }
     const RING* g_ring = static_cast<const RING*>(a.ring) + (size_t)tile * R * T;
@@ -389,7 +390,15 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                 int slot = slot0;
                 for (int si = 0; si < wn; ++si, slot = (slot + 1 == R) ? 0 : slot + 1) {
                     const int64_t n = t0 + si;
-                    const float x = (float)((double)ring[slot * T + li] * a.fx_inv);
+                    float x, x_in = 0.f;
+                    if (MODEL == CORTEX_MODEL_COND) {
+                        // the two channels of the cell: excitatory low, inhibitory high
+                        const unsigned long long c = (unsigned long long)ring[slot * T + li];
+                        x = (float)((double)(uint32_t)c * a.fx_inv);
+                        x_in = (float)((double)(uint32_t)(c >> 32) * a.fx_inv);
+                    } else {
+                        x = (float)((double)ring[slot * T + li] * a.fx_inv);
+                    }
                     ring[slot * T + li] = 0;
                     const int kc = s_kcb[(size_t)((n >> 3) & 1) * 8 * T + (size_t)(n & 7) * T + li];
                     const float inp = x + a.w_ext * (float)kc;
@@ -398,6 +407,11 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     if (!integ) {
                         RF[k] -= 1;
                         u_new = a.Ur;
+                    } else if (MODEL == CORTEX_MODEL_COND) {
+                        // the exact solution for conductances held over the step
+                        const float G = a.gL + Y1[k] + Y2[k];
+                        const float u_inf = (Y1[k] * a.Eex + Y2[k] * a.Ein + a.Ie) / G;
+                        u_new = u_inf + (U[k] - u_inf) * expf(-a.dt_C * G);
                     } else if (MODEL == CORTEX_MODEL_DELTA) {
                         u_new = a.P22 * U[k] + a.P20Ie + inp;
                     } else if (MODEL == CORTEX_MODEL_EXP) {
@@ -410,6 +424,11 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                     } else if (MODEL == CORTEX_MODEL_ALPHA) {
                         Y2[k] = a.P21s * Y1[k] + a.P22s * Y2[k];
                         Y1[k] = a.P11 * Y1[k] + a.jump * inp;
+                    } else if (MODEL == CORTEX_MODEL_COND) {
+                        const float ext = a.w_ext * (float)kc;   // into the channel of its sign
+                        Y1[k] = a.P11 * Y1[k] + x + (ext >= 0.f ? ext : 0.f);
+                        Y2[k] = a.P11 * Y2[k] + x_in + (ext < 0.f ? -ext : 0.f);
+                        x = x - x_in;   // the trace records the signed sum of the arrivals
                     }
                     const bool spk = a.frz_ptr ? ((frz >> si) & 1u) != 0 : (integ && u_new >= a.theta);
                     if (spk) {
@@ -462,7 +481,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
             a.U[g0 + li] = U[k];
             a.r[g0 + li] = RF[k];
             if (MODEL != CORTEX_MODEL_DELTA) a.y1[g0 + li] = Y1[k];
-            if (MODEL == CORTEX_MODEL_ALPHA) a.y2[g0 + li] = Y2[k];
+            if (MODEL == CORTEX_MODEL_ALPHA || MODEL == CORTEX_MODEL_COND) a.y2[g0 + li] = Y2[k];
         }
     }
     RING* g_ring_out = static_cast<RING*>(a.ring) + (size_t)tile * R * T;
@@ -496,11 +515,20 @@ KernelFn pick_model(int model, int meta_bytes, int w_bytes, int npt) {
     switch (model) {
         case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA, RING>(meta_bytes, w_bytes, npt);
         case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP, RING>(meta_bytes, w_bytes, npt);
-        default: return pick_fmt<CORTEX_MODEL_ALPHA, RING>(meta_bytes, w_bytes, npt);
+        case CORTEX_MODEL_ALPHA: return pick_fmt<CORTEX_MODEL_ALPHA, RING>(meta_bytes, w_bytes, npt);
+        default: return nullptr;
     }
 }
 
+// Conductances: two 32-bit channels per 64-bit cell, FP32 weights.
+KernelFn pick_cond(int meta_bytes, int w_bytes, int npt) {
+    if (w_bytes != 4) return nullptr;
+    return meta_bytes == 2 ? pick_npt<CORTEX_MODEL_COND, uint16_t, false, unsigned long long>(npt)
+                           : pick_npt<CORTEX_MODEL_COND, uint32_t, false, unsigned long long>(npt);
+}
+
 KernelFn pick_variant(int model, int meta_bytes, int w_bytes, int npt, int ring_bytes) {
+    if (model == CORTEX_MODEL_COND) return ring_bytes == 8 ? pick_cond(meta_bytes, w_bytes, npt) : nullptr;
     return ring_bytes == 8 ? pick_model<long long>(model, meta_bytes, w_bytes, npt)
                            : pick_model<int>(model, meta_bytes, w_bytes, npt);
 }
@@ -616,6 +644,11 @@ void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     // weights are rounded at 2^(fx - fx_shift) and summed in those units
     a.fxw_scale = std::ldexp(1.0f, n->fx - n->fx_shift);
     a.fx_inv = std::ldexp(1.0, n->fx_shift - n->fx);
+    a.gL = (float)(n->spec.C_m / n->spec.tau_m);
+    a.Eex = (float)(n->spec.E_ex - n->spec.E_L);
+    a.Ein = (float)(n->spec.E_in - n->spec.E_L);
+    a.Ie = (float)n->spec.I_e;
+    a.dt_C = (float)(n->spec.dt / n->spec.C_m);
     a.seed = n->seed;
     for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
     KernelFn f = pick_kernel(n);

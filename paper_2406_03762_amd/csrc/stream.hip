@@ -457,7 +457,8 @@ StreamFn pick_stream(int model, int meta_bytes, int w_bytes, int npt) {
     switch (model) {
         case CORTEX_MODEL_DELTA: return pick_fmt<CORTEX_MODEL_DELTA>(meta_bytes, w_bytes, npt);
         case CORTEX_MODEL_EXP: return pick_fmt<CORTEX_MODEL_EXP>(meta_bytes, w_bytes, npt);
-        default: return pick_fmt<CORTEX_MODEL_ALPHA>(meta_bytes, w_bytes, npt);
+        case CORTEX_MODEL_ALPHA: return pick_fmt<CORTEX_MODEL_ALPHA>(meta_bytes, w_bytes, npt);
+        default: return nullptr;   // conductances need 64-bit rings
     }
 }
 

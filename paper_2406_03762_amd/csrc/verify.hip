@@ -39,6 +39,7 @@ struct VerifyArgs {
     int64_t N, W, n0, log_step0, log_steps;
     int Hr, model, n_ref, n_thr;
     double P22, P20Ie, P11, P21, P31, P32, P21s, P22s, jump, theta, Ur, w_ext, E_L;
+    double gL, Eex, Ein, Ie, dt_C;   // conductance model (reversal potentials relative to E_L)
     uint64_t seed;
     uint32_t thr[64];
 };
@@ -50,14 +51,17 @@ __global__ void __launch_bounds__(256) verify_step_kernel(VerifyArgs a, int64_t 
     bool spk = false;
     unsigned long long ev = 0;
     if (i < a.N) {
-        double x = 0.0;
+        // conductances: excitatory (w >= 0) and inhibitory (|w|) arrivals in
+        // two sums, each in the canonical order
+        double x = 0.0, xin = 0.0;
         for (uint64_t e = a.in_ptr[i]; e < a.in_ptr[i + 1]; ++e) {
             const int64_t m = n - (int64_t)a.in_d[e];
             if (m < 0) continue;
             const uint32_t j = a.in_src[e];
             const uint64_t word = a.hist[(m & (a.Hr - 1)) * a.W + (j >> 6)];
             if ((word >> (j & 63)) & 1ull) {
-                x = x + a.in_w[e];
+                if (MODEL == CORTEX_MODEL_COND && a.in_w[e] < 0.0) xin = xin + (-a.in_w[e]);
+                else x = x + a.in_w[e];
                 ++ev;
             }
         }
@@ -78,7 +82,28 @@ __global__ void __launch_bounds__(256) verify_step_kernel(VerifyArgs a, int64_t 
         double U = a.U[i];
         int rr = a.r[i];
         bool integ = false;
-        if (rr > 0) {
+        if (MODEL == CORTEX_MODEL_COND) {
+            if (rr > 0) {
+                rr -= 1;
+                U = a.Ur;
+            } else {
+                integ = true;
+                double G = a.gL + a.y1[i];
+                G = G + a.y2[i];
+                double num = a.y1[i] * a.Eex;
+                num = num + a.y2[i] * a.Ein;
+                num = num + a.Ie;
+                const double u_inf = num / G;
+                const double e = exp(-a.dt_C * G);
+                U = u_inf + (U - u_inf) * e;
+            }
+            double gex = a.P11 * a.y1[i];
+            double gin = a.P11 * a.y2[i];
+            if (ext >= 0.0) gex = gex + ext; else gin = gin - ext;
+            a.y1[i] = gex + x;
+            a.y2[i] = gin + xin;
+            x = x - xin;   // the trace records the signed sum of the arrivals
+        } else if (rr > 0) {
             rr -= 1;
             U = a.Ur;
         } else {
@@ -180,6 +205,11 @@ void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits, 
     a.Ur = n->spec.V_reset - n->spec.E_L;
     a.w_ext = n->w_ext_native;
     a.E_L = n->spec.E_L;
+    a.gL = n->spec.C_m / n->spec.tau_m;
+    a.Eex = n->spec.E_ex - n->spec.E_L;
+    a.Ein = n->spec.E_in - n->spec.E_L;
+    a.Ie = n->spec.I_e;
+    a.dt_C = n->spec.dt / n->spec.C_m;
     a.seed = n->seed;
     for (int m = 0; m < n->n_thr; ++m) a.thr[m] = n->thr[m];
     const int grid = (int)((n->N + 255) / 256);
@@ -192,6 +222,10 @@ void launch_step_fp64(cortex_net* n, int64_t n_steps, const uint64_t* frz_bits, 
                 break;
             case CORTEX_MODEL_EXP:
                 hipLaunchKernelGGL(verify_step_kernel<CORTEX_MODEL_EXP>, dim3(grid), dim3(256), 0,
+                                   n->stream, a, step);
+                break;
+            case CORTEX_MODEL_COND:
+                hipLaunchKernelGGL(verify_step_kernel<CORTEX_MODEL_COND>, dim3(grid), dim3(256), 0,
                                    n->stream, a, step);
                 break;
             default:

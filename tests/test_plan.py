@@ -155,3 +155,26 @@ def test_plasticity_plans_are_streamed_with_short_windows():
     with pytest.raises(cx.CortexError) as e:
         cx.cortex_plan(bad, **MI355X)
     assert e.value.status == cx.EINVAL
+
+
+def test_conductance_plans_are_resident_with_64_bit_rings():
+    inst = netspec.brunel_instance(800, 200, 80, 20, 1.0, 5.0, delay="uniform_int", d0=10, d1=20)
+    spec = netspec.NetSpec(model="cond", tau_m=20.0, C_m=250.0, E_L=-70.0, V_th=-50.0, V_reset=-60.0,
+                           tau_syn=2.0, poisson_lambda=0.45, w_ext=0.5, instances=[inst])
+    p = cx.cortex_plan(spec, **MI355X)
+    check(p, spec)
+    assert p["plan"] == cx.PLAN_RESIDENT and p["ring_bytes"] == 8
+    for bad, status in ((dict(plan="streamed"), cx.EUNSUPPORTED),):
+        with pytest.raises(cx.CortexError) as e:
+            cx.cortex_plan(spec, **bad, **MI355X)
+        assert e.value.status == status
+    psp = netspec.NetSpec(**{**spec.__dict__, "weight_unit": "psp_mV"})
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(psp, **MI355X)
+    assert e.value.status == cx.EINVAL
+    # a network too large for the resident plan is refused, not streamed
+    big = netspec.brunel_2m_bf16()
+    big = netspec.NetSpec(**{**big.__dict__, "model": "cond", "weight_dtype": "fp32", "tau_syn": 2.0})
+    with pytest.raises(cx.CortexError) as e:
+        cx.cortex_plan(big, **MI355X)
+    assert e.value.status == cx.EUNSUPPORTED
