@@ -152,7 +152,10 @@ def choose_plan(cx, spec, seed, args):
     """The launch plan request of a timed network: the command line's, else
     a freshly measured one (--autotune), else the tuned table's entry for
     this network on this device, else the planner's default."""
-    explicit = dict(tile_size=args.tile_size, block_size=args.block_size, wg_per_cu=args.wg_per_cu)
+    explicit = dict(tile_size=args.tile_size, block_size=args.block_size, wg_per_cu=args.wg_per_cu,
+                    steps_per_sync=getattr(args, "steps_per_sync", 0))
+    if getattr(args, "stage_records", 0):
+        explicit["stage_records"] = args.stage_records
     if any(explicit.values()):
         return explicit, "command line"
     if args.autotune:
@@ -354,6 +357,9 @@ def main():
     ap.add_argument("--tile-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--steps-per-sync", type=int, default=0, help="exchange window W (0: tuned or planner)")
+    ap.add_argument("--stage-records", type=int, default=0,
+                    help="streamed plan: records per tile staged per window (0: automatic, -1: none)")
     ap.add_argument("--autotune", action="store_true",
                     help="measure the candidate launch plans of the timed networks first (minutes for the "
                          "two-million-neuron net) and use the fastest; without it the tuned table is used")
@@ -403,6 +409,7 @@ def main():
     log(f"[bench] built: N={net.N} E={net.E} plan={'streamed' if net.query('PLAN') == 2 else 'resident'} "
         f"tiles={net.query('TILES')} T={net.query('TILE_SIZE')} R={net.query('RING_SLOTS')} "
         f"W={net.query('STEPS_PER_SYNC')} BS={net.query('BLOCK_SIZE')} rec={net.query('EDGE_BYTES')}B "
+        f"staged={net.query('STAGE_RECORDS')} "
         f"device={net.query('DEVICE_BYTES') / 2**30:.1f} GiB in {t_build:.1f}s")
 
     if args.copy_calibration_mib > 0:

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CORTEX_ABI_VERSION 3
+#define CORTEX_ABI_VERSION 4
 
 typedef enum {
     CORTEX_OK = 0,
@@ -160,6 +160,14 @@ typedef struct {
        plan with 64-bit rings (the two channels in two 32-bit halves); no
        plasticity and no adjoint. */
     double E_ex, E_in;
+    /* FP32 streamed plan of one instance whose sources reach a tile through
+       a few synapses each (segments shorter than 16): records per tile that
+       a window copies from the graph into a tile-major run before its
+       delivery (every record line then read once, instead of a line per
+       spike and tile).  0 = automatic (a window at 50 Hz, the buffer within
+       4 GiB), < 0 = no staging.  A window with more records for a tile
+       delivers the excess straight from the graph; the sums are the same. */
+    int64_t stage_records;
 } cortex_spec;
 
 /* Device memory and stream supplied by the caller.  alloc returns device
@@ -201,7 +209,8 @@ int cortex_build_network(const cortex_spec* spec, uint64_t seed, const cortex_de
    entries, fewer are cut): plan kind, tiles, tile stride T, workgroup size,
    neurons per thread, steps per exchange W, ring slots, history slots, chunk,
    largest tile count of an instance, LDS bytes, ring element bytes, d_min,
-   d_max, XCD map, one-thread-per-segment delivery.  Errors: EINVAL,
+   d_max, XCD map, one-thread-per-segment delivery, records per tile staged
+   per window (0: none).  Errors: EINVAL,
    EUNSUPPORTED (no plan fits, or a plan failed its check). */
 int cortex_plan(const cortex_spec* spec, int32_t n_cu, int64_t lds_per_cu, int32_t threads_per_cu,
                 int64_t* plan, int32_t n_plan);
@@ -334,7 +343,8 @@ enum {
     CORTEX_Q_STEPS_PER_SYNC = 15, /* FP32: time steps per spike exchange chosen at build */
     CORTEX_Q_RING_BYTES = 16,     /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
     CORTEX_Q_PLAN = 17,           /* FP32: CORTEX_PLAN_RESIDENT or CORTEX_PLAN_STREAMED */
-    CORTEX_Q_NPT = 18             /* FP32: neurons per thread */
+    CORTEX_Q_NPT = 18,            /* FP32: neurons per thread */
+    CORTEX_Q_STAGE_RECORDS = 19   /* FP32 streamed: records per tile staged per window (0: none) */
 };
 /* Passage: the sizes of G (Sec. II-A) and of its decomposition (Eq. 9-10);
    EVENTS counts the edges of the spiking sub-graphs (Eq. 11) delivered.

@@ -18,11 +18,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcortex.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cortex.h")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
 Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
          STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
-         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16, PLAN=17, NPT=18)
+         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16, PLAN=17, NPT=18, STAGE_RECORDS=19)
 PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAMED = 0, 1, 2
 _PLAN = {"auto": PLAN_AUTO, "resident": PLAN_RESIDENT, "streamed": PLAN_STREAMED}
 
@@ -60,7 +60,7 @@ class cortex_spec(C.Structure):
                 ("stdp_enable", C.c_int32), ("stdp_pop", C.c_int32), ("stdp_lambda", C.c_double),
                 ("stdp_alpha", C.c_double), ("stdp_mu", C.c_double), ("stdp_tau_plus", C.c_double),
                 ("stdp_tau_minus", C.c_double), ("stdp_w0", C.c_double), ("stdp_wmax", C.c_double),
-                ("E_ex", C.c_double), ("E_in", C.c_double)]
+                ("E_ex", C.c_double), ("E_in", C.c_double), ("stage_records", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -151,9 +151,11 @@ _UNIT = {"native": 0, "psp_mV": 1}
 
 def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 0,
               ckpt_every: int = 0, adjoint_steps: int = 0, spin_limit_log2: int = 0,
-              steps_per_sync: int = 0, plan: str = "auto", wg_per_cu: int = 0):
+              steps_per_sync: int = 0, plan: str = "auto", wg_per_cu: int = 0, stage_records: int = 0):
     """Marshal a network description (netspec.NetSpec) into cortex_spec.
-    ``plan``: "auto", "resident" or "streamed" (FP32 launch plan).
+    ``plan``: "auto", "resident" or "streamed" (FP32 launch plan);
+    ``stage_records``: streamed plan, records per tile staged per window (0:
+    automatic, negative: no staging).
 
     Returns (spec, keepalive)."""
     pops, projs = [], []
@@ -197,6 +199,7 @@ def make_spec(net, tile_size: int = 0, block_size: int = 0, record_steps: int = 
         s.stdp_lambda, s.stdp_alpha, s.stdp_mu = st.lam, st.alpha, st.mu
         s.stdp_tau_plus, s.stdp_tau_minus, s.stdp_w0, s.stdp_wmax = st.tau_plus, st.tau_minus, st.w0, st.wmax
     s.wg_per_cu = wg_per_cu
+    s.stage_records = stage_records
     return s, (pa, qa)
 
 
@@ -239,7 +242,7 @@ def cortex_build_network(net, seed: int, device=None, stream=None, **plan):
 
 
 PLAN_FIELDS = ("plan", "tiles", "T", "block_size", "npt", "W", "R", "H", "chunk", "ntb_max", "lds_bytes",
-               "ring_bytes", "dmin", "dmax", "xcd_map", "thread_segments")
+               "ring_bytes", "dmin", "dmax", "xcd_map", "thread_segments", "stage_records")
 
 
 def cortex_plan(net, n_cu: int = 256, lds_per_cu: int = 163840, threads_per_cu: int = 2048, **plan) -> dict:

@@ -23,6 +23,7 @@ SOURCES = [
     ("stream.hip", []),
     ("noalloc.hip", []),
     ("stdp.hip", []),
+    ("gather.hip", []),
 ]
 
 ARCH = os.environ.get("CORTEX_OFFLOAD_ARCH", "gfx950")

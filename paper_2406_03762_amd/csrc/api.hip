@@ -636,6 +636,21 @@ static void plan_stream(cortex_net* n) {
     double seg = 0.0;
     for (int b = 0; b < n->n_inst; ++b) seg = std::max(seg, K[b] * (double)Tb[b] / (double)n->inst_N[b]);
     n->thread_segments = seg < 16.0 ? 1 : 0;
+    // tile-major staging of each window's records (one instance, short
+    // segments): capacity per tile for a window at 50 Hz by default, the
+    // whole buffer within 4 GiB; a denser window delivers its excess from
+    // the graph
+    n->stage_cap = 0;
+    if (n->thread_segments && n->n_inst == 1 && s.stage_records >= 0) {
+        const uint64_t rec = (s.weight_dtype == CORTEX_W_BF16) ? 4 : 8;
+        const uint64_t lim = std::min<uint64_t>((4ull << 30) / ((uint64_t)n->n_tiles * rec), 0x7FFFFFFFull);
+        uint64_t cap = (uint64_t)s.stage_records;
+        if (cap == 0) {
+            const double per = K[0] * (double)Tb[0] * (double)n->W * s.dt * 1e-3 * 50.0;
+            cap = std::max<uint64_t>(4096, ((uint64_t)std::ceil(per) + 63) & ~63ull);
+        }
+        n->stage_cap = (uint32_t)std::min(cap, lim);
+    }
     std::vector<double> load(n->n_tiles);
     for (int t = 0; t < n->n_tiles; ++t) load[t] = K[n->tile_inst[t]] * n->tile_size[t];
     const bool uniform = *std::max_element(load.begin(), load.end()) <= 1.05 * *std::min_element(load.begin(), load.end());
@@ -706,6 +721,13 @@ static std::string plan_violation(const cortex_net* n) {
             if (perm) seen[t] = 1;
         }
         need(perm, "workgroup order is not a permutation of the tiles");
+        if (n->stage_cap) {
+            need(n->thread_segments && n->n_inst == 1, "staging needs one instance with short segments");
+            need(n->W <= 8, "staging window");
+            // a staged record's ring row relative to the window, meta + qi T,
+            // stays below R T (and 2^16 with 16-bit records)
+            need(n->stage_cap >= 1 && n->stage_cap < 0x80000000u, "staging capacity");
+        }
     } else {
         need(n->lds_bytes == step_lds_bytes(n->R, n->T, n->W, n->ntb_max, n->chunk, n->ring_bytes),
              "resident LDS carve-up");
@@ -802,6 +824,12 @@ static void alloc_state_fp32(cortex_net* n) {
         n->d_spk_ids = dev_alloc_t<uint32_t>(n, (size_t)n->H * n->N);
         n->d_clock = dev_alloc_t<int64_t>(n, 2);
         n->use_graph = true;
+        n->d_kcache = dev_alloc_t<unsigned long long>(n, n->N);
+        if (n->stage_cap) {
+            const size_t rec = n->w_bytes == 2 ? 4 : 8;
+            n->d_stage = dev_alloc(n, (size_t)n->n_tiles * n->stage_cap * rec);
+            n->d_cursor = dev_alloc_t<unsigned long long>(n, n->n_tiles);
+        }
         if (n->stdp) {
             n->d_seg_state = dev_alloc_t<uint64_t>(n, std::max<uint64_t>(1, n->n_seg));
             n->d_hist_step = dev_alloc_t<int32_t>(n, (size_t)n->N * kHistLen);
@@ -848,6 +876,8 @@ static void zero_dynamic_fp32(cortex_net* n) {
     if (n->plan_kind == CORTEX_PLAN_STREAMED) {
         dev_zero(n, n->d_spk_cnt, (size_t)n->H * n->n_inst * sizeof(uint32_t));
         dev_zero(n, n->d_clock, 2 * sizeof(int64_t));
+        if (n->stage_cap) dev_zero(n, n->d_cursor, (size_t)n->n_tiles * sizeof(unsigned long long));
+        dev_zero(n, n->d_kcache, (size_t)n->N * sizeof(unsigned long long));
         n->clock_parity = 0;
         drop_graph(n);
         if (n->stdp) {   // traces and histories restart; the weights stay
@@ -1212,7 +1242,7 @@ int cortex_plan(const cortex_spec* spec, int32_t n_cu, int64_t lds_per_cu, int32
         plan_fp32(n);
         const int64_t out[] = {n->plan_kind, n->n_tiles, n->T, n->BS, n->NPT, n->W, n->R, n->H, n->chunk,
                                n->ntb_max, (int64_t)n->lds_bytes, n->ring_bytes, n->dmin, n->dmax, n->xcd_map,
-                               n->thread_segments};
+                               n->thread_segments, (int64_t)n->stage_cap};
         for (int i = 0; i < n_plan && i < (int)(sizeof out / sizeof out[0]); ++i) plan[i] = out[i];
         delete n;
         return CORTEX_OK;
@@ -1504,6 +1534,7 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
         case CORTEX_Q_RING_BYTES: *value = fp64 ? 8 : n->ring_bytes; break;
         case CORTEX_Q_PLAN: *value = fp64 ? 0 : n->plan_kind; break;
         case CORTEX_Q_NPT: *value = fp64 ? 0 : n->NPT; break;
+        case CORTEX_Q_STAGE_RECORDS: *value = fp64 ? 0 : (int64_t)n->stage_cap; break;
         case CORTEX_Q_EVENTS:
         case CORTEX_Q_SPIKES: {
             require(!n->failed, CORTEX_ESTATE, "network failed earlier");

@@ -38,6 +38,14 @@ __device__ __forceinline__ Philox4 philox(uint64_t c0, uint64_t c1, uint64_t c2,
     return o;
 }
 
+// Word i (0..3) of a Philox block, chosen by selects: an array indexed by a
+// run-time value would be kept in scratch memory.
+__device__ __forceinline__ uint64_t philox_word(const Philox4& p, uint32_t i) {
+    const uint64_t lo = (i & 1u) ? p.v[1] : p.v[0];
+    const uint64_t hi = (i & 1u) ? p.v[3] : p.v[2];
+    return (i & 2u) ? hi : lo;
+}
+
 // Stream tags of the counter's last word.
 enum : uint64_t { kTagEdge = 1, kTagPoisson = 2, kTagV0 = 3, kTagPair = 5 };
 

@@ -1,0 +1,247 @@
+// Tile-major staging of a window's synapse records, for the streamed plan
+// when a source's segment into a tile holds only a few synapses (e.g. two
+// million neurons in tiles of about a thousand: 5-6 synapses, 22 bytes).
+//
+// Delivered straight from the graph, every (spike, tile) pair costs the tile
+// a cache line of records and a line of its segment descriptor, for some 30
+// useful bytes; the segments of one spike into consecutive tiles are
+// adjacent in memory (the graph is source-major, tiles in order), but the
+// workgroups of those tiles run on different compute units at different
+// times and rarely share the lines.  Here one launch per window first copies
+// the window's records, spike by spike, from those contiguous source rows
+// into a run per tile, so that every line is read once and the delivery
+// launch then streams its tile's run.
+//
+// The sums do not depend on the order of the additions (the ring adds
+// 32-bit fixed-point integers), so a tile's run holds its records in any
+// order: each copy work item (64 spikes x 64 tiles) reserves room in a
+// tile's run with one atomic add on the tile's cursor.  A staged record
+// carries its ring row relative to the window's first: meta + qi T, with qi
+// the spike's delivered step in the window (below R T, as meta is).  The
+// delivery kernel of the window reads the cursor of its tile and resets it;
+// a cursor past the capacity `cap` means the run is incomplete, and that
+// tile takes the whole window from the graph instead.  One instance only.
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace cortex {
+namespace {
+
+constexpr int kGChunk = 64;     // spikes per work item
+constexpr int kGTiles = 64;     // tiles per work item
+constexpr int kGMaxQ = 8;       // delivered steps per window
+constexpr int kGThreads = 512;  // threads per workgroup
+constexpr int kGWaves = kGThreads / 64;
+constexpr int kGPer = kGChunk / kGWaves;   // spikes of an item per wave
+constexpr int kGU = 4;          // records in flight per lane
+constexpr int kGatherGrid = 1024;
+
+struct GatherArgs {
+    const uint64_t* seg;        // (first synapse << 24) | length per (source, tile)
+    const void* meta;           // records (packed 32-bit words with bf16 weights)
+    const float* w;             // fp32 weights (separate array)
+    const uint32_t* spk_cnt;    // [H] spikes per step
+    const uint32_t* spk_ids;    // [H][N]
+    const int64_t* clock;       // [2] window starts
+    unsigned long long* cursor; // [ntb] records reserved in each tile's run
+    void* stage;                // [ntb][cap] records: u32 (bf16 packed) or uint2 {meta, weight bits}
+    uint64_t offb;              // the instance's first descriptor
+    int64_t N;
+    uint32_t cap, T;
+    int parity, wn, H, dmin, ntb;
+};
+
+struct CopyLds {
+    uint32_t rel[kGChunk][kGTiles];       // low 32 bits of each segment's first record
+    uint32_t dst[kGChunk][kGTiles];       // the segment's place in the item's share of its tile's run
+    unsigned long long e0[kGChunk];       // the spike's first record in the tile block
+    uint32_t end_lo[kGChunk];             // low 32 bits of the end of its records in the block
+    uint32_t j[kGChunk];
+    uint32_t qoff[kGChunk];               // ring row of its step, relative to the window's first: qi T
+    uint32_t tot[kGTiles];                // the item's records per tile
+    unsigned long long base[kGTiles];     // their place in the tile's run
+    uint32_t ok[kGTiles];
+    uint32_t wpre[kGWaves][kGPer + 1];    // per wave: prefix of its spikes' record counts
+};
+
+// One work item per (64 consecutive spikes of the window, block of 64
+// tiles).  The item's descriptors go to workgroup-local memory; a
+// workgroup-local atomic per segment gives its place in the item's share of
+// the tile's run, and one global atomic per tile reserves that share.  Each
+// wave then takes every kGWaves-th spike of the item and walks their records
+// as one flat list (a spike's segments into the block are one contiguous
+// range, in tile order), kGU records in flight per lane.
+// (Latency bound: eight waves per SIMD, each with kGU records in flight,
+// measured faster than fewer waves with more records each.)
+template <bool WBF16, typename META>
+__global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(8))) gather_copy_kernel(GatherArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    CopyLds& s = *reinterpret_cast<CopyLds*>(lds_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the window's delivered steps and the prefix of their spike counts
+    const int64_t t0 = a.clock[a.parity];
+    const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
+    const int nq = (int)max((int64_t)0, t0 - a.dmin + a.wn - q_lo);
+    uint32_t pc[kGMaxQ + 1];
+    pc[0] = 0;
+#pragma unroll
+    for (int qi = 0; qi < kGMaxQ; ++qi)
+        pc[qi + 1] = pc[qi] + (qi < nq ? a.spk_cnt[(size_t)((q_lo + qi) & (a.H - 1))] : 0u);
+    const uint32_t S = pc[kGMaxQ];
+    const uint32_t n_items_s = (S + kGChunk - 1) / kGChunk;
+    const uint32_t ngr = (uint32_t)(a.ntb + kGTiles - 1) / kGTiles;
+    const uint64_t rowlen = (uint64_t)a.ntb + 1;
+    for (uint32_t item = blockIdx.x; item < n_items_s * ngr; item += gridDim.x) {
+        const uint32_t c = item / ngr, g = item % ngr;
+        const uint32_t tb = g * kGTiles;
+        const int ntg = (int)min((uint32_t)kGTiles, (uint32_t)a.ntb - tb);
+        const uint32_t kn = min((uint32_t)kGChunk, S - c * kGChunk);
+        __syncthreads();   // the previous item's tables are read
+        if (tid < (int)kn) {
+            const uint32_t kf = c * kGChunk + (uint32_t)tid;
+            int qi = 0;
+#pragma unroll
+            for (int q = 1; q < kGMaxQ; ++q)
+                if (q < nq && pc[q] <= kf) qi = q;
+            s.j[tid] = a.spk_ids[(size_t)((q_lo + qi) & (a.H - 1)) * a.N + (kf - pc[qi])];
+            s.qoff[tid] = (uint32_t)qi * a.T;
+        }
+        if (tid < kGTiles) s.tot[tid] = 0;
+        __syncthreads();
+        // descriptors, all loads issued before their uses (an unused slot
+        // reads spike 0's descriptor of the block's first tile)
+        {
+            constexpr int UD = kGChunk * kGTiles / kGThreads;
+            uint64_t d[UD];
+#pragma unroll
+            for (int u = 0; u < UD; ++u) {
+                const int p = tid + kGThreads * u, k = p / kGTiles, tt = p % kGTiles;
+                const bool v = k < (int)kn && tt < ntg;
+                d[u] = a.seg[a.offb + (uint64_t)s.j[v ? k : 0] * rowlen + tb + (v ? tt : 0)];
+            }
+#pragma unroll
+            for (int u = 0; u < UD; ++u) {
+                const int p = tid + kGThreads * u, k = p / kGTiles, tt = p % kGTiles;
+                if (k < (int)kn && tt < ntg) {
+                    const uint64_t first = d[u] >> 24;
+                    const uint32_t len = (uint32_t)(d[u] & 0xFFFFFFu);
+                    s.rel[k][tt] = (uint32_t)first;
+                    s.dst[k][tt] = len ? atomicAdd(&s.tot[tt], len) : 0u;
+                    if (tt == 0) s.e0[k] = first;
+                    if (tt == ntg - 1) s.end_lo[k] = (uint32_t)(first + len);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < ntg) {
+            const uint32_t n = s.tot[tid];
+            const unsigned long long b = n ? atomicAdd(&a.cursor[tb + tid], (unsigned long long)n) : 0ull;
+            s.base[tid] = b;
+            s.ok[tid] = n > 0 && b + n <= a.cap;
+        }
+        __syncthreads();
+        // this wave's spikes k = wave + kGWaves i: prefix of their record counts
+        {
+            const uint32_t k = (uint32_t)wave + (uint32_t)kGWaves * (uint32_t)lane;
+            const uint32_t rl = (lane < kGPer && k < kn) ? s.end_lo[k] - (uint32_t)s.e0[k] : 0u;
+            const uint32_t incl = wave_incl_scan(rl);
+            if (lane < kGPer) s.wpre[wave][lane] = incl - rl;
+            if (lane == kGPer - 1) s.wpre[wave][kGPer] = incl;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t* wp = s.wpre[wave];
+        const uint32_t total = wp[kGPer];
+        constexpr int U = kGU;
+        for (uint32_t f0 = (uint32_t)lane; f0 < total; f0 += 64u * U) {
+            size_t at[U];
+            uint64_t e[U];
+            uint32_t qo[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // past the end: the last record (a valid address), not stored
+                const uint32_t f = min(f0 + 64u * (uint32_t)u, total - 1);
+                // fixed-step searches (no data-dependent branches, so that the
+                // eight records' lookups overlap): the spike, last i with
+                // wp[i] <= f ...
+                int lo = 0;
+#pragma unroll
+                for (int step = kGPer / 2; step > 0; step >>= 1)
+                    lo += wp[lo + step] <= f ? step : 0;
+                const uint32_t k = (uint32_t)wave + (uint32_t)kGWaves * (uint32_t)lo;
+                const uint32_t off = f - wp[lo];
+                const uint32_t r0 = (uint32_t)s.e0[k];
+                // ... and the tile, the last segment starting at or before off
+                int tl = 0;
+#pragma unroll
+                for (int step = kGTiles / 2; step > 0; step >>= 1) {
+                    const int cand = tl + step;
+                    const uint32_t rv = s.rel[k][min(cand, kGTiles - 1)];   // read either way: no branch
+                    tl = ((cand < ntg) & (rv - r0 <= off)) ? cand : tl;
+                }
+                ok[u] = f0 + 64u * (uint32_t)u < total && s.ok[tl] != 0;
+                e[u] = s.e0[k] + off;
+                qo[u] = s.qoff[k];
+                at[u] = (size_t)(tb + tl) * a.cap + s.base[tl] + s.dst[k][tl] + (off - (s.rel[k][tl] - r0));
+            }
+            if (WBF16) {
+                uint32_t r[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) r[u] = static_cast<const uint32_t*>(a.meta)[e[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u)   // meta + qi T stays below 2^16: no carry into the weight
+                    if (ok[u]) static_cast<uint32_t*>(a.stage)[at[u]] = r[u] + qo[u];
+            } else {
+                uint2 r[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    r[u] = make_uint2((uint32_t) static_cast<const META*>(a.meta)[e[u]], __float_as_uint(a.w[e[u]]));
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) static_cast<uint2*>(a.stage)[at[u]] = make_uint2(r[u].x + qo[u], r[u].y);
+            }
+        }
+    }
+}
+
+void (*copy_kernel(const cortex_net* n))(GatherArgs) {
+    if (n->w_bytes == 2) return gather_copy_kernel<true, uint16_t>;
+    return n->meta_bytes == 2 ? gather_copy_kernel<false, uint16_t> : gather_copy_kernel<false, uint32_t>;
+}
+
+}  // namespace
+
+// Once per network, before any launch is captured.
+void gather_prepare(cortex_net* n) {
+    CX_HIP(hipFuncSetAttribute((const void*)copy_kernel(n), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sizeof(CopyLds)));
+}
+
+void launch_gather(cortex_net* n, int parity, int wn, hipStream_t stream) {
+    GatherArgs a{};
+    a.seg = n->d_seg;
+    a.meta = n->d_meta;
+    a.w = static_cast<const float*>(n->d_w);
+    a.spk_cnt = n->d_spk_cnt;
+    a.spk_ids = n->d_spk_ids;
+    a.clock = n->d_clock;
+    a.cursor = n->d_cursor;
+    a.stage = n->d_stage;
+    a.offb = n->inst_offbase[0];
+    a.N = n->N;
+    a.cap = n->stage_cap;
+    a.T = (uint32_t)n->T;
+    a.parity = parity;
+    a.wn = wn;
+    a.H = n->H;
+    a.dmin = n->dmin;
+    a.ntb = n->n_tiles;
+    hipLaunchKernelGGL(copy_kernel(n), dim3(kGatherGrid), dim3(kGThreads), sizeof(CopyLds), stream, a);
+    CX_HIP(hipGetLastError());
+}
+
+}  // namespace cortex

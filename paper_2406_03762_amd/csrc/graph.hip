@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) gen_kernel(GenArgs a, double conv) {
                 if (j < B.n_src) {
                     const Philox4 p = philox((uint64_t)tl, (uint64_t)(j >> 2), (uint64_t)B.proj_local,
                                              kTagPair, a.seed, (uint64_t)B.instance);
-                    conn = (B.all_pairs || p.v[j & 3] < B.thr_p) &&
+                    conn = (B.all_pairs || philox_word(p, (uint32_t)(j & 3)) < B.thr_p) &&
                            !(B.same_pop_no_autapse && j == t_in_pop);
                 }
                 const uint64_t mask = __ballot(conn);

@@ -165,6 +165,12 @@ struct cortex_net {
     cortex::DeviceDesc dd;
     int clock_parity = 0;
     int thread_segments = 0;           // streamed delivery with one thread per (short) segment
+    // tile-major staging of each window's records (streamed plan, short
+    // segments, one instance): records per tile (0: no staging)
+    uint32_t stage_cap = 0;
+    void* d_stage = nullptr;                 // [n_tiles][stage_cap] records
+    unsigned long long* d_cursor = nullptr;  // [n_tiles] records staged for the coming delivery
+    unsigned long long* d_kcache = nullptr;  // streamed plan, [N]: Poisson counts of one 8-step block
     bool use_graph = true;
     // plasticity (streamed plan): per (source, tile) segment the presynaptic
     // trace just after the source's last spike and that spike's step + 1
@@ -249,6 +255,8 @@ void check_plastic_raster(const cortex_net* n, const uint32_t* st, const uint32_
 // Plasticity pass of one window of the streamed plan (stdp.hip): on `stream`,
 // before the window's delivery launch with the same clock parity and length.
 void launch_stdp(cortex_net* n, int parity, int wn, hipStream_t stream);
+void launch_gather(cortex_net* n, int parity, int wn, hipStream_t stream);
+void gather_prepare(cortex_net* n);
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                       const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
                       uint8_t* m_trace = nullptr);

@@ -172,7 +172,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
     uint64_t ev = 0, nspk = 0;
     const int64_t spin_max = (int64_t)1 << a.spin_log2;
     bool bail = false;
-    int64_t kc_blk[2] = {-1, -1};   // 8-step blocks held in s_kcb (same in every thread)
+    // 8-step blocks held in the two halves of s_kcb (same in every thread;
+    // two scalars, not an indexed array, which would live in scratch memory)
+    int64_t kc_blk0 = -1, kc_blk1 = -1;
     __syncthreads();
 
     for (int64_t t0 = a.n0; t0 < a.n1; t0 += a.W) {
@@ -201,7 +203,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
         auto prepare = [&]() {
             const int64_t blk0 = t0 >> 3, blk1 = (t0 + wn - 1) >> 3;
             for (int64_t blk = blk0; blk <= blk1; ++blk) {
-                if (kc_blk[blk & 1] == blk) continue;
+                if (((blk & 1) ? kc_blk1 : kc_blk0) == blk) continue;
                 unsigned char* dst = s_kcb + (size_t)(blk & 1) * 8 * T;
                 for (int li = tid; li < tsz; li += bs) {
                     const Philox4 p = philox((uint64_t)(g0 - n0b + li), (uint64_t)blk, 0, kTagPoisson, a.seed,
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         dst[sub * T + li] = (unsigned char)kc;
                     }
                 }
-                kc_blk[blk & 1] = blk;
+                if (blk & 1) kc_blk1 = blk; else kc_blk0 = blk;
             }
             prepared = true;
         };

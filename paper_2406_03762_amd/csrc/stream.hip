@@ -27,6 +27,7 @@
 // captured sequence of launches can be replayed without new arguments.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "deliver.hpp"
 #include "device_common.hpp"
@@ -54,6 +55,7 @@ struct StreamArgs {
     float* y1;
     float* y2;
     int32_t* r;
+    unsigned long long* kcache;    // per neuron: Poisson counts of one 8-step block (see block_counts)
     int32_t* ring;                 // [n_tiles][R][T] 32-bit fixed-point sums
     uint32_t* spk_cnt;             // [H][n_inst] spikes per step and instance
     uint32_t* spk_ids;             // [H][N] their ids (instance b at offset inst_n0[b])
@@ -72,6 +74,9 @@ struct StreamArgs {
     float* v_trace;
     uint8_t* m_trace;
     int64_t trace_step0;
+    const void* stage;             // staged records [n_tiles][stage_cap] (null: no staging)
+    unsigned long long* cursor;    // [n_tiles] records staged for this window (reset here)
+    uint32_t stage_cap;
     int64_t log_step0, log_steps, N;
     int parity, wn;
     int thread_segments;           // segments of a few synapses: one thread per segment
@@ -103,6 +108,84 @@ size_t stream_lds_bytes(int R, int T, int W, int chunk) {
 
 namespace {
 
+// Poisson counts of one 8-step block (neuron nl, steps 8 blk .. 8 blk + 7):
+// step 8 blk + sub takes the 32-bit half (sub & 1) of word sub >> 1 of the
+// Philox block (nl, blk, 0, Poisson tag); its count is the number of the
+// (increasing) thresholds at or below it, found by a binary search of the
+// table in workgroup-local memory.  6 bits per step, step sub at bit 6 sub.
+// A cache entry holds such a block's counts (48 bits) and, in its top 16
+// bits, the block's index + 1 modulo 2^16 (0: empty); the entry is rewritten
+// at least every second window, so a stale entry never matches.
+constexpr unsigned long long kCountsMask = (1ull << 48) - 1;
+
+__device__ __forceinline__ uint64_t block_counts(uint64_t nl, uint64_t blk, const uint32_t* s_thr, int n_thr,
+                                                 uint64_t seed, uint64_t inst) {
+    const Philox4 p = philox(nl, blk, 0, kTagPoisson, seed, inst);
+    uint64_t packed = 0;
+#pragma unroll
+    for (int sub = 0; sub < 8; ++sub) {
+        const uint64_t word = p.v[sub >> 1];
+        const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+        int kc = 0;
+#pragma unroll
+        for (int h = kMaxThr; h > 0; h >>= 1)
+            if (kc + h <= n_thr && s_thr[kc + h - 1] <= u) kc += h;
+        packed |= (uint64_t)kc << (6 * sub);
+    }
+    return packed;
+}
+
+__device__ __forceinline__ bool kcache_holds(unsigned long long e, uint64_t blk) {
+    return (e >> 48) == ((blk + 1) & 0xFFFFull);
+}
+
+__device__ __forceinline__ unsigned long long kcache_entry(uint64_t blk, uint64_t counts) {
+    return (((blk + 1) & 0xFFFFull) << 48) | (counts & kCountsMask);
+}
+
+// Staged records (gather.hip): u32 words (16-bit record with the bf16
+// weight in the high half) or {record, fp32 weight bits}.
+template <bool WBF16>
+using StagedRec = typename std::conditional<WBF16, uint32_t, uint2>::type;
+
+template <bool WBF16>
+__device__ __forceinline__ void staged_add(const StreamArgs& a, int32_t* ring, StagedRec<WBF16> r, bool use,
+                                           uint32_t row0, uint32_t RT) {
+    uint32_t m;
+    float wv;
+    if constexpr (WBF16) {
+        m = r & 0xFFFFu;
+        wv = __uint_as_float(r & 0xFFFF0000u);
+    } else {
+        m = r.x;
+        wv = __uint_as_float(r.y);
+    }
+    uint32_t x = m + row0;
+    x = min(x, x - RT);
+    // an unused slot adds 0 at ring index 0
+    ring_add(ring, use ? x : 0u, use ? __float2int_rn(wv * a.fxw_scale) : 0);
+}
+
+// The tile's n_st staged records, in any order, each with its ring row
+// relative to the window's first delivered step; every thread takes records
+// tid, tid + bs, ..., kStageU at a time.  Clamped indices keep the loads free
+// of branches (a clamped record adds 0).
+constexpr int kStageU = 8;
+
+template <bool WBF16>
+__device__ __forceinline__ void deliver_staged(const StreamArgs& a, int32_t* ring, uint32_t n_st, int tile,
+                                               int base_slot, uint32_t T, uint32_t RT, int tid, int bs) {
+    const StagedRec<WBF16>* run = static_cast<const StagedRec<WBF16>*>(a.stage) + (size_t)tile * a.stage_cap;
+    const uint32_t row0 = (uint32_t)base_slot * T;
+    for (uint32_t i0 = (uint32_t)tid; i0 < n_st; i0 += kStageU * (uint32_t)bs) {
+        StagedRec<WBF16> r[kStageU];
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) r[u] = run[min(i0 + (uint32_t)(u * bs), n_st - 1)];
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) staged_add<WBF16>(a, ring, r[u], i0 + (uint32_t)(u * bs) < n_st, row0, RT);
+    }
+}
+
 // Short segments (a few synapses each, e.g. two million neurons in tiles of
 // about a thousand) without workgroup-wide staging: every wave takes 64
 // spikes at a time, one per lane.  A lane loads its spike's segment
@@ -116,7 +199,7 @@ template <typename META, bool WBF16>
 __device__ __forceinline__ uint32_t deliver_waves(const StreamArgs& a, int32_t* ring, const uint32_t* s_pc, int nq,
                                                   int64_t q_lo, int64_t n0b, uint64_t offb, int ntb, int tl,
                                                   int base_slot, uint32_t RT, int lane, int wave, int n_waves,
-                                                  uint4* s_wv) {
+                                                  uint4* s_wv, uint32_t k_begin) {
     const uint32_t S = s_pc[nq];
     const uint32_t T = (uint32_t)a.T;
     uint4* my = s_wv + 64 * wave;   // this wave's 64 segment slots
@@ -125,7 +208,7 @@ __device__ __forceinline__ uint32_t deliver_waves(const StreamArgs& a, int32_t* 
     // together before the first round's synapses
     constexpr int D = 4;
     const uint32_t stride = (uint32_t)n_waves * 64u;
-    for (uint32_t kd = (uint32_t)wave * 64u; kd < S; kd += D * stride) {
+    for (uint32_t kd = k_begin + (uint32_t)wave * 64u; kd < S; kd += D * stride) {
         uint32_t len[D], roff[D];
         uint64_t beg[D];
         uint32_t j[D];
@@ -204,7 +287,9 @@ __device__ __forceinline__ uint32_t deliver_waves(const StreamArgs& a, int32_t* 
 }
 
 template <int MODEL, typename META, bool WBF16, int NPT>
-__global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
+// At most 4 waves per SIMD (1024 threads, or 2 x 512, per compute unit and
+// its whole workgroup-local memory): registers for loads in flight are free.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) stream_kernel(StreamArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tid = threadIdx.x, bs = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
@@ -242,45 +327,92 @@ __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
             a.spk_cnt[(size_t)(n & (H - 1)) * a.n_inst + (i % a.n_inst)] = 0u;
         }
     }
+    // The delivered steps' spike counts and the staged run's length (wave
+    // 0) are requested first and used after the input ring is staged.
+    const int64_t q_hi = t0 - a.dmin + wn;
+    const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
+    const int nq = (int)max((int64_t)0, q_hi - q_lo);
+    uint32_t c_q = 0;
+    unsigned long long c_run = 0;
+    if (wave == 0) {
+        c_q = lane < nq ? a.spk_cnt[(size_t)((q_lo + lane) & (H - 1)) * a.n_inst + b] : 0u;
+        if (lane == 0 && a.stage) c_run = a.cursor[tile];
+        if (lane < kMaxThr) s_thr[lane] = lane < a.n_thr ? a.thr[lane] : 0xFFFFFFFFu;
+    }
     // ------------------------------------------------------------ stage in
+    // (kStageIn loads in flight per thread before their stores; no branches,
+    // so that the loads are all issued first: an index past the end is
+    // clamped to the last word, which is then read and written again with its
+    // own value)
     {
+        constexpr int kStageIn = 8;
         const int4* src = reinterpret_cast<const int4*>(a.ring + (size_t)tile * R * T);
         int4* dst = reinterpret_cast<int4*>(ring);
-        for (int i = tid; i < (R * T) / 4; i += bs) dst[i] = src[i];
+        const int n4 = (R * T) / 4;
+        for (int i0 = tid; i0 < n4; i0 += kStageIn * bs) {
+            int4 v[kStageIn];
+#pragma unroll
+            for (int u = 0; u < kStageIn; ++u) v[u] = src[min(i0 + u * bs, n4 - 1)];
+#pragma unroll
+            for (int u = 0; u < kStageIn; ++u) dst[min(i0 + u * bs, n4 - 1)] = v[u];
+        }
         for (int i = ((R * T) & ~3) + tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
     }
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
+    unsigned long long KC[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int li = tid + k * bs;
-        U[k] = Y1[k] = Y2[k] = 0.f;
-        RF[k] = 0;
-        if (li < tsz) {
-            U[k] = a.U[g0 + li];
-            RF[k] = a.r[g0 + li];
-            if (MODEL != CORTEX_MODEL_DELTA) Y1[k] = a.y1[g0 + li];
-            if (MODEL == CORTEX_MODEL_ALPHA) Y2[k] = a.y2[g0 + li];
+        // (a thread past the tile's end reads its last neuron and never uses it)
+        const int64_t gi = g0 + min(tid + k * bs, tsz - 1);
+        U[k] = a.U[gi];
+        RF[k] = a.r[gi];
+        Y1[k] = MODEL != CORTEX_MODEL_DELTA ? a.y1[gi] : 0.f;
+        Y2[k] = MODEL == CORTEX_MODEL_ALPHA ? a.y2[gi] : 0.f;
+        KC[k] = a.kcache[gi];
+    }
+    // Poisson counts of the window's steps, 6 bits per step, before the
+    // delivery (the update below is then only the ring and the membrane).  A
+    // window of at most 8 steps touches at most two 8-step blocks; the block
+    // of a neuron's last step is kept in kcache for the next window, so a
+    // block is drawn once.
+    __syncthreads();   // s_thr
+    uint64_t kcs[NPT];
+    {
+        const uint64_t blk_lo = (uint64_t)(t0 >> 3), blk_hi = (uint64_t)((t0 + wn - 1) >> 3);
+        const int s0 = (int)(t0 & 7);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int li = tid + k * bs;
+            const uint64_t nl = (uint64_t)(g0 - n0b + min(li, tsz - 1));   // instance-local neuron
+            const uint64_t cl = kcache_holds(KC[k], blk_lo)
+                                    ? KC[k] & kCountsMask
+                                    : block_counts(nl, blk_lo, s_thr, a.n_thr, a.seed, (uint64_t)b);
+            const uint64_t ch = blk_hi != blk_lo ? block_counts(nl, blk_hi, s_thr, a.n_thr, a.seed, (uint64_t)b) : cl;
+            // steps s0.. of the first block, then the second block's
+            const uint64_t w = (cl >> (6 * s0)) | (s0 ? ch << (6 * (8 - s0)) : 0ull);
+            kcs[k] = w & ((1ull << (6 * wn)) - 1);
+            const unsigned long long kn = kcache_entry(blk_hi, ch);
+            if (li < tsz && kn != KC[k]) a.kcache[g0 + li] = kn;
+        }
+    }
+    if (wave == 0) {
+        // exclusive prefix s_pc[0..nq] of the delivered steps' spike counts;
+        // the run staged for this window, and its cursor reset for the next
+        const uint32_t incl = wave_incl_scan(c_q);
+        if (lane <= nq) s_pc[lane] = incl - c_q;
+        if (lane == 0 && a.stage) {
+            s_misc[5] = (int)min(c_run, 0xFFFFFFFFull);
+            a.cursor[tile] = 0ull;
         }
     }
     for (int i = tid; i < T; i += bs) s_frz[i] = 0;
-    if (tid < kMaxThr) s_thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xFFFFFFFFu;
     if (tid < kMaxW) s_cnt[tid] = 0;
     if (tid == 0) s_misc[7] = 0;
-    // spikes of the delivered steps [q_lo, q_hi) of this instance
-    const int64_t q_hi = t0 - a.dmin + wn;
-    const int64_t q_lo = max((int64_t)0, t0 - a.dmin);
-    const int nq = (int)max((int64_t)0, q_hi - q_lo);
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int qi = 0; qi < nq; ++qi) {
-            s_pc[qi] = run;
-            run += a.spk_cnt[(size_t)((q_lo + qi) & (H - 1)) * a.n_inst + b];
-        }
-        s_pc[nq] = run;
-    }
-    // frozen spikes of the updated steps (replay)
+    // frozen spikes of the updated steps (replay); the bits are set only
+    // once every thread has cleared its share of them
     if (a.frz_ptr) {
+        __syncthreads();
         for (int si = 0; si < wn; ++si) {
             const int64_t n = t0 + si;
             const size_t at = (size_t)(n - a.frz_step0) * a.n_tiles + tile;
@@ -297,12 +429,23 @@ __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
     const int base_slot = (int)((q_lo + a.dmin) % R);
     uint64_t ev = 0;
     if (a.thread_segments) {
+        uint32_t k_begin = 0, n_staged = 0;
+        if (a.stage) {
+            // a complete run replaces the window's spikes; an incomplete one
+            // (more records than the capacity) is ignored
+            const uint32_t c = (uint32_t)s_misc[5];
+            if (c <= a.stage_cap) {
+                deliver_staged<WBF16>(a, ring, c, tile, base_slot, (uint32_t)T, RT, tid, bs);
+                n_staged = c;
+                k_begin = S;
+            }
+        }
         // the descriptor area holds the waves' segment slots (16 x 64 x 16 B)
         const uint32_t wev = deliver_waves<META, WBF16>(a, ring, s_pc, nq, q_lo, n0b, offb, ntb, tl, base_slot, RT,
-                                                        lane, wave, n_waves, s_sg);
+                                                        lane, wave, n_waves, s_sg, k_begin);
         if (lane == 0) atomicAdd(reinterpret_cast<unsigned int*>(&s_misc[7]), wev);
         __syncthreads();
-        ev = (uint32_t)s_misc[7];
+        ev = (uint64_t)(uint32_t)s_misc[7] + n_staged;
     }
     for (uint32_t c0 = 0; c0 < (a.thread_segments ? 0u : S); c0 += CH) {
         const int cn = (int)min((uint32_t)CH, S - c0);
@@ -337,23 +480,12 @@ __global__ void __launch_bounds__(1024) stream_kernel(StreamArgs a) {
         const int li = tid + k * bs;
         if (li < tsz) {
             const uint32_t frz = s_frz[li];
-            const uint64_t nl = (uint64_t)(g0 - n0b + li);   // instance-local neuron
-            Philox4 pw{};
             int slot = slot0;
             for (int si = 0; si < wn; ++si, slot = (slot + 1 == R) ? 0 : slot + 1) {
                 const int64_t n = t0 + si;
                 const float x = (float)((double)ring[slot * T + li] * a.fx_inv);
                 ring[slot * T + li] = 0;
-                // Poisson count: 32-bit half (n & 1) of word (n & 7) >> 1 of
-                // the block (neuron, n >> 3, 0, Poisson tag)
-                if (si == 0 || (n & 7) == 0)
-                    pw = philox(nl, (uint64_t)(n >> 3), 0, kTagPoisson, a.seed, (uint64_t)b);
-                const uint64_t word = pw.v[(n & 7) >> 1];
-                const uint32_t u = (n & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-                int kc = 0;
-#pragma unroll
-                for (int h = kMaxThr; h > 0; h >>= 1)
-                    if (kc + h <= a.n_thr && s_thr[kc + h - 1] <= u) kc += h;
+                const int kc = (int)((kcs[k] >> (6 * si)) & 63u);
                 const float inp = x + a.w_ext * (float)kc;
                 const bool integ = RF[k] == 0;
                 float u_new;
@@ -495,6 +627,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.U = n->d_U;
     a.y1 = n->d_y1;
     a.y2 = n->d_y2;
+    a.kcache = n->d_kcache;
     a.r = n->d_r;
     a.ring = static_cast<int32_t*>(n->d_ring);
     a.spk_cnt = n->d_spk_cnt;
@@ -514,6 +647,9 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.v_trace = v_trace;
     a.m_trace = m_trace;
     a.trace_step0 = trace_step0;
+    a.stage = n->stage_cap ? n->d_stage : nullptr;
+    a.cursor = n->d_cursor;
+    a.stage_cap = n->stage_cap;
     a.log_step0 = n->log_step0;
     a.log_steps = n->log_steps;
     a.N = n->N;
@@ -550,6 +686,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
 
 static void launch_window(cortex_net* n, StreamFn f, StreamArgs& a, int wn, hipStream_t stream) {
     if (n->stdp) launch_stdp(n, n->clock_parity, wn, stream);   // weights first, then their delivery
+    if (n->stage_cap) launch_gather(n, n->clock_parity, wn, stream);
     a.parity = n->clock_parity;
     a.wn = wn;
     hipLaunchKernelGGL(f, dim3(n->n_tiles), dim3(n->BS), n->lds_bytes, stream, a);
@@ -563,6 +700,7 @@ void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
     StreamFn f = pick_stream(n->spec.model, n->meta_bytes, n->w_bytes, n->NPT);
     require(f != nullptr, CORTEX_EUNSUPPORTED, "no streamed kernel for this record format");
     CX_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)n->lds_bytes));
+    if (n->stage_cap) gather_prepare(n);
     const int64_t first = n->step;
     StreamArgs a = stream_args(n, frz_ids, frz_ptr, frz_n, first, x_trace, v_trace, m_trace, first);
     int64_t left = n_steps;

@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) verify_step_kernel(VerifyArgs a, int64_t 
         if (a.n_thr > 0) {
             const Philox4 p = philox((uint64_t)(i - a.inst_n0[lo]), (uint64_t)(n >> 3), 0, kTagPoisson,
                                      a.seed, (uint64_t)lo);
-            const uint64_t word = p.v[(n & 7) >> 1];
+            const uint64_t word = philox_word(p, (uint32_t)(n & 7) >> 1);
             const uint32_t u = (n & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
             for (int m = 0; m < a.n_thr; ++m) kc += (u >= a.thr[m]) ? 1 : 0;
         }

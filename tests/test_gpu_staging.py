@@ -1,0 +1,58 @@
+"""Tile-major staging of a window's records (streamed plan, short segments)
+against delivery straight from the graph.  The input rings add 32-bit
+fixed-point integers, so the order of the additions does not change the sums:
+a closed-loop run must give the same raster, state and event count bit for
+bit whether every window's records are staged, delivered from the graph, or
+split between the two (a staging capacity below a window's load)."""
+import numpy as np
+import pytest
+
+import netspec
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def cx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_03762_amd as m
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("wdt", ["bf16", "fp32"])
+def test_staged_direct_and_mixed_delivery_give_identical_runs(cx, wdt):
+    # 100,000 neurons with the in-degree of the two-million-neuron network,
+    # tiles of 128: segments of about 14 synapses
+    spec = netspec.brunel_2m_bf16(scale_n=0.05)
+    spec.weight_dtype = wdt
+    chunks = [32 * 5, 3, 32 * 5 + 17, 32 * 5]
+    T = sum(chunks)
+    runs = []
+    for stage in (0, -1, 3000, 64):
+        case(f"{wdt} weights, stage_records={stage}, {T} steps")
+        g = cx.Network(spec, 5, record_steps=T, plan="streamed", tile_size=128, steps_per_sync=5,
+                       stage_records=stage)
+        assert g.query("PLAN") == cx.PLAN_STREAMED
+        staged = g.query("STAGE_RECORDS")
+        assert (staged > 0) == (stage >= 0) and (stage <= 0 or staged == stage)
+        for c in chunks:
+            g.step(c)
+        st, ids = g.spikes(0, T)
+        V, r, _, _ = g.state()
+        runs.append((st, ids, np.asarray(V), np.asarray(r), g.query("EVENTS")))
+        g.close()
+    st, ids = runs[0][0], runs[0][1]
+    rate = len(st) / (spec.n_neurons * T * spec.dt * 1e-3)
+    print("spikes", len(st), "rate", rate, flush=True)
+    assert 1.0 < rate < 50.0
+    for other in runs[1:]:
+        for a, b in zip(runs[0][:4], other[:4]):
+            assert np.array_equal(a, b)
+        assert runs[0][4] == other[4]

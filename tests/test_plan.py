@@ -7,6 +7,7 @@ threads (the launch bound of that kernel variant), including the packing of
 48 batched instances."""
 import itertools
 
+import numpy as np
 import pytest
 
 import netspec
@@ -178,3 +179,23 @@ def test_conductance_plans_are_resident_with_64_bit_rings():
     with pytest.raises(cx.CortexError) as e:
         cx.cortex_plan(big, **MI355X)
     assert e.value.status == cx.EUNSUPPORTED
+
+
+def test_staging_applies_to_one_instance_with_short_segments():
+    big = netspec.brunel_2m_bf16()
+    p = cx.cortex_plan(big, **MI355X)
+    check(p, big)
+    # a window at 50 Hz: K T W dt 50 Hz records per tile, 4-byte records within 4 GiB
+    K, T, W = 11250, p["T"], p["W"]
+    want = -(-int(np.ceil(K * T * W * big.dt * 1e-3 * 50.0)) // 64) * 64
+    assert p["thread_segments"] == 1 and p["stage_records"] == max(4096, want)
+    assert p["stage_records"] * p["tiles"] * 4 <= 4 << 30
+    assert cx.cortex_plan(big, stage_records=-1, **MI355X)["stage_records"] == 0
+    assert cx.cortex_plan(big, stage_records=5000, **MI355X)["stage_records"] == 5000
+    # long segments, or several instances: no staging
+    s50 = netspec.brunel_2m_bf16(scale_n=0.025)
+    assert cx.cortex_plan(s50, plan="streamed", **MI355X)["stage_records"] == 0
+    assert cx.cortex_plan(s50, plan="streamed", tile_size=64, **MI355X)["stage_records"] > 0
+    multi = netspec.batched_brunel([2000, 3000])
+    p = cx.cortex_plan(multi, plan="streamed", tile_size=64, **MI355X)
+    assert p["thread_segments"] == 1 and p["stage_records"] == 0
