@@ -46,7 +46,8 @@ TRAFFIC = {
 
 
 def source_hash(kernel: str) -> str:
-    files = {"step_kernel": ["step.hip", "deliver.hpp"], "stream_kernel": ["stream.hip", "deliver.hpp"]}[kernel]
+    files = {"step_kernel": ["step.hip", "deliver.hpp"], "stream_kernel": ["stream.hip", "deliver.hpp"],
+             "gather_copy_kernel": ["gather.hip"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         h.update(open(os.path.join(CSRC, f), "rb").read())
@@ -72,6 +73,8 @@ def timed_run(net, torch, steps, warmup, sim_steps, name):
         net.step(sim_steps)
         torch.cuda.synchronize()
         log(f"[bench] {name}: warmup {w + 1}/{warmup} done")
+    if net.query("PLAN") == 2:
+        net.kernel_timing(True)   # launches time themselves from here on (sums cleared)
     stream = torch.cuda.current_stream()
     ev0, sp0 = net.query("EVENTS"), net.query("SPIKES")
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -96,26 +99,50 @@ def timed_run(net, torch, steps, warmup, sim_steps, name):
     return out
 
 
-def roofline(net, run, steps, sim_steps):
-    """Roofline of the dominant kernel: algorithmic record bytes of one launch
-    over the launch's average duration (event-timed calls divided by their
-    launches: one persistent launch per call, or one per window)."""
+def roofline(net, run, steps, sim_steps, ktimes=None):
+    """Roofline of the dominant kernel: its algorithmic bytes per launch over
+    its average launch duration.  Resident plan: one persistent launch per
+    call (event-timed calls).  Streamed plan: per window a delivery launch
+    and, when the plan stages records, a staging copy; their mean durations
+    over the timed region are measured by the launches themselves on the
+    device clock (earliest workgroup start to latest workgroup end).
+    Algorithmic bytes: the delivery
+    launch reads each delivered record once (record bytes per event); the
+    copy reads it from the graph and writes it to the tile's run (twice
+    that), and reads one 8-byte descriptor per (delivered spike, tile)."""
     streamed = net.query("PLAN") == 2
-    kernel = "stream_kernel" if streamed else "step_kernel"
     W = net.query("STEPS_PER_SYNC")
     launches = -(-sim_steps // W) if streamed else 1
     B_rec = net.query("EDGE_BYTES")
     events_per_launch = run["events"] / steps / launches
-    avg_launch_s = run["gpu_ms_per_step"] * 1e-3 / launches
-    achieved = events_per_launch * B_rec / avg_launch_s / 1e9
+    spikes_per_launch = run["spikes"] / steps / launches
+    desc_bytes = spikes_per_launch * net.query("TILES") * 8
+    out = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "launches_per_step": launches,
+           "record_bytes": B_rec}
+    if not streamed:
+        kernel, alg, avg_s = "step_kernel", events_per_launch * B_rec, run["gpu_ms_per_step"] * 1e-3
+    else:
+        copy_ms, deliver_ms, nw = ktimes
+        if nw == 0:
+            raise RuntimeError("no per-kernel timing from the window graph")
+        staged = net.query("STAGE_RECORDS") > 0
+        per = {"stream_kernel": (events_per_launch * B_rec, deliver_ms * 1e-3)}
+        if staged:
+            per["gather_copy_kernel"] = (events_per_launch * 2 * B_rec + desc_bytes, copy_ms * 1e-3)
+        kernel = max(per, key=lambda k: per[k][1])
+        alg, avg_s = per[kernel]
+        out["kernels"] = {k: {"algorithmic_bytes_per_launch": b, "avg_launch_ms": t * 1e3,
+                              "achieved_GBps": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS}
+                          for k, (b, t) in per.items()}
+        out["window_ms"] = run["gpu_ms_per_step"] / launches
+        out["timed_windows"] = nw
+    achieved = alg / avg_s / 1e9
     tpe = traffic_per_event(kernel)
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if tpe is None else tpe * events_per_launch,
-            "kernel": kernel, "launches_per_step": launches, "record_bytes": B_rec,
-            "algorithmic_bytes_per_launch": events_per_launch * B_rec,
-            "avg_launch_ms": avg_launch_s * 1e3,
-            "offset_bytes_per_launch": run["spikes"] / steps / launches * net.query("TILES") * 8}
+    out.update({"achieved": achieved, "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None if tpe is None else tpe * events_per_launch, "kernel": kernel,
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3,
+                "descriptor_bytes_per_launch": desc_bytes})
+    return out
 
 
 def cpu_baseline(spec, rate_hz, seed, n_targets, n_steps):
@@ -422,8 +449,10 @@ def main():
         log(f"[bench] calibration copy of {nb} bytes done")
         del src, dst
 
+    streamed = net.query("PLAN") == 2
     run = timed_run(net, torch, args.steps, args.warmup, args.sim_steps, "headline")
-    roof = roofline(net, run, args.steps, args.sim_steps)
+    ktimes = net.kernel_times() if streamed else None
+    roof = roofline(net, run, args.steps, args.sim_steps, ktimes)
     rec = "16-bit record + bf16 weight" if spec.weight_dtype == "bf16" else "16-bit record + fp32 weight"
     cfg = {
         "workload": (f"balanced random net, {spec.model}-current LIF, {spec.n_neurons:,} neurons "

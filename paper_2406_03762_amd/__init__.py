@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
         L.cortex_export_canonical.argtypes = [P, P]
         L.cortex_export_tiles.argtypes = [P, P, P, P]
         L.cortex_query.argtypes = [P, C.c_int, C.POINTER(i64)]
+        L.cortex_kernel_timing.argtypes = [P, C.c_int]
+        L.cortex_kernel_times.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.cortex_destroy.argtypes = [P]
         L.cortex_destroy.restype = None
         _lib = L
@@ -258,6 +260,20 @@ def cortex_step(h, n_steps: int) -> None:
     _check(lib().cortex_step(h, n_steps))
 
 
+def cortex_kernel_timing(h, on: bool = True) -> None:
+    """Streamed plan: record per-kernel HIP events in the window graph."""
+    _check(lib().cortex_kernel_timing(h, int(on)))
+
+
+def cortex_kernel_times(h):
+    """(staging copy ms, delivery launch ms, windows averaged) of the window
+    graph's last replay."""
+    ms = (C.c_double * 2)()
+    nw = C.c_int32()
+    _check(lib().cortex_kernel_times(h, ms, C.byref(nw)))
+    return ms[0], ms[1], nw.value
+
+
 def cortex_query(h, what: str) -> int:
     v = C.c_int64()
     _check(lib().cortex_query(h, Q[what], C.byref(v)))
@@ -410,6 +426,12 @@ class Network:
 
     def query(self, what: str) -> int:
         return cortex_query(self._h, what)
+
+    def kernel_timing(self, on: bool = True) -> None:
+        cortex_kernel_timing(self._h, on)
+
+    def kernel_times(self):
+        return cortex_kernel_times(self._h)
 
     def step(self, n_steps: int) -> None:
         cortex_step(self._h, n_steps)

@@ -51,6 +51,7 @@ struct GatherArgs {
     int64_t N;
     uint32_t cap, T;
     int parity, wn, H, dmin, ntb;
+    KernelTime* ktime;          // launch timing (null: off)
 };
 
 struct CopyLds {
@@ -78,6 +79,7 @@ struct CopyLds {
 template <bool WBF16, typename META>
 __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(8))) gather_copy_kernel(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const unsigned long long t_begin = wall_clock64();
     CopyLds& s = *reinterpret_cast<CopyLds*>(lds_raw);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the window's delivered steps and the prefix of their spike counts
@@ -206,6 +208,7 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
             }
         }
     }
+    if (a.ktime) ktime_end(a.ktime, t_begin, gridDim.x);
 }
 
 void (*copy_kernel(const cortex_net* n))(GatherArgs) {
@@ -240,6 +243,7 @@ void launch_gather(cortex_net* n, int parity, int wn, hipStream_t stream) {
     a.H = n->H;
     a.dmin = n->dmin;
     a.ntb = n->n_tiles;
+    a.ktime = n->ktiming ? n->d_ktime : nullptr;
     hipLaunchKernelGGL(copy_kernel(n), dim3(kGatherGrid), dim3(kGThreads), sizeof(CopyLds), stream, a);
     CX_HIP(hipGetLastError());
 }

@@ -68,6 +68,16 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Live timing of a kernel's launches by the kernel itself (constant-rate
+// device clock): every workgroup folds its start and end into the launch's
+// earliest start and latest end; the last workgroup to finish adds the
+// launch's span to `sum`, counts it, and resets the extremes for the next
+// launch (launches on one stream do not overlap).
+struct KernelTime {
+    unsigned long long start, end, sum, count;
+    unsigned int done, pad;
+};
+
 // What the planner needs to know of the device: compute units, LDS bytes and
 // resident threads per compute unit, and whether kernel occupancy can be
 // asked of the runtime (a live device) or must be estimated from LDS and
@@ -188,7 +198,12 @@ struct cortex_net {
     hipGraphExec_t graph_exec = nullptr;   // kGraphWindows window launches
     hipStream_t graph_stream = nullptr;    // library stream the graph is captured on and replayed on
     hipEvent_t fence_in = nullptr, fence_out = nullptr;   // order it after / before the caller's stream
+    // per-kernel timing of the window launches (cortex_kernel_timing):
+    // [0] staging copy, [1] delivery launch
+    bool ktiming = false;
+    cortex::KernelTime* d_ktime = nullptr;
     int64_t graph_log_step0 = -1, graph_log_steps = -1;
+    bool graph_ktiming = false;
     // initial state copy (reset / adjoint)
     float *d_U0 = nullptr;
     // FP64 verify graph and state
@@ -267,6 +282,26 @@ void republish(cortex_net* n, int64_t q0, int64_t q1, const uint32_t* ids, const
 size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_bytes);
 // stream.hip: window launches of the streamed plan
 constexpr int kGraphWindows = 32;
+
+
+__device__ inline void ktime_end(KernelTime* kt, unsigned long long t_begin, unsigned int n_wg) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t_end = wall_clock64();
+        atomicMin(&kt->start, t_begin);
+        atomicMax(&kt->end, t_end);
+        __threadfence();
+        if (atomicAdd(&kt->done, 1u) == n_wg - 1) {
+            __threadfence();
+            const unsigned long long s = atomicAdd(&kt->start, 0ull), e = atomicAdd(&kt->end, 0ull);
+            atomicAdd(&kt->sum, e - s);
+            atomicAdd(&kt->count, 1ull);
+            atomicExch(&kt->start, ~0ull);
+            atomicExch(&kt->end, 0ull);
+            atomicExch(&kt->done, 0u);
+        }
+    }
+}
 constexpr int kHistLen = 32;   // postsynaptic spikes a neuron keeps for plasticity   // window launches per captured graph (even)
 size_t stream_lds_bytes(int R, int T, int W, int chunk);
 int stream_occupancy(int model, int meta_bytes, int w_bytes, int npt, int bs, size_t lds);

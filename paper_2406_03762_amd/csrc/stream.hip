@@ -76,6 +76,7 @@ struct StreamArgs {
     int64_t trace_step0;
     const void* stage;             // staged records [n_tiles][stage_cap] (null: no staging)
     unsigned long long* cursor;    // [n_tiles] records staged for this window (reset here)
+    KernelTime* ktime;             // launch timing (null: off)
     uint32_t stage_cap;
     int64_t log_step0, log_steps, N;
     int parity, wn;
@@ -291,6 +292,7 @@ template <int MODEL, typename META, bool WBF16, int NPT>
 // its whole workgroup-local memory): registers for loads in flight are free.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) stream_kernel(StreamArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const unsigned long long t_begin = wall_clock64();
     const int tid = threadIdx.x, bs = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
     const int tile = a.order[blockIdx.x];
@@ -567,6 +569,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         a.spikes[tile] += nspk;
         a.log_pos[tile] = log_pos;
     }
+    if (a.ktime) ktime_end(a.ktime, t_begin, gridDim.x);
 }
 
 using StreamFn = void (*)(StreamArgs);
@@ -650,6 +653,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.stage = n->stage_cap ? n->d_stage : nullptr;
     a.cursor = n->d_cursor;
     a.stage_cap = n->stage_cap;
+    a.ktime = n->ktiming ? n->d_ktime + 1 : nullptr;
     a.log_step0 = n->log_step0;
     a.log_steps = n->log_steps;
     a.N = n->N;
@@ -684,6 +688,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     return a;
 }
 
+// One window: plasticity, staging copy, delivery launch.
 static void launch_window(cortex_net* n, StreamFn f, StreamArgs& a, int wn, hipStream_t stream) {
     if (n->stdp) launch_stdp(n, n->clock_parity, wn, stream);   // weights first, then their delivery
     if (n->stage_cap) launch_gather(n, n->clock_parity, wn, stream);
@@ -724,7 +729,8 @@ void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                 CX_HIP(hipEventCreateWithFlags(&n->fence_in, hipEventDisableTiming));
                 CX_HIP(hipEventCreateWithFlags(&n->fence_out, hipEventDisableTiming));
             }
-            if (!n->graph_exec || n->graph_log_step0 != n->log_step0 || n->graph_log_steps != n->log_steps) {
+            if (!n->graph_exec || n->graph_log_step0 != n->log_step0 || n->graph_log_steps != n->log_steps ||
+                n->graph_ktiming != n->ktiming) {
                 if (n->graph_exec) {
                     CX_HIP(hipStreamSynchronize(n->graph_stream));
                     CX_HIP(hipGraphExecDestroy(n->graph_exec));
@@ -740,6 +746,7 @@ void launch_stream_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                 CX_HIP(hipGraphDestroy(g));
                 n->graph_log_step0 = n->log_step0;
                 n->graph_log_steps = n->log_steps;
+                n->graph_ktiming = n->ktiming;
             }
             CX_HIP(hipEventRecord(n->fence_in, n->stream));
             CX_HIP(hipStreamWaitEvent(n->graph_stream, n->fence_in, 0));

@@ -23,7 +23,7 @@ def main() -> None:
     import paper_2406_03762_amd as cx
 
     workloads = {
-        "brunel_2m_bf16": (netspec.brunel_2m_bf16, 5, 1000, 100),
+        "brunel_2m_bf16": (netspec.brunel_2m_bf16, 5, 2000, 2000),
         "brunel_112k_alpha": (netspec.brunel_112k_alpha, 2, 4000, 500),
         "microcircuit_77k": (netspec.microcircuit_77k, 3, 4000, 500),
         "batched_64": (netspec.batched_brunel, 4, 2000, 200),

@@ -93,6 +93,8 @@ def test_null_handles_return_einval(L):
     v = C.c_int64()
     assert L.cortex_step(None, 1) == cx.EINVAL
     assert L.cortex_query(None, 0, C.byref(v)) == cx.EINVAL
+    assert L.cortex_kernel_timing(None, 1) == cx.EINVAL
+    assert L.cortex_kernel_times(None, None, None) == cx.EINVAL
     assert L.cortex_reset(None) == cx.EINVAL
     assert L.cortex_get_spikes(None, 0, 1, None, None, 0, C.byref(v)) == cx.EINVAL
     assert L.cortex_backward(None, None, None, None) == cx.EINVAL

@@ -56,3 +56,24 @@ def test_staged_direct_and_mixed_delivery_give_identical_runs(cx, wdt):
         for a, b in zip(runs[0][:4], other[:4]):
             assert np.array_equal(a, b)
         assert runs[0][4] == other[4]
+
+
+def test_kernel_timing_reports_both_launches_and_changes_nothing(cx):
+    spec = netspec.brunel_2m_bf16(scale_n=0.05)
+    T = 32 * 5 * 2
+    runs = []
+    for timing in (False, True):
+        case(f"kernel timing {'on' if timing else 'off'}")
+        g = cx.Network(spec, 5, record_steps=T, plan="streamed", tile_size=128, steps_per_sync=5)
+        if timing:
+            g.kernel_timing(True)
+        g.step(T)
+        st, ids = g.spikes(0, T)
+        if timing:
+            copy_ms, deliver_ms, nw = g.kernel_times()
+            print("copy", copy_ms, "deliver", deliver_ms, flush=True)
+            assert nw == T // 5 and copy_ms > 0 and deliver_ms > 0
+        runs.append((st, ids, g.query("EVENTS")))
+        g.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]
