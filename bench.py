@@ -36,12 +36,15 @@ CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
 # size, as the summaries under profiles/ state), valid only for the sources
 # they were measured on: {kernel: (bytes per event, source hash)}.
 TRAFFIC = {
-    # 112,500-neuron alpha net, one 1000-step launch: (3.2983e6 KiB x 2.0
-    # + 2.0457e5 KiB x 1.0) x 1024 / 9.708e8 events
-    "step_kernel": (7.174, "d0432f40e622e854"),
-    # two-million-neuron bf16 net, launches 10-199 of a 1000-step run:
-    # (1.5260e6 KiB x 2.0 + 3.1359e5 KiB x 1.0) x 1024 / 8.5245e7 events
-    "stream_kernel": (40.43, "277e5d087d96aaa2"),
+    # 112,500-neuron alpha net, one 1000-step launch: (3.3021e6 KiB x 2.0
+    # + 2.0456e5 KiB x 1.0) x 1024 / 9.708e8 events
+    "step_kernel": (7.182, "2a1f56a6bb60aa11"),
+    # two-million-neuron bf16 net, launches 10-199 of a 1000-step run,
+    # 8.5245e7 events per launch: delivery (2.8468e5 KiB x 2.0 + 2.6023e5
+    # KiB x 1.0) x 1024, staging copy (2.5556e5 KiB x 2.0 + 5.6665e5 KiB x
+    # 1.0) x 1024
+    "stream_kernel": (9.965, "abe03b8332f934a5"),
+    "gather_copy_kernel": (12.946, "25a2e02e59047d78"),
 }
 
 
@@ -105,7 +108,8 @@ def roofline(net, run, steps, sim_steps, ktimes=None):
     call (event-timed calls).  Streamed plan: per window a delivery launch
     and, when the plan stages records, a staging copy; their mean durations
     over the timed region are measured by the launches themselves on the
-    device clock (earliest workgroup start to latest workgroup end).
+    device clock (from a launch's start to the next launch's: its duration
+    and the gap before the next).
     Algorithmic bytes: the delivery
     launch reads each delivered record once (record bytes per event); the
     copy reads it from the graph and writes it to the tile's run (twice
@@ -131,9 +135,12 @@ def roofline(net, run, steps, sim_steps, ktimes=None):
             per["gather_copy_kernel"] = (events_per_launch * 2 * B_rec + desc_bytes, copy_ms * 1e-3)
         kernel = max(per, key=lambda k: per[k][1])
         alg, avg_s = per[kernel]
-        out["kernels"] = {k: {"algorithmic_bytes_per_launch": b, "avg_launch_ms": t * 1e3,
-                              "achieved_GBps": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS}
-                          for k, (b, t) in per.items()}
+        out["kernels"] = {}
+        for k, (b, t) in per.items():
+            tk = traffic_per_event(k)
+            out["kernels"][k] = {"algorithmic_bytes_per_launch": b, "avg_launch_ms": t * 1e3,
+                                 "achieved_GBps": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS,
+                                 "traffic": None if tk is None else tk * events_per_launch}
         out["window_ms"] = run["gpu_ms_per_step"] / launches
         out["timed_windows"] = nw
     achieved = alg / avg_s / 1e9

@@ -355,13 +355,15 @@ int cortex_query(cortex_net* net, int what, int64_t* value);
 /* Passage: none (measurement of the kernels of Sec. III-B's delivery).
    FP32 streamed plan: live timing of the window launches.  on != 0 clears
    the sums and makes the staging copy (if the plan stages) and the delivery
-   launch of every window time themselves on the device clock (each launch's
-   span from its earliest workgroup start to its latest workgroup end); on ==
-   0 stops it.  cortex_kernel_times synchronises and writes the mean launch
-   duration in milliseconds since the last cortex_kernel_timing(net, 1) of
-   the staging copy (0 without staging) into ms[0] and of the delivery launch
-   into ms[1]; *n_windows = the delivery launches timed.  Errors:
-   EUNSUPPORTED (not a streamed FP32 network), EINVAL (NULL). */
+   launch of every window stamp the device clock as they start (one thread
+   each); the interval from a launch's stamp to the next launch's is its
+   duration plus the gap before the next one.  on == 0 stops it.
+   cortex_kernel_times synchronises and writes the mean interval in
+   milliseconds since the last cortex_kernel_timing(net, 1) of the staging
+   copy (0 without staging) into ms[0] and of the delivery launch into ms[1]
+   (which includes a plasticity pass, if any); *n_windows = the delivery
+   launches counted.  Errors: EUNSUPPORTED (not a streamed FP32 network),
+   EINVAL (NULL). */
 int cortex_kernel_timing(cortex_net* net, int on);
 int cortex_kernel_times(cortex_net* net, double* ms, int32_t* n_windows);
 

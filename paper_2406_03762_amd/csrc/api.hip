@@ -1561,11 +1561,11 @@ int cortex_kernel_timing(cortex_net* n, int on) {
     require(n != nullptr, CORTEX_EINVAL, "null network");
     require(n->spec.precision == CORTEX_FP32 && n->plan_kind == CORTEX_PLAN_STREAMED, CORTEX_EUNSUPPORTED,
             "kernel timing is for the streamed FP32 plan");
-    if (on && !n->d_ktime) n->d_ktime = dev_alloc_t<KernelTime>(n, 2);
+    if (on && !n->d_ktime) n->d_ktime = dev_alloc_t<KernelTime>(n, 1);
     if (on) {
-        // sums cleared, extremes at their identities
-        const KernelTime init[2] = {{~0ull, 0, 0, 0, 0, 0}, {~0ull, 0, 0, 0, 0, 0}};
-        CX_HIP(hipMemcpyAsync(n->d_ktime, init, sizeof init, hipMemcpyHostToDevice, n->stream));
+        // sums cleared, no open interval
+        const KernelTime init{};
+        CX_HIP(hipMemcpyAsync(n->d_ktime, &init, sizeof init, hipMemcpyHostToDevice, n->stream));
         CX_HIP(hipStreamSynchronize(n->stream));
     }
     if ((on != 0) != n->ktiming) {
@@ -1586,14 +1586,14 @@ int cortex_kernel_times(cortex_net* n, double* ms, int32_t* n_windows) {
     if (!n->ktiming || !n->d_ktime) return CORTEX_OK;
     CX_HIP(hipStreamSynchronize(n->stream));
     if (n->graph_stream) CX_HIP(hipStreamSynchronize(n->graph_stream));
-    KernelTime kt[2];
-    CX_HIP(hipMemcpy(kt, n->d_ktime, sizeof kt, hipMemcpyDeviceToHost));
+    KernelTime kt{};
+    CX_HIP(hipMemcpy(&kt, n->d_ktime, sizeof kt, hipMemcpyDeviceToHost));
     int rate_khz = 0;
     CX_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, n->device));
     require(rate_khz > 0, CORTEX_EDEVICE, "device clock rate unknown");
     for (int k = 0; k < 2; ++k)
-        ms[k] = kt[k].count ? (double)kt[k].sum / (double)kt[k].count / (double)rate_khz : 0.0;
-    *n_windows = (int32_t)std::min<unsigned long long>(kt[1].count, 0x7FFFFFFF);
+        ms[k] = kt.count[k] ? (double)kt.sum[k] / (double)kt.count[k] / (double)rate_khz : 0.0;
+    *n_windows = (int32_t)std::min<unsigned long long>(kt.count[1], 0x7FFFFFFF);
     return CORTEX_OK;
     CX_API_END
 }

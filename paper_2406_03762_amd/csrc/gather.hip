@@ -79,7 +79,7 @@ struct CopyLds {
 template <bool WBF16, typename META>
 __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(8))) gather_copy_kernel(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const unsigned long long t_begin = wall_clock64();
+    if (a.ktime) ktime_mark(a.ktime, 0);
     CopyLds& s = *reinterpret_cast<CopyLds*>(lds_raw);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the window's delivered steps and the prefix of their spike counts
@@ -208,7 +208,6 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
             }
         }
     }
-    if (a.ktime) ktime_end(a.ktime, t_begin, gridDim.x);
 }
 
 void (*copy_kernel(const cortex_net* n))(GatherArgs) {

@@ -68,16 +68,18 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-// Live timing of a kernel's launches by the kernel itself (constant-rate
-// device clock): every workgroup folds its start and end into the launch's
-// earliest start and latest end; the last workgroup to finish adds the
-// launch's span to `sum`, counts it, and resets the extremes for the next
-// launch (launches on one stream do not overlap).
+// Live timing of the window launches by the launches themselves (constant-
+// rate device clock): thread 0 of workgroup 0 of each timed launch (the
+// first dispatched) reads the clock at its start, which closes the previous
+// timed launch's interval on the same stream; launches on one stream run one
+// after another, so an interval is the launch's duration and the gap to the
+// next launch.  One thread per launch: no contention.
 struct KernelTime {
-    unsigned long long start, end, sum, count;
-    unsigned int done, pad;
+    unsigned long long last_t;     // start of the last timed launch (0: none yet)
+    unsigned long long sum[2];     // summed intervals: [0] staging copy, [1] delivery launch
+    unsigned long long count[2];
+    int last_kind, pad;
 };
-
 // What the planner needs to know of the device: compute units, LDS bytes and
 // resident threads per compute unit, and whether kernel occupancy can be
 // asked of the runtime (a live device) or must be estimated from LDS and
@@ -284,23 +286,16 @@ size_t step_lds_bytes(int R, int T, int W, int ntiles_max, int chunk, int ring_b
 constexpr int kGraphWindows = 32;
 
 
-__device__ inline void ktime_end(KernelTime* kt, unsigned long long t_begin, unsigned int n_wg) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned long long t_end = wall_clock64();
-        atomicMin(&kt->start, t_begin);
-        atomicMax(&kt->end, t_end);
-        __threadfence();
-        if (atomicAdd(&kt->done, 1u) == n_wg - 1) {
-            __threadfence();
-            const unsigned long long s = atomicAdd(&kt->start, 0ull), e = atomicAdd(&kt->end, 0ull);
-            atomicAdd(&kt->sum, e - s);
-            atomicAdd(&kt->count, 1ull);
-            atomicExch(&kt->start, ~0ull);
-            atomicExch(&kt->end, 0ull);
-            atomicExch(&kt->done, 0u);
-        }
+__device__ inline void ktime_mark(KernelTime* kt, int kind) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const unsigned long long t = wall_clock64();
+    const unsigned long long p = kt->last_t;
+    if (p != 0) {
+        kt->sum[kt->last_kind] += t - p;
+        kt->count[kt->last_kind] += 1;
     }
+    kt->last_t = t;
+    kt->last_kind = kind;
 }
 constexpr int kHistLen = 32;   // postsynaptic spikes a neuron keeps for plasticity   // window launches per captured graph (even)
 size_t stream_lds_bytes(int R, int T, int W, int chunk);

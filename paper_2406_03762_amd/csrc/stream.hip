@@ -292,7 +292,7 @@ template <int MODEL, typename META, bool WBF16, int NPT>
 // its whole workgroup-local memory): registers for loads in flight are free.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) stream_kernel(StreamArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const unsigned long long t_begin = wall_clock64();
+    if (a.ktime) ktime_mark(a.ktime, 1);
     const int tid = threadIdx.x, bs = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = bs >> 6;
     const int tile = a.order[blockIdx.x];
@@ -569,7 +569,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         a.spikes[tile] += nspk;
         a.log_pos[tile] = log_pos;
     }
-    if (a.ktime) ktime_end(a.ktime, t_begin, gridDim.x);
 }
 
 using StreamFn = void (*)(StreamArgs);
@@ -653,7 +652,7 @@ static StreamArgs stream_args(cortex_net* n, const uint32_t* frz_ids, const uint
     a.stage = n->stage_cap ? n->d_stage : nullptr;
     a.cursor = n->d_cursor;
     a.stage_cap = n->stage_cap;
-    a.ktime = n->ktiming ? n->d_ktime + 1 : nullptr;
+    a.ktime = n->ktiming ? n->d_ktime : nullptr;
     a.log_step0 = n->log_step0;
     a.log_steps = n->log_steps;
     a.N = n->N;
