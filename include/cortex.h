@@ -344,7 +344,8 @@ enum {
     CORTEX_Q_RING_BYTES = 16,     /* FP32: bytes of one input-ring element (8: 64-bit, 4: 32-bit sums) */
     CORTEX_Q_PLAN = 17,           /* FP32: CORTEX_PLAN_RESIDENT or CORTEX_PLAN_STREAMED */
     CORTEX_Q_NPT = 18,            /* FP32: neurons per thread */
-    CORTEX_Q_STAGE_RECORDS = 19   /* FP32 streamed: records per tile staged per window (0: none) */
+    CORTEX_Q_STAGE_RECORDS = 19,  /* FP32 streamed: records per tile staged per window (0: none) */
+    CORTEX_Q_STAGE_GROUP = 20     /* FP32 streamed with staging: tiles per copy work item (0: no staging) */
 };
 /* Passage: the sizes of G (Sec. II-A) and of its decomposition (Eq. 9-10);
    EVENTS counts the edges of the spiking sub-graphs (Eq. 11) delivered.

@@ -22,7 +22,8 @@ ABI_VERSION = 4
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ETIMEOUT, ETRUNC = 0, -1, -2, -3, -4, -5, -6, -7
 Q = dict(NEURONS=0, SYNAPSES=1, MIN_DELAY=2, MAX_DELAY=3, TILES=4, TILE_SIZE=5, RING_SLOTS=6,
          STEP=7, EVENTS=8, SPIKES=9, DEVICE_BYTES=10, EDGE_BYTES=11, BLOCK_SIZE=12, LDS_BYTES=13,
-         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16, PLAN=17, NPT=18, STAGE_RECORDS=19)
+         OFFSET_BYTES=14, STEPS_PER_SYNC=15, RING_BYTES=16, PLAN=17, NPT=18, STAGE_RECORDS=19,
+         STAGE_GROUP=20)
 PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAMED = 0, 1, 2
 _PLAN = {"auto": PLAN_AUTO, "resident": PLAN_RESIDENT, "streamed": PLAN_STREAMED}
 

@@ -650,6 +650,12 @@ static void plan_stream(cortex_net* n) {
             cap = std::max<uint64_t>(4096, ((uint64_t)std::ceil(per) + 63) & ~63ull);
         }
         n->stage_cap = (uint32_t)std::min(cap, lim);
+        // tiles per copy work item: the records of 64 spikes into the
+        // group fit the copy's workgroup-local buffer with room to spare
+        n->stage_group = 16;
+        while (n->stage_group > 1 &&
+               64.0 * n->stage_group * seg * 1.15 > (double)gather_out_records((int)rec))
+            n->stage_group /= 2;
     }
     std::vector<double> load(n->n_tiles);
     for (int t = 0; t < n->n_tiles; ++t) load[t] = K[n->tile_inst[t]] * n->tile_size[t];
@@ -727,6 +733,8 @@ static std::string plan_violation(const cortex_net* n) {
             // a staged record's ring row relative to the window, meta + qi T,
             // stays below R T (and 2^16 with 16-bit records)
             need(n->stage_cap >= 1 && n->stage_cap < 0x80000000u, "staging capacity");
+            need(n->stage_group >= 1 && n->stage_group <= 16 && (n->stage_group & (n->stage_group - 1)) == 0,
+                 "tiles per copy work item");
         }
     } else {
         need(n->lds_bytes == step_lds_bytes(n->R, n->T, n->W, n->ntb_max, n->chunk, n->ring_bytes),
@@ -1535,6 +1543,7 @@ int cortex_query(cortex_net* n, int what, int64_t* value) {
         case CORTEX_Q_PLAN: *value = fp64 ? 0 : n->plan_kind; break;
         case CORTEX_Q_NPT: *value = fp64 ? 0 : n->NPT; break;
         case CORTEX_Q_STAGE_RECORDS: *value = fp64 ? 0 : (int64_t)n->stage_cap; break;
+        case CORTEX_Q_STAGE_GROUP: *value = (fp64 || !n->stage_cap) ? 0 : (int64_t)n->stage_group; break;
         case CORTEX_Q_EVENTS:
         case CORTEX_Q_SPIKES: {
             require(!n->failed, CORTEX_ESTATE, "network failed earlier");

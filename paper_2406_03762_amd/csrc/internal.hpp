@@ -180,6 +180,7 @@ struct cortex_net {
     // tile-major staging of each window's records (streamed plan, short
     // segments, one instance): records per tile (0: no staging)
     uint32_t stage_cap = 0;
+    int stage_group = 16;                    // tiles per copy work item (a power of two, at most 16)
     void* d_stage = nullptr;                 // [n_tiles][stage_cap] records
     unsigned long long* d_cursor = nullptr;  // [n_tiles] records staged for the coming delivery
     unsigned long long* d_kcache = nullptr;  // streamed plan, [N]: Poisson counts of one 8-step block
@@ -274,6 +275,8 @@ void check_plastic_raster(const cortex_net* n, const uint32_t* st, const uint32_
 void launch_stdp(cortex_net* n, int parity, int wn, hipStream_t stream);
 void launch_gather(cortex_net* n, int parity, int wn, hipStream_t stream);
 void gather_prepare(cortex_net* n);
+// records of rec_bytes each that one copy work item can hold in workgroup-local memory
+int gather_out_records(int rec_bytes);
 void launch_step_fp32(cortex_net* n, int64_t n_steps, const uint32_t* frz_ids,
                       const uint64_t* frz_ptr, uint64_t frz_n, float* x_trace, float* v_trace,
                       uint8_t* m_trace = nullptr);
