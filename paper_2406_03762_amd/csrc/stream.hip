@@ -342,23 +342,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         if (lane < kMaxThr) s_thr[lane] = lane < a.n_thr ? a.thr[lane] : 0xFFFFFFFFu;
     }
     // ------------------------------------------------------------ stage in
-    // (kStageIn loads in flight per thread before their stores; no branches,
-    // so that the loads are all issued first: an index past the end is
-    // clamped to the last word, which is then read and written again with its
-    // own value)
+    // Only the rows that can hold sums: the spikes delivered before this
+    // window were emitted before t0 - dmin and arrive before
+    // t0 + dmax - dmin, so the rows of arrival steps t0 .. t0 + nin - 1
+    // (nin = dmax - dmin = R - W) are loaded and the other W rows start at
+    // zero (their stored contents are stale: consumed rows are not written
+    // back).  kStageIn loads in flight per thread before their stores; no
+    // branches, so that the loads are all issued first: an index past the
+    // end is clamped to the last piece, which is then read and written
+    // again with its own value.
+    const int T4 = T / 4, RT4 = R * T4;   // 16-byte pieces (T is a multiple of 4)
+    const int nin4 = (R - a.W) * T4;
     {
         constexpr int kStageIn = 8;
         const int4* src = reinterpret_cast<const int4*>(a.ring + (size_t)tile * R * T);
         int4* dst = reinterpret_cast<int4*>(ring);
-        const int n4 = (R * T) / 4;
-        for (int i0 = tid; i0 < n4; i0 += kStageIn * bs) {
+        const int p0 = (int)(t0 % R) * T4;
+        for (int i0 = tid; i0 < nin4; i0 += kStageIn * bs) {
             int4 v[kStageIn];
+            int at[kStageIn];
 #pragma unroll
-            for (int u = 0; u < kStageIn; ++u) v[u] = src[min(i0 + u * bs, n4 - 1)];
+            for (int u = 0; u < kStageIn; ++u) {
+                const int p = p0 + min(i0 + u * bs, nin4 - 1);
+                at[u] = p >= RT4 ? p - RT4 : p;
+                v[u] = src[at[u]];
+            }
 #pragma unroll
-            for (int u = 0; u < kStageIn; ++u) dst[min(i0 + u * bs, n4 - 1)] = v[u];
+            for (int u = 0; u < kStageIn; ++u) dst[at[u]] = v[u];
         }
-        for (int i = ((R * T) & ~3) + tid; i < R * T; i += bs) ring[i] = a.ring[(size_t)tile * R * T + i];
+        const int z0 = (int)((t0 + (R - a.W)) % R) * T4;
+        for (int i = tid; i < RT4 - nin4; i += bs) {
+            const int p = z0 + i;
+            dst[p >= RT4 ? p - RT4 : p] = make_int4(0, 0, 0, 0);
+        }
     }
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
@@ -558,11 +574,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         nspk += c;
     }
     // ------------------------------------------------------------ stage out
+    // the rows the next window loads: arrival steps t0 + wn .. t0 + wn + nin - 1
     {
         int4* dst = reinterpret_cast<int4*>(a.ring + (size_t)tile * R * T);
         const int4* src = reinterpret_cast<const int4*>(ring);
-        for (int i = tid; i < (R * T) / 4; i += bs) dst[i] = src[i];
-        for (int i = ((R * T) & ~3) + tid; i < R * T; i += bs) a.ring[(size_t)tile * R * T + i] = ring[i];
+        const int p0 = (int)((t0 + wn) % R) * T4;
+        for (int i = tid; i < nin4; i += bs) {
+            const int p = p0 + i;
+            const int q = p >= RT4 ? p - RT4 : p;
+            dst[q] = src[q];
+        }
     }
     if (tid == 0) {
         a.events[tile] += ev;
