@@ -165,8 +165,9 @@ typedef struct {
        a window copies from the graph into a tile-major run before its
        delivery (every record line then read once, instead of a line per
        spike and tile).  0 = automatic (a window at 50 Hz, the buffer within
-       4 GiB), < 0 = no staging.  A window with more records for a tile
-       delivers the excess straight from the graph; the sums are the same. */
+       4 GiB), < 0 = no staging; a requested count is rounded up to a
+       multiple of 4.  A window with more records for a tile delivers the
+       excess straight from the graph; the sums are the same. */
     int64_t stage_records;
 } cortex_spec;
 

@@ -643,8 +643,11 @@ static void plan_stream(cortex_net* n) {
     n->stage_cap = 0;
     if (n->thread_segments && n->n_inst == 1 && s.stage_records >= 0) {
         const uint64_t rec = (s.weight_dtype == CORTEX_W_BF16) ? 4 : 8;
-        const uint64_t lim = std::min<uint64_t>((4ull << 30) / ((uint64_t)n->n_tiles * rec), 0x7FFFFFFFull);
-        uint64_t cap = (uint64_t)s.stage_records;
+        // (a multiple of 4 records, so that every tile's run starts
+        // 16-byte aligned for the delivery launch's 16-byte loads)
+        const uint64_t lim =
+            std::min<uint64_t>((4ull << 30) / ((uint64_t)n->n_tiles * rec), 0x7FFFFFFFull) & ~3ull;
+        uint64_t cap = ((uint64_t)s.stage_records + 3) & ~3ull;
         if (cap == 0) {
             const double per = K[0] * (double)Tb[0] * (double)n->W * s.dt * 1e-3 * 50.0;
             cap = std::max<uint64_t>(4096, ((uint64_t)std::ceil(per) + 63) & ~63ull);
@@ -732,7 +735,7 @@ static std::string plan_violation(const cortex_net* n) {
             need(n->W <= 8, "staging window");
             // a staged record's ring row relative to the window, meta + qi T,
             // stays below R T (and 2^16 with 16-bit records)
-            need(n->stage_cap >= 1 && n->stage_cap < 0x80000000u, "staging capacity");
+            need(n->stage_cap >= 4 && n->stage_cap < 0x80000000u && n->stage_cap % 4 == 0, "staging capacity");
             need(n->stage_group >= 1 && n->stage_group <= 16 && (n->stage_group & (n->stage_group - 1)) == 0,
                  "tiles per copy work item");
         }

@@ -38,8 +38,6 @@ constexpr int kGTiles = 16;     // at most this many tiles per work item
 constexpr int kGMaxQ = 8;       // delivered steps per window
 constexpr int kGThreads = 512;  // threads per workgroup
 constexpr int kGWaves = kGThreads / 64;
-constexpr int kGPer = kGChunk / kGWaves;   // spikes of an item per wave
-constexpr int kGU = 4;          // records in flight per lane
 constexpr int kGXcd = 8;        // XCDs; workgroup b runs on XCD b mod 8
 constexpr int kGatherGrid = 1024;          // four workgroups per compute unit, a multiple of kGXcd
 constexpr int kGOutBytes = 29696;          // an item's records in workgroup-local memory
@@ -63,30 +61,26 @@ struct GatherArgs {
 
 struct CopyLds {
     uint32_t out[kGOutBytes / 4];         // the item's records, tile after tile
-    uint32_t rel[kGChunk][kGTiles];       // low 32 bits of each segment's first record
-    uint32_t dst[kGChunk][kGTiles];       // the segment's place in the item's share of its tile's run
-    unsigned long long e0[kGChunk];       // the spike's first record in the tile group
-    uint32_t end_lo[kGChunk];             // low 32 bits of the end of its records in the group
     uint32_t j[kGChunk];
     uint32_t qoff[kGChunk];               // ring row of its step, relative to the window's first: qi T
     uint32_t tot[kGTiles];                // the item's records per tile
     uint32_t obase[kGTiles + 1];          // their first place in `out`; obase[kGTiles]: the item's total
     unsigned long long base[kGTiles];     // their place in the tile's run
     uint32_t ok[kGTiles];
-    uint32_t wpre[kGWaves][kGPer + 1];    // per wave: prefix of its spikes' record counts
 };
 
 // One work item per (64 consecutive spikes of the window, group of G = 2^lg
-// tiles).  The item's descriptors go to workgroup-local memory; a
+// tiles).  Each thread takes the item's segments (spike, tile) at tid and
+// tid + kGThreads and keeps their descriptors in registers; a
 // workgroup-local atomic per segment gives its place in the item's share of
 // the tile's run, and one global atomic per tile reserves that share (its
 // result is needed only when the shares are written, so the atomics'
-// latency overlaps the gathering).  Each wave then takes every kGWaves-th
-// spike of the item and walks their records as one flat list (a spike's
-// segments into the group are one contiguous range, in tile order), kGU
-// records in flight per lane, into the item's buffer; the workgroup then
-// writes the buffer out share by share.  An item whose records overflow the
-// buffer writes them straight to the runs instead.
+// latency overlaps the gathering).  The thread then copies its segments'
+// records, a few 16-byte loads per segment, into the item's buffer (no
+// per-record search: a record's place is its segment's place plus its
+// index); the workgroup then writes the buffer out share by share.  An item
+// whose records overflow the buffer writes them straight to the runs
+// instead.
 //
 // The tile groups are split into kGXcd contiguous ranges, one per XCD, and
 // an XCD's workgroups take its items spike chunk by spike chunk: the items
@@ -96,6 +90,10 @@ struct CopyLds {
 template <bool WBF16, typename META>
 __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(8))) gather_copy_kernel(GatherArgs a) {
     using Rec = typename std::conditional<WBF16, uint32_t, uint2>::type;
+    // a lane loads PR consecutive records of a segment at once: 16 bytes of
+    // packed records, or one record and its separate weight
+    using Piece = typename std::conditional<WBF16, uint4, uint2>::type;
+    constexpr uint32_t PR = WBF16 ? 4u : 1u;
     constexpr uint32_t kOutCap = kGOutBytes / sizeof(Rec);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     if (a.ktime) ktime_mark(a.ktime, 0);
@@ -127,19 +125,32 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
         __syncthreads();   // the previous item's tables and buffer are read
         if (tid < (int)kn) {
             const uint32_t kf = c * kGChunk + (uint32_t)tid;
+            // (the step and its first spike selected in the unrolled loop:
+            // no runtime index into pc, which would put it in scratch)
             int qi = 0;
+            uint32_t k0 = 0;
 #pragma unroll
             for (int q = 1; q < kGMaxQ; ++q)
-                if (q < nq && pc[q] <= kf) qi = q;
-            s.j[tid] = a.spk_ids[(size_t)((q_lo + qi) & (a.H - 1)) * a.N + (kf - pc[qi])];
+                if (q < nq && pc[q] <= kf) {
+                    qi = q;
+                    k0 = pc[q];
+                }
+            s.j[tid] = a.spk_ids[(size_t)((q_lo + qi) & (a.H - 1)) * a.N + (kf - k0)];
             s.qoff[tid] = (uint32_t)qi * a.T;
         }
         if (tid < kGTiles) s.tot[tid] = 0;
         __syncthreads();
-        // descriptors, all loads issued before their uses (an unused slot
-        // reads spike 0's descriptor of the group's first tile)
+        // descriptors: thread tid takes the segments (spike k, tile tt) of
+        // p = tid + kGThreads h, h < UD, and keeps each segment's first
+        // record, length, ring-row offset and place in the item's share of
+        // its tile (a workgroup-local atomic) in registers; the loads are all
+        // issued before their uses (an unused slot reads spike 0's
+        // descriptor of the group's first tile and has length 0)
+        constexpr int UD = kGChunk * kGTiles / kGThreads;
+        uint64_t sf[UD];
+        uint32_t sl[UD], sd[UD], sq[UD];
+        int st[UD];
         {
-            constexpr int UD = kGChunk * kGTiles / kGThreads;
             uint64_t d[UD];
 #pragma unroll
             for (int u = 0; u < UD; ++u) {
@@ -150,14 +161,12 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int u = 0; u < UD; ++u) {
                 const int p = tid + kGThreads * u, k = p >> a.lg, tt = p & (G - 1);
-                if (k < (int)kn && tt < ntg) {
-                    const uint64_t first = d[u] >> 24;
-                    const uint32_t len = (uint32_t)(d[u] & 0xFFFFFFu);
-                    s.rel[k][tt] = (uint32_t)first;
-                    s.dst[k][tt] = len ? atomicAdd(&s.tot[tt], len) : 0u;
-                    if (tt == 0) s.e0[k] = first;
-                    if (tt == ntg - 1) s.end_lo[k] = (uint32_t)(first + len);
-                }
+                const bool v = k < (int)kn && tt < ntg;
+                sf[u] = d[u] >> 24;
+                sl[u] = v ? (uint32_t)(d[u] & 0xFFFFFFu) : 0u;
+                st[u] = v ? tt : 0;
+                sq[u] = v ? s.qoff[k] : 0u;
+                sd[u] = sl[u] ? atomicAdd(&s.tot[tt], sl[u]) : 0u;
             }
         }
         __syncthreads();
@@ -171,14 +180,6 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
             if (lane < kGTiles) s.obase[lane] = incl - my_n;
             if (lane == kGTiles - 1) s.obase[kGTiles] = incl;
         }
-        // this wave's spikes k = wave + kGWaves i: prefix of their record counts
-        {
-            const uint32_t k = (uint32_t)wave + (uint32_t)kGWaves * (uint32_t)lane;
-            const uint32_t rl = (lane < kGPer && k < kn) ? s.end_lo[k] - (uint32_t)s.e0[k] : 0u;
-            const uint32_t incl = wave_incl_scan(rl);
-            if (lane < kGPer) s.wpre[wave][lane] = incl - rl;
-            if (lane == kGPer - 1) s.wpre[wave][kGPer] = incl;
-        }
         __syncthreads();
         const uint32_t total = s.obase[kGTiles];
         const bool fits = total <= kOutCap;   // the same for the whole workgroup
@@ -189,62 +190,54 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
             }
             __syncthreads();
         }
-        const uint32_t* wp = s.wpre[wave];
-        const uint32_t wtotal = wp[kGPer];
-        constexpr int U = kGU;
-        for (uint32_t f0 = (uint32_t)lane; f0 < wtotal; f0 += 64u * U) {
-            uint64_t e[U];
-            uint32_t qo[U], tls[U], sh[U];
-            bool ok[U];
+        // every thread copies its segments, PR x UR records of each at a
+        // time: a lane's loads read its segments' own records (a segment of
+        // a few records is one or two 16-byte loads); a load at or past a
+        // segment's end is clamped to its last records (at most PR - 1
+        // records past the segment, inside the record array and its 16 bytes
+        // of slack), and only the segment's records are stored
+        uint32_t dst0[UD];
+        bool wr[UD];
+        uint32_t mx = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                // past the end: the last record (a valid address, stored
-                // again to its own place)
-                const uint32_t f = min(f0 + 64u * (uint32_t)u, wtotal - 1);
-                // fixed-step searches (no data-dependent branches, so that the
-                // records' lookups overlap): the spike, last i with
-                // wp[i] <= f ...
-                int lo = 0;
+        for (int u = 0; u < UD; ++u) {
+            mx = max(mx, sl[u]);
+            dst0[u] = fits ? s.obase[st[u]] + sd[u] : s.base[st[u]] + sd[u];
+            wr[u] = fits || s.ok[st[u]];
+        }
+        constexpr int UR = WBF16 ? 2 : 4;
+        for (uint32_t i0 = 0; i0 < mx; i0 += PR * UR) {
+            Piece v[UD][UR];
 #pragma unroll
-                for (int step = kGPer / 2; step > 0; step >>= 1)
-                    lo += wp[lo + step] <= f ? step : 0;
-                const uint32_t k = (uint32_t)wave + (uint32_t)kGWaves * (uint32_t)lo;
-                const uint32_t off = f - wp[lo];
-                const uint32_t r0 = (uint32_t)s.e0[k];
-                // ... and the tile, the last segment starting at or before off
-                int tl = 0;
+            for (int u = 0; u < UD; ++u)
 #pragma unroll
-                for (int step = kGTiles / 2; step > 0; step >>= 1) {
-                    const int cand = tl + step;
-                    const uint32_t rv = s.rel[k][cand];   // cand <= kGTiles - 1: read either way, no branch
-                    tl = ((cand < ntg) & (rv - r0 <= off)) ? cand : tl;
+                for (int r = 0; r < UR; ++r) {
+                    const uint64_t e = sf[u] + min(i0 + (uint32_t)r * PR, max(sl[u], 1u) - 1u);
+                    if constexpr (WBF16) {
+                        __builtin_memcpy(&v[u][r], static_cast<const uint32_t*>(a.meta) + e, sizeof(Piece));
+                    } else {
+                        v[u][r] = make_uint2((uint32_t) static_cast<const META*>(a.meta)[e], __float_as_uint(a.w[e]));
+                    }
                 }
-                ok[u] = f0 + 64u * (uint32_t)u < wtotal;
-                e[u] = s.e0[k] + off;
-                qo[u] = s.qoff[k];
-                tls[u] = (uint32_t)tl;
-                sh[u] = s.dst[k][tl] + (off - (s.rel[k][tl] - r0));   // place in the item's share
-            }
-            Rec r[U];
-            if constexpr (WBF16) {
 #pragma unroll
-                for (int u = 0; u < U; ++u)   // meta + qi T stays below 2^16: no carry into the weight
-                    r[u] = static_cast<const uint32_t*>(a.meta)[e[u]] + qo[u];
-            } else {
+            for (int u = 0; u < UD; ++u)
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    r[u] = make_uint2((uint32_t) static_cast<const META*>(a.meta)[e[u]] + qo[u],
-                                      __float_as_uint(a.w[e[u]]));
-            }
-            if (fits) {
+                for (int r = 0; r < UR; ++r)
 #pragma unroll
-                for (int u = 0; u < U; ++u) out[s.obase[tls[u]] + sh[u]] = r[u];
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u] && s.ok[tls[u]])
-                        stage[(size_t)(tb + tls[u]) * a.cap + s.base[tls[u]] + sh[u]] = r[u];
-            }
+                    for (int c = 0; c < (int)PR; ++c) {
+                        const uint32_t i = i0 + (uint32_t)r * PR + (uint32_t)c;
+                        if (!wr[u] || i >= sl[u]) continue;
+                        Rec rec;
+                        if constexpr (WBF16) {
+                            // meta + qi T stays below 2^16: no carry into the weight
+                            const uint32_t w4 = c == 0 ? v[u][r].x : c == 1 ? v[u][r].y : c == 2 ? v[u][r].z : v[u][r].w;
+                            rec = w4 + sq[u];
+                        } else {
+                            rec = make_uint2(v[u][r].x + sq[u], v[u][r].y);
+                        }
+                        if (fits) out[dst0[u] + i] = rec;
+                        else stage[(size_t)(tb + st[u]) * a.cap + dst0[u] + i] = rec;
+                    }
         }
         if (fits) {
             if (wave == 0 && lane < ntg) {

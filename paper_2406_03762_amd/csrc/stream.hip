@@ -129,8 +129,11 @@ __device__ __forceinline__ uint64_t block_counts(uint64_t nl, uint64_t blk, cons
         const uint32_t u = (sub & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
         int kc = 0;
 #pragma unroll
-        for (int h = kMaxThr; h > 0; h >>= 1)
-            if (kc + h <= n_thr && s_thr[kc + h - 1] <= u) kc += h;
+        for (int h = kMaxThr; h > 0; h >>= 1) {
+            // (no branch: the 8 searches of a block interleave)
+            const uint32_t t = s_thr[min(kc + h, kMaxThr) - 1];
+            kc += (kc + h <= n_thr && t <= u) ? h : 0;
+        }
         packed |= (uint64_t)kc << (6 * sub);
     }
     return packed;
@@ -163,27 +166,44 @@ __device__ __forceinline__ void staged_add(const StreamArgs& a, int32_t* ring, S
     }
     uint32_t x = m + row0;
     x = min(x, x - RT);
-    // an unused slot adds 0 at ring index 0
-    ring_add(ring, use ? x : 0u, use ? __float2int_rn(wv * a.fxw_scale) : 0);
+    if (use) ring_add(ring, x, __float2int_rn(wv * a.fxw_scale));
 }
 
 // The tile's n_st staged records, in any order, each with its ring row
-// relative to the window's first delivered step; every thread takes records
-// tid, tid + bs, ..., kStageU at a time.  Clamped indices keep the loads free
-// of branches (a clamped record adds 0).
+// relative to the window's first delivered step, read as 16-byte pieces (4
+// bf16 records or 2 fp32 records; the run starts 16-byte aligned because the
+// capacity per tile is a multiple of 4 records): every thread takes pieces
+// tid, tid + bs, ..., kStageU at a time, so that a workgroup has kStageU x 16
+// bytes per thread in flight.  Clamped indices keep the loads free of
+// branches; the records of a clamped piece, and those past n_st in the last
+// piece (which lies inside the tile's capacity), are not added.
 constexpr int kStageU = 8;
 
 template <bool WBF16>
 __device__ __forceinline__ void deliver_staged(const StreamArgs& a, int32_t* ring, uint32_t n_st, int tile,
                                                int base_slot, uint32_t T, uint32_t RT, int tid, int bs) {
-    const StagedRec<WBF16>* run = static_cast<const StagedRec<WBF16>*>(a.stage) + (size_t)tile * a.stage_cap;
+    constexpr uint32_t PER = WBF16 ? 4u : 2u;
+    const uint4* run =
+        reinterpret_cast<const uint4*>(static_cast<const StagedRec<WBF16>*>(a.stage) + (size_t)tile * a.stage_cap);
     const uint32_t row0 = (uint32_t)base_slot * T;
-    for (uint32_t i0 = (uint32_t)tid; i0 < n_st; i0 += kStageU * (uint32_t)bs) {
-        StagedRec<WBF16> r[kStageU];
+    const uint32_t np = (n_st + PER - 1) / PER;
+    for (uint32_t i0 = (uint32_t)tid; i0 < np; i0 += kStageU * (uint32_t)bs) {
+        uint4 r[kStageU];
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) r[u] = run[min(i0 + (uint32_t)(u * bs), n_st - 1)];
+        for (int u = 0; u < kStageU; ++u) r[u] = run[min(i0 + (uint32_t)(u * bs), np - 1)];
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) staged_add<WBF16>(a, ring, r[u], i0 + (uint32_t)(u * bs) < n_st, row0, RT);
+        for (int u = 0; u < kStageU; ++u) {
+            const uint32_t first = (i0 + (uint32_t)(u * bs)) * PER;
+            if constexpr (WBF16) {
+                staged_add<true>(a, ring, r[u].x, first < n_st, row0, RT);
+                staged_add<true>(a, ring, r[u].y, first + 1 < n_st, row0, RT);
+                staged_add<true>(a, ring, r[u].z, first + 2 < n_st, row0, RT);
+                staged_add<true>(a, ring, r[u].w, first + 3 < n_st, row0, RT);
+            } else {
+                staged_add<false>(a, ring, make_uint2(r[u].x, r[u].y), first < n_st, row0, RT);
+                staged_add<false>(a, ring, make_uint2(r[u].z, r[u].w), first + 1 < n_st, row0, RT);
+            }
+        }
     }
 }
 
@@ -341,41 +361,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         if (lane == 0 && a.stage) c_run = a.cursor[tile];
         if (lane < kMaxThr) s_thr[lane] = lane < a.n_thr ? a.thr[lane] : 0xFFFFFFFFu;
     }
-    // ------------------------------------------------------------ stage in
-    // Only the rows that can hold sums: the spikes delivered before this
-    // window were emitted before t0 - dmin and arrive before
-    // t0 + dmax - dmin, so the rows of arrival steps t0 .. t0 + nin - 1
-    // (nin = dmax - dmin = R - W) are loaded and the other W rows start at
-    // zero (their stored contents are stale: consumed rows are not written
-    // back).  kStageIn loads in flight per thread before their stores; no
-    // branches, so that the loads are all issued first: an index past the
-    // end is clamped to the last piece, which is then read and written
-    // again with its own value.
-    const int T4 = T / 4, RT4 = R * T4;   // 16-byte pieces (T is a multiple of 4)
-    const int nin4 = (R - a.W) * T4;
-    {
-        constexpr int kStageIn = 8;
-        const int4* src = reinterpret_cast<const int4*>(a.ring + (size_t)tile * R * T);
-        int4* dst = reinterpret_cast<int4*>(ring);
-        const int p0 = (int)(t0 % R) * T4;
-        for (int i0 = tid; i0 < nin4; i0 += kStageIn * bs) {
-            int4 v[kStageIn];
-            int at[kStageIn];
-#pragma unroll
-            for (int u = 0; u < kStageIn; ++u) {
-                const int p = p0 + min(i0 + u * bs, nin4 - 1);
-                at[u] = p >= RT4 ? p - RT4 : p;
-                v[u] = src[at[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kStageIn; ++u) dst[at[u]] = v[u];
-        }
-        const int z0 = (int)((t0 + (R - a.W)) % R) * T4;
-        for (int i = tid; i < RT4 - nin4; i += bs) {
-            const int p = z0 + i;
-            dst[p >= RT4 ? p - RT4 : p] = make_int4(0, 0, 0, 0);
-        }
-    }
     float U[NPT], Y1[NPT], Y2[NPT];
     int RF[NPT];
     unsigned long long KC[NPT];
@@ -389,12 +374,47 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         Y2[k] = MODEL == CORTEX_MODEL_ALPHA ? a.y2[gi] : 0.f;
         KC[k] = a.kcache[gi];
     }
+    __syncthreads();   // s_thr
+    // ------------------------------------------------------------ stage in
+    // Only the rows that can hold sums: the spikes delivered before this
+    // window were emitted before t0 - dmin and arrive before
+    // t0 + dmax - dmin, so the rows of arrival steps t0 .. t0 + nin - 1
+    // (nin = dmax - dmin = R - W) are loaded and the other W rows start at
+    // zero (their stored contents are stale: consumed rows are not written
+    // back).  The first kStageIn pieces per thread are requested before the
+    // Poisson draws below and stored after them, so that the draws run while
+    // the loads are in flight; the loads carry no branches: an index past the
+    // end is clamped to the last piece, which is then read and written again
+    // with its own value.
+    const int T4 = T / 4, RT4 = R * T4;   // 16-byte pieces (T is a multiple of 4)
+    const int nin4 = (R - a.W) * T4;
+    constexpr int kStageIn = 8;
+    const int4* ring_src = reinterpret_cast<const int4*>(a.ring + (size_t)tile * R * T);
+    int4* ring_dst = reinterpret_cast<int4*>(ring);
+    const int p_in = (int)(t0 % R) * T4;
+    int4 v_in[kStageIn];
+    int at_in[kStageIn];
+    // (equal delays leave no row to load: then the piece at p_in is read
+    // and zero is stored, as the zero rows below do)
+    const int last_in = max(nin4 - 1, 0);
+#pragma unroll
+    for (int u = 0; u < kStageIn; ++u) {
+        const int p = p_in + min(tid + u * bs, last_in);
+        at_in[u] = p >= RT4 ? p - RT4 : p;
+        v_in[u] = ring_src[at_in[u]];
+    }
+    {
+        const int z0 = (int)((t0 + (R - a.W)) % R) * T4;
+        for (int i = tid; i < RT4 - nin4; i += bs) {
+            const int p = z0 + i;
+            ring_dst[p >= RT4 ? p - RT4 : p] = make_int4(0, 0, 0, 0);
+        }
+    }
     // Poisson counts of the window's steps, 6 bits per step, before the
     // delivery (the update below is then only the ring and the membrane).  A
     // window of at most 8 steps touches at most two 8-step blocks; the block
     // of a neuron's last step is kept in kcache for the next window, so a
     // block is drawn once.
-    __syncthreads();   // s_thr
     uint64_t kcs[NPT];
     {
         const uint64_t blk_lo = (uint64_t)(t0 >> 3), blk_hi = (uint64_t)((t0 + wn - 1) >> 3);
@@ -413,6 +433,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
             const unsigned long long kn = kcache_entry(blk_hi, ch);
             if (li < tsz && kn != KC[k]) a.kcache[g0 + li] = kn;
         }
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIn; ++u) ring_dst[at_in[u]] = nin4 > 0 ? v_in[u] : make_int4(0, 0, 0, 0);
+    for (int i0 = tid + kStageIn * bs; i0 < nin4; i0 += kStageIn * bs) {
+        int4 v[kStageIn];
+        int at[kStageIn];
+#pragma unroll
+        for (int u = 0; u < kStageIn; ++u) {
+            const int p = p_in + min(i0 + u * bs, nin4 - 1);
+            at[u] = p >= RT4 ? p - RT4 : p;
+            v[u] = ring_src[at[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageIn; ++u) ring_dst[at[u]] = v[u];
     }
     if (wave == 0) {
         // exclusive prefix s_pc[0..nq] of the delivered steps' spike counts;

@@ -192,6 +192,9 @@ def test_staging_applies_to_one_instance_with_short_segments():
     assert p["stage_records"] * p["tiles"] * 4 <= 4 << 30
     assert cx.cortex_plan(big, stage_records=-1, **MI355X)["stage_records"] == 0
     assert cx.cortex_plan(big, stage_records=5000, **MI355X)["stage_records"] == 5000
+    # rounded up to whole 16-byte pieces of 4-byte records
+    for asked, got in ((5001, 5004), (1, 4), (4, 4)):
+        assert cx.cortex_plan(big, stage_records=asked, **MI355X)["stage_records"] == got
     # long segments, or several instances: no staging
     s50 = netspec.brunel_2m_bf16(scale_n=0.025)
     assert cx.cortex_plan(s50, plan="streamed", **MI355X)["stage_records"] == 0
