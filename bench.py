@@ -39,12 +39,12 @@ TRAFFIC = {
     # 112,500-neuron alpha net, one 1000-step launch: (3.3021e6 KiB x 2.0
     # + 2.0456e5 KiB x 1.0) x 1024 / 9.708e8 events
     "step_kernel": (7.182, "2a1f56a6bb60aa11"),
-    # two-million-neuron bf16 net, launches 10-199 of a 1000-step run,
-    # 8.5245e7 events per launch: delivery (2.8468e5 KiB x 2.0 + 2.6023e5
-    # KiB x 1.0) x 1024, staging copy (2.5556e5 KiB x 2.0 + 5.6665e5 KiB x
-    # 1.0) x 1024
-    "stream_kernel": (9.965, "abe03b8332f934a5"),
-    "gather_copy_kernel": (12.946, "25a2e02e59047d78"),
+    # two-million-neuron bf16 net, the 2,000 window launches of each kernel
+    # in the timed second of a run after one second of warmup, 1.59677e11
+    # events: delivery (5.3993e8 KiB x 2.0 + 4.4242e8 KiB x 1.0) x 1024,
+    # staging copy (4.7192e8 KiB x 2.0 + 6.3864e8 KiB x 1.0) x 1024
+    "stream_kernel": (9.762, "514371863229d0d7"),
+    "gather_copy_kernel": (10.148, "9ef9851f1adbe75b"),
 }
 
 
