@@ -147,6 +147,29 @@ __device__ __forceinline__ unsigned long long kcache_entry(uint64_t blk, uint64_
     return (((blk + 1) & 0xFFFFull) << 48) | (counts & kCountsMask);
 }
 
+// Data a launch touches once, in streams (the staged run, the ring rows
+// staged in and written back), are loaded and stored with the non-temporal
+// hint (the instructions' nt bit), so that they do not push more reused
+// lines out of the caches.  Measured on the two-million-neuron net: the
+// delivery launch 0.203 -> 0.187 ms, the next staging copy 0.189 -> 0.181 ms.
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 load_stream(const int4* p) {
+    const i32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(p));
+    return make_int4(q.x, q.y, q.z, q.w);
+}
+__device__ __forceinline__ uint4 load_stream(const uint4* p) {
+    const int4 q = load_stream(reinterpret_cast<const int4*>(p));
+    return make_uint4((uint32_t)q.x, (uint32_t)q.y, (uint32_t)q.z, (uint32_t)q.w);
+}
+__device__ __forceinline__ void store_stream(int4* p, int4 v) {
+    i32x4_t q;
+    q.x = v.x;
+    q.y = v.y;
+    q.z = v.z;
+    q.w = v.w;
+    __builtin_nontemporal_store(q, reinterpret_cast<i32x4_t*>(p));
+}
+
 // Staged records (gather.hip): u32 words (16-bit record with the bf16
 // weight in the high half) or {record, fp32 weight bits}.
 template <bool WBF16>
@@ -190,7 +213,7 @@ __device__ __forceinline__ void deliver_staged(const StreamArgs& a, int32_t* rin
     for (uint32_t i0 = (uint32_t)tid; i0 < np; i0 += kStageU * (uint32_t)bs) {
         uint4 r[kStageU];
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) r[u] = run[min(i0 + (uint32_t)(u * bs), np - 1)];
+        for (int u = 0; u < kStageU; ++u) r[u] = load_stream(&run[min(i0 + (uint32_t)(u * bs), np - 1)]);
 #pragma unroll
         for (int u = 0; u < kStageU; ++u) {
             const uint32_t first = (i0 + (uint32_t)(u * bs)) * PER;
@@ -401,7 +424,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     for (int u = 0; u < kStageIn; ++u) {
         const int p = p_in + min(tid + u * bs, last_in);
         at_in[u] = p >= RT4 ? p - RT4 : p;
-        v_in[u] = ring_src[at_in[u]];
+        v_in[u] = load_stream(&ring_src[at_in[u]]);
     }
     {
         const int z0 = (int)((t0 + (R - a.W)) % R) * T4;
@@ -616,7 +639,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         for (int i = tid; i < nin4; i += bs) {
             const int p = p0 + i;
             const int q = p >= RT4 ? p - RT4 : p;
-            dst[q] = src[q];
+            store_stream(&dst[q], src[q]);
         }
     }
     if (tid == 0) {
