@@ -148,10 +148,11 @@ __device__ __forceinline__ unsigned long long kcache_entry(uint64_t blk, uint64_
 }
 
 // Data a launch touches once, in streams (the staged run, the ring rows
-// staged in and written back), are loaded and stored with the non-temporal
-// hint (the instructions' nt bit), so that they do not push more reused
-// lines out of the caches.  Measured on the two-million-neuron net: the
-// delivery launch 0.203 -> 0.187 ms, the next staging copy 0.189 -> 0.181 ms.
+// staged in and written back, the neurons' state), are loaded and stored
+// with the non-temporal hint (the instructions' nt bit), so that they do not
+// push more reused lines out of the caches.  Measured on the two-million-
+// neuron net: the delivery launch 0.203 -> 0.183 ms, the next staging copy
+// 0.189 -> 0.181 ms.
 typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int4 load_stream(const int4* p) {
     const i32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(p));
@@ -391,11 +392,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     for (int k = 0; k < NPT; ++k) {
         // (a thread past the tile's end reads its last neuron and never uses it)
         const int64_t gi = g0 + min(tid + k * bs, tsz - 1);
-        U[k] = a.U[gi];
-        RF[k] = a.r[gi];
-        Y1[k] = MODEL != CORTEX_MODEL_DELTA ? a.y1[gi] : 0.f;
-        Y2[k] = MODEL == CORTEX_MODEL_ALPHA ? a.y2[gi] : 0.f;
-        KC[k] = a.kcache[gi];
+        U[k] = __builtin_nontemporal_load(&a.U[gi]);
+        RF[k] = __builtin_nontemporal_load(&a.r[gi]);
+        Y1[k] = MODEL != CORTEX_MODEL_DELTA ? __builtin_nontemporal_load(&a.y1[gi]) : 0.f;
+        Y2[k] = MODEL == CORTEX_MODEL_ALPHA ? __builtin_nontemporal_load(&a.y2[gi]) : 0.f;
+        KC[k] = __builtin_nontemporal_load(&a.kcache[gi]);
     }
     __syncthreads();   // s_thr
     // ------------------------------------------------------------ stage in
@@ -454,7 +455,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
             const uint64_t w = (cl >> (6 * s0)) | (s0 ? ch << (6 * (8 - s0)) : 0ull);
             kcs[k] = w & ((1ull << (6 * wn)) - 1);
             const unsigned long long kn = kcache_entry(blk_hi, ch);
-            if (li < tsz && kn != KC[k]) a.kcache[g0 + li] = kn;
+            if (li < tsz && kn != KC[k]) __builtin_nontemporal_store(kn, &a.kcache[g0 + li]);
         }
     }
 #pragma unroll
@@ -595,10 +596,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
                     if (a.m_trace) a.m_trace[ti] = (integ && !spk) ? 1 : 0;
                 }
             }
-            a.U[g0 + li] = U[k];
-            a.r[g0 + li] = RF[k];
-            if (MODEL != CORTEX_MODEL_DELTA) a.y1[g0 + li] = Y1[k];
-            if (MODEL == CORTEX_MODEL_ALPHA) a.y2[g0 + li] = Y2[k];
+            __builtin_nontemporal_store(U[k], &a.U[g0 + li]);
+            __builtin_nontemporal_store(RF[k], &a.r[g0 + li]);
+            if (MODEL != CORTEX_MODEL_DELTA) __builtin_nontemporal_store(Y1[k], &a.y1[g0 + li]);
+            if (MODEL == CORTEX_MODEL_ALPHA) __builtin_nontemporal_store(Y2[k], &a.y2[g0 + li]);
         }
     }
     __syncthreads();
