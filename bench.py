@@ -41,9 +41,9 @@ TRAFFIC = {
     "step_kernel": (7.182, "2a1f56a6bb60aa11"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
-    # events: delivery (5.3993e8 KiB x 2.0 + 4.4242e8 KiB x 1.0) x 1024,
+    # events: delivery (5.4007e8 KiB x 2.0 + 4.4253e8 KiB x 1.0) x 1024,
     # staging copy (4.7192e8 KiB x 2.0 + 6.3864e8 KiB x 1.0) x 1024
-    "stream_kernel": (9.762, "514371863229d0d7"),
+    "stream_kernel": (9.765, "6a1b3e78466d66f9"),
     "gather_copy_kernel": (10.148, "9ef9851f1adbe75b"),
 }
 
@@ -102,7 +102,7 @@ def timed_run(net, torch, steps, warmup, sim_steps, name):
     return out
 
 
-def roofline(net, run, steps, sim_steps, ktimes=None):
+def roofline(net, run, steps, sim_steps, ktimes=None, model="delta"):
     """Roofline of the dominant kernel: its algorithmic bytes per launch over
     its average launch duration.  Resident plan: one persistent launch per
     call (event-timed calls).  Streamed plan: per window a delivery launch
@@ -113,7 +113,13 @@ def roofline(net, run, steps, sim_steps, ktimes=None):
     Algorithmic bytes: the delivery
     launch reads each delivered record once (record bytes per event); the
     copy reads it from the graph and writes it to the tile's run (twice
-    that), and reads one 8-byte descriptor per (delivered spike, tile)."""
+    that), and reads one 8-byte descriptor per (delivered spike, tile).
+    The delivery launch also carries per-window state, reported beside it
+    (state_bytes_per_launch, frac_with_state), not in `frac`: the ring rows
+    that can hold sums, (R - W) x T cells per tile, loaded and written back,
+    and every neuron's state (membrane, refractory count, cached Poisson
+    counts and, for exp/alpha currents, the synaptic currents) loaded and
+    stored."""
     streamed = net.query("PLAN") == 2
     W = net.query("STEPS_PER_SYNC")
     launches = -(-sim_steps // W) if streamed else 1
@@ -141,6 +147,13 @@ def roofline(net, run, steps, sim_steps, ktimes=None):
             out["kernels"][k] = {"algorithmic_bytes_per_launch": b, "avg_launch_ms": t * 1e3,
                                  "achieved_GBps": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS,
                                  "traffic": None if tk is None else tk * events_per_launch}
+        ring = (net.query("TILES") * (net.query("RING_SLOTS") - W) * net.query("TILE_SIZE")
+                * net.query("RING_BYTES") * 2)
+        per_neuron = 16 + (4 if model in ("exp", "alpha") else 0) + (4 if model == "alpha" else 0)
+        state = ring + net.query("NEURONS") * per_neuron * 2
+        sk = out["kernels"]["stream_kernel"]
+        sk["state_bytes_per_launch"] = state
+        sk["frac_with_state"] = (sk["algorithmic_bytes_per_launch"] + state) / (sk["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
         out["window_ms"] = run["gpu_ms_per_step"] / launches
         out["timed_windows"] = nw
     achieved = alg / avg_s / 1e9
@@ -459,7 +472,7 @@ def main():
     streamed = net.query("PLAN") == 2
     run = timed_run(net, torch, args.steps, args.warmup, args.sim_steps, "headline")
     ktimes = net.kernel_times() if streamed else None
-    roof = roofline(net, run, args.steps, args.sim_steps, ktimes)
+    roof = roofline(net, run, args.steps, args.sim_steps, ktimes, model=spec.model)
     rec = "16-bit record + bf16 weight" if spec.weight_dtype == "bf16" else "16-bit record + fp32 weight"
     cfg = {
         "workload": (f"balanced random net, {spec.model}-current LIF, {spec.n_neurons:,} neurons "

@@ -156,10 +156,7 @@ __global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(
             for (int u = 0; u < UD; ++u) {
                 const int p = tid + kGThreads * u, k = p >> a.lg, tt = p & (G - 1);
                 const bool v = k < (int)kn && tt < ntg;
-                // (non-temporal: the descriptors are read once per window; the
-            // records, whose lines at the ends of a segment run are shared
-            // with the neighbouring items, are not)
-            d[u] = __builtin_nontemporal_load(&a.seg[a.offb + (uint64_t)s.j[v ? k : 0] * rowlen + tb + (v ? tt : 0)]);
+                d[u] = a.seg[a.offb + (uint64_t)s.j[v ? k : 0] * rowlen + tb + (v ? tt : 0)];
             }
 #pragma unroll
             for (int u = 0; u < UD; ++u) {
