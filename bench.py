@@ -36,15 +36,15 @@ CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
 # size, as the summaries under profiles/ state), valid only for the sources
 # they were measured on: {kernel: (bytes per event, source hash)}.
 TRAFFIC = {
-    # 112,500-neuron alpha net, one 1000-step launch: (3.3021e6 KiB x 2.0
-    # + 2.0456e5 KiB x 1.0) x 1024 / 9.708e8 events
-    "step_kernel": (7.182, "2a1f56a6bb60aa11"),
+    # 112,500-neuron alpha net, one 1000-step launch: (3.7757e6 KiB x 2.0
+    # + 4.3662e4 KiB x 1.0) x 1024 / 9.708e8 events
+    "step_kernel": (8.011, "6bac180e1ce2986e"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
-    # events: delivery (5.4007e8 KiB x 2.0 + 4.4253e8 KiB x 1.0) x 1024,
-    # staging copy (4.7192e8 KiB x 2.0 + 6.3864e8 KiB x 1.0) x 1024
-    "stream_kernel": (9.765, "6a1b3e78466d66f9"),
-    "gather_copy_kernel": (10.148, "9ef9851f1adbe75b"),
+    # events: delivery (5.4006e8 KiB x 2.0 + 4.4253e8 KiB x 1.0) x 1024,
+    # staging copy (4.7046e8 KiB x 2.0 + 6.3850e8 KiB x 1.0) x 1024
+    "stream_kernel": (9.765, "331d5c7e8fdcb486"),
+    "gather_copy_kernel": (10.129, "9ef9851f1adbe75b"),
 }
 
 
