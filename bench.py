@@ -41,10 +41,10 @@ TRAFFIC = {
     "step_kernel": (8.011, "6bac180e1ce2986e"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
-    # events: delivery (5.4006e8 KiB x 2.0 + 4.4253e8 KiB x 1.0) x 1024,
-    # staging copy (4.7046e8 KiB x 2.0 + 6.3850e8 KiB x 1.0) x 1024
-    "stream_kernel": (9.765, "331d5c7e8fdcb486"),
-    "gather_copy_kernel": (10.129, "9ef9851f1adbe75b"),
+    # events: delivery (5.4017e8 KiB x 2.0 + 4.4255e8 KiB x 1.0) x 1024,
+    # staging copy (4.7089e8 KiB x 2.0 + 6.3859e8 KiB x 1.0) x 1024
+    "stream_kernel": (9.766, "d365c7ced7e2ef67"),
+    "gather_copy_kernel": (10.135, "9ef9851f1adbe75b"),
 }
 
 
