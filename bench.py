@@ -36,15 +36,15 @@ CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
 # size, as the summaries under profiles/ state), valid only for the sources
 # they were measured on: {kernel: (bytes per event, source hash)}.
 TRAFFIC = {
-    # 112,500-neuron alpha net, one 1000-step launch: (3.7757e6 KiB x 2.0
-    # + 4.3662e4 KiB x 1.0) x 1024 / 9.708e8 events
-    "step_kernel": (8.011, "6bac180e1ce2986e"),
+    # 112,500-neuron alpha net, one 1000-step launch: (3.3021e6 KiB x 2.0
+    # + 2.0456e5 KiB x 1.0) x 1024 / 9.708e8 events
+    "step_kernel": (7.182, "2a1f56a6bb60aa11"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
-    # events: delivery (5.4017e8 KiB x 2.0 + 4.4255e8 KiB x 1.0) x 1024,
-    # staging copy (4.7089e8 KiB x 2.0 + 6.3859e8 KiB x 1.0) x 1024
-    "stream_kernel": (9.766, "d365c7ced7e2ef67"),
-    "gather_copy_kernel": (10.135, "9ef9851f1adbe75b"),
+    # events: delivery (5.4017e8 KiB x 2.0 + 4.4254e8 KiB x 1.0) x 1024,
+    # staging copy (4.7157e8 KiB x 2.0 + 6.3852e8 KiB x 1.0) x 1024
+    "stream_kernel": (9.766, "5d4c650108de557a"),
+    "gather_copy_kernel": (10.143, "9ef9851f1adbe75b"),
 }
 
 

@@ -48,11 +48,6 @@ __device__ __forceinline__ void ring_add(RING* ring, uint32_t x, int32_t iw) {
     }
 }
 
-// Synapse records are loaded with the non-temporal hint: a record is read
-// once per spike of its source, and the graph is far larger than the caches,
-// which are better left to the step records and spike lists every workgroup
-// polls (112,500-neuron net, resident plan: 1.6 % faster).
-//
 // Record e: meta (delay - d_min) T + target and the weight.  Two layouts:
 // META (16 or 32 bits) and an fp32 weight in separate arrays, or, for bf16
 // weights, one packed 32-bit word (weight in the high half, 16-bit record
@@ -60,12 +55,12 @@ __device__ __forceinline__ void ring_add(RING* ring, uint32_t x, int32_t iw) {
 template <typename META, bool WBF16>
 __device__ __forceinline__ void load_rec(const void* meta, const void* w, uint64_t e, uint32_t& m, float& wv) {
     if (WBF16) {
-        const uint32_t r = __builtin_nontemporal_load(&static_cast<const uint32_t*>(meta)[e]);
+        const uint32_t r = static_cast<const uint32_t*>(meta)[e];
         m = r & 0xFFFFu;
         wv = __uint_as_float(r & 0xFFFF0000u);
     } else {
-        m = __builtin_nontemporal_load(&static_cast<const META*>(meta)[e]);
-        wv = __builtin_nontemporal_load(&static_cast<const float*>(w)[e]);
+        m = static_cast<const META*>(meta)[e];
+        wv = static_cast<const float*>(w)[e];
     }
 }
 
@@ -112,12 +107,12 @@ __device__ __forceinline__ void deliver_long(const uint4* s_sg, RING* ring, int 
                 // m[u] and wv[u] are read below under the same condition
                 if (o < len[u]) {
                     if (WBF16) {
-                        const uint32_t r = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(mp[u] + o * 4u));
+                        const uint32_t r = *reinterpret_cast<const uint32_t*>(mp[u] + o * 4u);
                         m[u] = r & 0xFFFFu;
                         wv[u] = __uint_as_float(r & 0xFFFF0000u);
                     } else {
-                        m[u] = __builtin_nontemporal_load(reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META)));
-                        wv[u] = __builtin_nontemporal_load(reinterpret_cast<const float*>(wp[u] + o * 4u));
+                        m[u] = *reinterpret_cast<const META*>(mp[u] + o * (uint32_t)sizeof(META));
+                        wv[u] = *reinterpret_cast<const float*>(wp[u] + o * 4u);
                     }
                 }
             }
