@@ -41,10 +41,10 @@ TRAFFIC = {
     "step_kernel": (7.182, "2a1f56a6bb60aa11"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
-    # events: delivery (5.4017e8 KiB x 2.0 + 4.4254e8 KiB x 1.0) x 1024,
-    # staging copy (4.7157e8 KiB x 2.0 + 6.3852e8 KiB x 1.0) x 1024
-    "stream_kernel": (9.766, "5d4c650108de557a"),
-    "gather_copy_kernel": (10.143, "9ef9851f1adbe75b"),
+    # events: delivery (5.4019e8 KiB x 2.0 + 4.4249e8 KiB x 1.0) x 1024,
+    # staging copy (4.7085e8 KiB x 2.0 + 6.3850e8 KiB x 1.0) x 1024
+    "stream_kernel": (9.766, "15876bd72a0de29e"),
+    "gather_copy_kernel": (10.133, "9ef9851f1adbe75b"),
 }
 
 

@@ -604,12 +604,27 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     }
     __syncthreads();
     // ------------------------------------------------------------ publish
-    // one reservation per step in the instance's list of that step
+    // one reservation per step in the instance's list of that step; the
+    // reservations are requested first and the ring rows the next window
+    // loads (arrival steps t0 + wn .. t0 + wn + nin - 1) are written back
+    // while they are in flight
+    uint32_t res_c = 0, res_at = 0;
     if (tid < wn) {
         const int64_t n = t0 + tid;
-        const uint32_t c = (uint32_t)s_cnt[tid];
-        s_misc[tid] = c ? (int)atomicAdd(&a.spk_cnt[(size_t)(n & (H - 1)) * a.n_inst + b], c) : 0;
+        res_c = (uint32_t)s_cnt[tid];
+        if (res_c) res_at = atomicAdd(&a.spk_cnt[(size_t)(n & (H - 1)) * a.n_inst + b], res_c);
     }
+    {
+        int4* dst = reinterpret_cast<int4*>(a.ring + (size_t)tile * R * T);
+        const int4* src = reinterpret_cast<const int4*>(ring);
+        const int p0 = (int)((t0 + wn) % R) * T4;
+        for (int i = tid; i < nin4; i += bs) {
+            const int p = p0 + i;
+            const int q = p >= RT4 ? p - RT4 : p;
+            store_stream(&dst[q], src[q]);
+        }
+    }
+    if (tid < wn) s_misc[tid] = res_c ? (int)res_at : 0;
     uint64_t log_pos = a.log_pos[tile];
     const uint64_t log_b = a.log_base[tile], log_cap = a.log_base[tile + 1] - log_b;
     __syncthreads();
@@ -630,18 +645,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
             }
         }
         nspk += c;
-    }
-    // ------------------------------------------------------------ stage out
-    // the rows the next window loads: arrival steps t0 + wn .. t0 + wn + nin - 1
-    {
-        int4* dst = reinterpret_cast<int4*>(a.ring + (size_t)tile * R * T);
-        const int4* src = reinterpret_cast<const int4*>(ring);
-        const int p0 = (int)((t0 + wn) % R) * T4;
-        for (int i = tid; i < nin4; i += bs) {
-            const int p = p0 + i;
-            const int q = p >= RT4 ? p - RT4 : p;
-            store_stream(&dst[q], src[q]);
-        }
     }
     if (tid == 0) {
         a.events[tile] += ev;
