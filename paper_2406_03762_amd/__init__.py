@@ -98,6 +98,9 @@ def lib() -> C.CDLL:
         L.cortex_set_weights.argtypes = [P, P]
         L.cortex_reset.argtypes = [P]
         L.cortex_get_state.argtypes = [P, P, P, P, P]
+        L.cortex_state_size.argtypes = [P, C.POINTER(i64)]
+        L.cortex_save_state.argtypes = [P, P, i64]
+        L.cortex_load_state.argtypes = [P, P, i64]
         L.cortex_export_graph.argtypes = [P, P, P, P, P]
         L.cortex_export_canonical.argtypes = [P, P]
         L.cortex_export_tiles.argtypes = [P, P, P, P]
@@ -374,6 +377,23 @@ def cortex_get_state(h, N: int):
     return V, r, y1, y2
 
 
+def cortex_state_size(h) -> int:
+    n = C.c_int64(0)
+    _check(lib().cortex_state_size(h, C.byref(n)))
+    return n.value
+
+
+def cortex_save_state(h) -> np.ndarray:
+    buf = np.zeros(cortex_state_size(h), np.uint8)
+    _check(lib().cortex_save_state(h, buf.ctypes.data, buf.size))
+    return buf
+
+
+def cortex_load_state(h, buf) -> None:
+    buf = np.ascontiguousarray(np.asarray(buf, dtype=np.uint8))
+    _check(lib().cortex_load_state(h, buf.ctypes.data, buf.size))
+
+
 def cortex_export_graph(h, E: int):
     src = np.zeros(E, np.int64)
     tgt = np.zeros(E, np.int64)
@@ -486,6 +506,14 @@ class Network:
 
     def state(self):
         return cortex_get_state(self._h, self.N)
+
+    def save_state(self) -> np.ndarray:
+        """The network's complete dynamic state as bytes (cortex_save_state)."""
+        return cortex_save_state(self._h)
+
+    def load_state(self, buf) -> None:
+        """Restore a state saved by a network of the same spec, seed and plan."""
+        cortex_load_state(self._h, buf)
 
     def graph(self):
         return cortex_export_graph(self._h, self.E)

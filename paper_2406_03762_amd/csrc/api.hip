@@ -1188,6 +1188,96 @@ static void require_net(cortex_net* n) {
     require(!n->failed, CORTEX_ESTATE, "network failed earlier; destroy it");
 }
 
+// The dynamic state of an FP32 network, part by part (device buffers), for
+// cortex_save_state / cortex_load_state: everything a step reads and writes
+// besides the immutable graph.  The staging cursors are zero between
+// windows and the staged runs are rebuilt by every window, so neither is
+// part of it.
+struct StatePart {
+    void* p;
+    size_t bytes;
+};
+
+static std::vector<StatePart> state_parts(cortex_net* n) {
+    const size_t N = (size_t)n->N, nt = (size_t)n->n_tiles;
+    std::vector<StatePart> v{{n->d_U, N * sizeof(float)},
+                             {n->d_y1, N * sizeof(float)},
+                             {n->d_y2, N * sizeof(float)},
+                             {n->d_r, N * sizeof(int32_t)},
+                             {n->d_ring, nt * n->R * n->T * n->ring_bytes}};
+    if (n->plan_kind == CORTEX_PLAN_STREAMED) {
+        v.push_back({n->d_spk_cnt, (size_t)n->H * n->n_inst * sizeof(uint32_t)});
+        v.push_back({n->d_spk_ids, (size_t)n->H * N * sizeof(uint32_t)});
+        v.push_back({n->d_clock, 2 * sizeof(int64_t)});
+        v.push_back({n->d_kcache, N * sizeof(unsigned long long)});
+        if (n->stdp) {
+            v.push_back({n->d_seg_state, std::max<uint64_t>(1, n->n_seg) * sizeof(uint64_t)});
+            v.push_back({n->d_hist_step, N * kHistLen * sizeof(int32_t)});
+            v.push_back({n->d_hist_y, N * kHistLen * sizeof(float)});
+            v.push_back({n->d_hist_cnt, N * sizeof(uint32_t)});
+            v.push_back({n->d_hist_upto, nt * sizeof(int64_t)});
+            // plastic weights, with their records: the order of the synapses
+            // inside a segment is not the same in every build, so the
+            // weights are restored only together with the records they
+            // belong to
+            v.push_back({n->d_meta, (size_t)n->E * n->meta_bytes});
+            v.push_back({n->d_w, (size_t)n->E * n->w_bytes});
+        }
+    } else {
+        v.push_back({n->d_pub, (size_t)n->H * nt * (n->T + 1) * sizeof(uint64_t)});
+    }
+    const int64_t per = (n->log_steps + n->k.n_ref) / (n->k.n_ref + 1);
+    uint64_t log_ids = 0;
+    for (int t = 0; t < n->n_tiles; ++t) log_ids += (uint64_t)n->tile_size[t] * per;
+    v.push_back({n->d_log_cnt, (size_t)std::max<int64_t>(1, n->log_steps) * nt * sizeof(uint32_t)});
+    v.push_back({n->d_log_ids, std::max<uint64_t>(1, log_ids) * sizeof(uint32_t)});
+    v.push_back({n->d_log_pos, nt * sizeof(uint64_t)});
+    v.push_back({n->d_events, nt * sizeof(uint64_t)});
+    v.push_back({n->d_spikes, nt * sizeof(uint64_t)});
+    v.push_back({n->d_err, 4 * sizeof(int32_t)});
+    return v;
+}
+
+// Header of a saved state: what identifies the network and its plan, and
+// the host side of the state.
+struct StateHeader {
+    uint64_t magic;
+    int64_t N, E, step, log_step0, log_steps, bytes;
+    int32_t n_tiles, T, R, H, W, ring_bytes, plan_kind, stdp, clock_parity, n_parts;
+    uint64_t seed;
+};
+constexpr uint64_t kStateMagic = 0x31455441545358ull;   // "XSTATE1"
+
+static void state_supported(cortex_net* n) {
+    require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "saved states are FP32 only");
+    require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "saved states exclude networks with the adjoint enabled");
+}
+
+static StateHeader state_header(cortex_net* n, const std::vector<StatePart>& parts) {
+    StateHeader h{};
+    h.magic = kStateMagic;
+    h.N = n->N;
+    h.E = n->E;
+    h.step = n->step;
+    h.log_step0 = n->log_step0;
+    h.log_steps = n->log_steps;
+    h.n_tiles = n->n_tiles;
+    h.T = n->T;
+    h.R = n->R;
+    h.H = n->H;
+    h.W = n->W;
+    h.ring_bytes = n->ring_bytes;
+    h.plan_kind = n->plan_kind;
+    h.stdp = n->stdp ? 1 : 0;
+    h.clock_parity = n->clock_parity;
+    h.n_parts = (int32_t)parts.size();
+    h.seed = n->seed;
+    int64_t b = sizeof(StateHeader);
+    for (const auto& p : parts) b += (int64_t)p.bytes;
+    h.bytes = b;
+    return h;
+}
+
 extern "C" {
 
 const char* cortex_last_error(void) { return g_error.c_str(); }
@@ -1405,6 +1495,72 @@ int cortex_reset(cortex_net* n) {
     n->step = 0;
     n->log_step0 = 0;
     CX_HIP(hipStreamSynchronize(n->stream));
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_state_size(cortex_net* n, int64_t* bytes) {
+    CX_API_BEGIN
+    require_net(n);
+    require(bytes != nullptr, CORTEX_EINVAL, "bytes is NULL");
+    state_supported(n);
+    const auto parts = state_parts(n);
+    *bytes = state_header(n, parts).bytes;
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_save_state(cortex_net* n, void* host, int64_t bytes) {
+    CX_API_BEGIN
+    require_net(n);
+    require(host != nullptr, CORTEX_EINVAL, "host buffer is NULL");
+    state_supported(n);
+    check_device_flag(n);
+    const auto parts = state_parts(n);
+    const StateHeader h = state_header(n, parts);
+    require(bytes >= h.bytes, CORTEX_EINVAL, "host buffer smaller than the state");
+    CX_HIP(hipStreamSynchronize(n->stream));
+    unsigned char* out = static_cast<unsigned char*>(host);
+    std::memcpy(out, &h, sizeof h);
+    size_t at = sizeof h;
+    for (const auto& p : parts) {
+        CX_HIP(hipMemcpyAsync(out + at, p.p, p.bytes, hipMemcpyDeviceToHost, n->stream));
+        at += p.bytes;
+    }
+    CX_HIP(hipStreamSynchronize(n->stream));
+    return CORTEX_OK;
+    CX_API_END
+}
+
+int cortex_load_state(cortex_net* n, const void* host, int64_t bytes) {
+    CX_API_BEGIN
+    require_net(n);
+    require(host != nullptr, CORTEX_EINVAL, "host buffer is NULL");
+    state_supported(n);
+    const auto parts = state_parts(n);
+    const StateHeader mine = state_header(n, parts);
+    require(bytes >= (int64_t)sizeof(StateHeader), CORTEX_EINVAL, "state buffer too small");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof h);
+    const bool same = h.magic == kStateMagic && h.N == mine.N && h.E == mine.E && h.log_steps == mine.log_steps &&
+                      h.n_tiles == mine.n_tiles && h.T == mine.T && h.R == mine.R && h.H == mine.H &&
+                      h.W == mine.W && h.ring_bytes == mine.ring_bytes && h.plan_kind == mine.plan_kind &&
+                      h.stdp == mine.stdp && h.n_parts == mine.n_parts && h.bytes == mine.bytes &&
+                      h.seed == mine.seed;
+    require(same, CORTEX_EINVAL, "the state was saved by a network of another spec, seed or plan");
+    require(bytes >= h.bytes, CORTEX_EINVAL, "state buffer shorter than its header says");
+    CX_HIP(hipStreamSynchronize(n->stream));
+    if (n->plan_kind == CORTEX_PLAN_STREAMED) drop_graph(n);
+    const unsigned char* in = static_cast<const unsigned char*>(host);
+    size_t at = sizeof h;
+    for (const auto& p : parts) {
+        CX_HIP(hipMemcpyAsync(p.p, in + at, p.bytes, hipMemcpyHostToDevice, n->stream));
+        at += p.bytes;
+    }
+    CX_HIP(hipStreamSynchronize(n->stream));
+    n->step = h.step;
+    n->log_step0 = h.log_step0;
+    n->clock_parity = h.clock_parity;
     return CORTEX_OK;
     CX_API_END
 }
