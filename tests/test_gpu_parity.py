@@ -351,7 +351,15 @@ def test_adjoint_matches_oracle_on_frozen_raster(cx, orc, model):
     assert loss == pytest.approx(loss_o, rel=1e-5)
     scale = np.abs(gro).max()
     assert scale > 0
-    assert np.allclose(gr, gro, rtol=1e-3, atol=1e-4 * scale)
+    # The forward runs in FP32: its membrane potentials carry relative
+    # errors near 1e-7, which reach every gradient through V - V*, so the
+    # absolute error is a fraction of the largest gradient rather than of
+    # each one (measured: at most 5.4e-6 of it over the three models); 2e-5
+    # checks the small gradients too, down to that level.
+    assert np.allclose(gr, gro, rtol=1e-3, atol=2e-5 * scale)
+    # synapses whose source never spikes early enough have no gradient at all
+    zero = gro == 0.0
+    assert zero.any() and np.all(gr[zero] == 0.0)
     # canonical order of the export matches the oracle's edge order
     canon = g.canonical()
     src, tgt, w, d = g.graph()
