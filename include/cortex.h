@@ -308,19 +308,19 @@ int cortex_get_state(cortex_net* net, double* V, int32_t* r, double* y1, double*
 /* Passage: the state of the simulation of Sec. II-B between two time steps
    (the neurons of Eq. 1-2, the delayed inputs of Sec. III-B not yet
    consumed, the spikes still to be delivered, Sec. III-C).
-   Checkpoint and resume of an FP32 network: cortex_state_size gives the
-   bytes of its complete dynamic state (neuron and synapse state, input
-   rings, pending spikes, cached Poisson counts, spike log and counters, and
-   with plasticity the synapse records with their weights, the traces and
-   the spike histories; the rest of the graph is rebuilt from the spec and
-   seed); cortex_save_state copies it into a
-   caller-owned host buffer of at least that size; cortex_load_state
-   restores it into a network built from the same spec and seed with the
-   same plan, which then continues exactly as the saved one would have
-   (same spikes, same state, bit for bit).  Synchronising.  Errors:
-   EUNSUPPORTED (FP64 networks, networks with the adjoint enabled), EINVAL
-   (NULL, a buffer too small, a state saved by a network of another spec,
-   seed or plan). */
+   Checkpoint and resume of a network: cortex_state_size gives the bytes of
+   its complete dynamic state (neuron and synapse state, input rings,
+   pending spikes, cached Poisson counts, spike log and counters, and with
+   plasticity the synapse records with their weights, the traces and the
+   spike histories; in FP64 verify mode the state, the recent spike bits and
+   the record window; the rest of the graph is rebuilt from the spec and
+   seed); cortex_save_state copies it into a caller-owned host buffer of at
+   least that size; cortex_load_state restores it into a network built from
+   the same spec and seed with the same plan, which then continues exactly
+   as the saved one would have (same spikes, same state, bit for bit).
+   Synchronising.  Errors: EUNSUPPORTED (networks with the adjoint enabled),
+   EINVAL (NULL, a buffer too small, a state saved by a network of another
+   spec, seed or plan). */
 int cortex_state_size(cortex_net* net, int64_t* bytes);
 int cortex_save_state(cortex_net* net, void* host, int64_t bytes);
 int cortex_load_state(cortex_net* net, const void* host, int64_t bytes);

@@ -1188,7 +1188,7 @@ static void require_net(cortex_net* n) {
     require(!n->failed, CORTEX_ESTATE, "network failed earlier; destroy it");
 }
 
-// The dynamic state of an FP32 network, part by part (device buffers), for
+// The dynamic state of a network, part by part (device buffers), for
 // cortex_save_state / cortex_load_state: everything a step reads and writes
 // besides the immutable graph.  The staging cursors are zero between
 // windows and the staged runs are rebuilt by every window, so neither is
@@ -1200,6 +1200,18 @@ struct StatePart {
 
 static std::vector<StatePart> state_parts(cortex_net* n) {
     const size_t N = (size_t)n->N, nt = (size_t)n->n_tiles;
+    if (n->spec.precision == CORTEX_FP64_VERIFY) {
+        // FP64 verify mode: the state, the spike bits of the last H steps
+        // (the pending deliveries) and of the record window, the counters
+        return {{n->d_Ud, N * sizeof(double)},
+                {n->d_y1d, N * sizeof(double)},
+                {n->d_y2d, N * sizeof(double)},
+                {n->d_r, N * sizeof(int32_t)},
+                {n->d_hist, (size_t)n->H * n->W64 * sizeof(uint64_t)},
+                {n->d_raster, (size_t)std::max<int64_t>(1, n->log_steps) * n->W64 * sizeof(uint64_t)},
+                {n->d_events, 2 * sizeof(uint64_t)},
+                {n->d_err, 4 * sizeof(int32_t)}};
+    }
     std::vector<StatePart> v{{n->d_U, N * sizeof(float)},
                              {n->d_y1, N * sizeof(float)},
                              {n->d_y2, N * sizeof(float)},
@@ -1249,7 +1261,6 @@ struct StateHeader {
 constexpr uint64_t kStateMagic = 0x31455441545358ull;   // "XSTATE1"
 
 static void state_supported(cortex_net* n) {
-    require(n->spec.precision != CORTEX_FP64_VERIFY, CORTEX_EUNSUPPORTED, "saved states are FP32 only");
     require(n->ckpt == 0, CORTEX_EUNSUPPORTED, "saved states exclude networks with the adjoint enabled");
 }
 

@@ -103,8 +103,31 @@ def test_state_of_another_network_is_refused(cx):
         g.load_state(buf[:100])
     assert e.value.status == cx.EINVAL
     g.close()
-    f = cx.Network(netspec.brunel_1250_fp64(), 1)
+    f = cx.Network(spec, 1, ckpt_every=50, adjoint_steps=100)
     with pytest.raises(cx.CortexError) as e:
         f.save_state()
     assert e.value.status == cx.EUNSUPPORTED
     f.close()
+
+
+def test_resume_fp64_verify_mode(cx):
+    spec = netspec.brunel_1250_fp64()
+    case("FP64 verify mode, 1,250 neurons, save at step 151")
+    a = cx.Network(spec, 1, record_steps=400)
+    a.step(151)
+    buf = a.save_state()
+    a.step(249)
+    sa, ia = a.spikes(0, 400)
+    stat_a = a.state()
+    a.close()
+    b = cx.Network(spec, 1, record_steps=400)
+    b.load_state(buf)
+    b.step(249)
+    sb, ib = b.spikes(0, 400)
+    stat_b = b.state()
+    b.close()
+    print("spikes", len(sa), flush=True)
+    assert np.count_nonzero(sa >= 151) > 50
+    assert np.array_equal(sa, sb) and np.array_equal(ia, ib)
+    for x, y in zip(stat_a, stat_b):
+        assert np.array_equal(x, y)
