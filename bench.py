@@ -36,9 +36,9 @@ CSRC = os.path.join(ROOT, "paper_2406_03762_amd", "csrc")
 # size, as the summaries under profiles/ state), valid only for the sources
 # they were measured on: {kernel: (bytes per event, source hash)}.
 TRAFFIC = {
-    # 112,500-neuron alpha net, one 1000-step launch: (3.3021e6 KiB x 2.0
-    # + 2.0456e5 KiB x 1.0) x 1024 / 9.708e8 events
-    "step_kernel": (7.182, "2a1f56a6bb60aa11"),
+    # 112,500-neuron alpha net, one 1000-step launch: (3.2547e6 KiB x 2.0
+    # + 3.8464e4 KiB x 1.0) x 1024 / 9.708e8 events
+    "step_kernel": (6.907, "382a76f1b7e1aa7d"),
     # two-million-neuron bf16 net, the 2,000 window launches of each kernel
     # in the timed second of a run after one second of warmup, 1.59677e11
     # events: delivery (5.4019e8 KiB x 2.0 + 4.4249e8 KiB x 1.0) x 1024,

@@ -88,16 +88,16 @@ __device__ __forceinline__ void coherent_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Re-read a published word until it carries `tag` (bounded).
+// Re-read a published word until it carries `tag` (bounded).  A wait that
+// gives up returns 0, whose tag (0) no published word carries; the status
+// travels in the return value, not through a pointer, so the caller's flag
+// stays in a register.
 __device__ __noinline__ uint64_t wait_tag(const uint64_t* p, uint64_t v, uint32_t tag, int64_t spin_max,
-                                          int32_t* err, bool* bail) {
+                                          int32_t* err) {
     int64_t spins = 0;
     int32_t e = 0;
     while ((uint32_t)(v >> 32) != tag) {
-        if (++spins > spin_max || e != 0) {
-            *bail = true;
-            return 0;
-        }
+        if (++spins > spin_max || e != 0) return 0;
         __builtin_amdgcn_s_sleep(1);
         // the error flag is read with the word, so one round trip per try
         e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -337,7 +337,9 @@ __global__ void __launch_bounds__(NPT == 4 ? 512 : 1024) step_kernel(StepArgs a)
                         const int64_t q = q_lo + qi;
                         const uint64_t* w = a.pub + (size_t)(q & (H - 1)) * pub_slot +
                                             (size_t)(tile0b + tt) * pub_tile + 1 + rnk;
-                        j = (uint32_t)wait_tag(w, coherent_load(w), (uint32_t)(q + 1), spin_max, a.err, &bail);
+                        const uint64_t v = wait_tag(w, coherent_load(w), (uint32_t)(q + 1), spin_max, a.err);
+                        if ((uint32_t)(v >> 32) != (uint32_t)(q + 1)) bail = true;
+                        j = (uint32_t)v;
                     }
                     if (bail) {
                         // the id never arrived: the kernel stops after this
